@@ -1,0 +1,825 @@
+/*
+ * oracle.c -- plain FP64 CPU oracle (TEST INFRASTRUCTURE ONLY; see oracle.h).
+ *
+ * It follows Sec. 2 of Ye et al. (arXiv 2006.07964) step by step, in the paper's order,
+ * with plain loops over grid lines (OpenMP only across independent lines).  Nothing here
+ * is blocked, fused or reordered for speed.  Readings of points the paper leaves open are
+ * marked "Reading:".
+ *
+ * Nondimensionalisation (Eq 1): rho_inf = 1, c_inf = 1, T = gamma p / rho (so T_inf = 1,
+ * p_inf = 1/gamma and the sound speed is c = sqrt(T)); the viscous terms carry Ma/Re.
+ * Index spacing is one in xi, eta and zeta.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define HS 3  /* halo of state / metric arrays */
+#define HX 6  /* halo of coordinate arrays     */
+
+/* ------------------------------------------------------------------------------------ */
+/* indexing                                                                              */
+/* ------------------------------------------------------------------------------------ */
+typedef struct { long sx, sy, sz, plane; } dims_t;
+
+static dims_t state_dims(const oracle_cfg* c) {
+  dims_t d;
+  d.sx = c->ni + 2 * HS; d.sy = c->nj + 2 * HS; d.sz = c->nk + 2 * HS;
+  d.plane = d.sx * d.sy * d.sz;
+  return d;
+}
+static dims_t coord_dims(const oracle_cfg* c) {
+  dims_t d;
+  d.sx = c->ni + 2 * HX; d.sy = c->nj + 2 * HX; d.sz = c->nk + 2 * HX;
+  d.plane = d.sx * d.sy * d.sz;
+  return d;
+}
+/* (i,j,k) are interior-based indices (0 = first interior point) */
+static long sidx(const dims_t* d, int i, int j, int k) {
+  return ((long)(k + HS) * d->sy + (j + HS)) * d->sx + (i + HS);
+}
+static long xidx(const dims_t* d, int i, int j, int k) {
+  return ((long)(k + HX) * d->sy + (j + HX)) * d->sx + (i + HX);
+}
+/* step of one index in direction dir (0: i, 1: j, 2: k) */
+static void unit(int dir, int* di, int* dj, int* dk) {
+  *di = dir == 0; *dj = dir == 1; *dk = dir == 2;
+}
+static int npts(const oracle_cfg* c, int dir) {
+  return dir == 0 ? c->ni : dir == 1 ? c->nj : c->nk;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Sixth-order central first derivative (Sec. 2, after Eq 8), unit spacing:            */
+/*   d6 g_i = 3/4 (g_{i+1}-g_{i-1}) - 3/20 (g_{i+2}-g_{i-2}) + 1/60 (g_{i+3}-g_{i-3})    */
+/* g[0..6] holds g_{i-3} .. g_{i+3}.                                                     */
+/* ------------------------------------------------------------------------------------ */
+static double d6(const double* g) {
+  return 3.0 / 4.0 * (g[4] - g[2]) - 3.0 / 20.0 * (g[5] - g[1]) + 1.0 / 60.0 * (g[6] - g[0]);
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Eq 7 / Eq 8: conservative metrics and Jacobian                                       */
+/* ------------------------------------------------------------------------------------ */
+/* derivative along dir of coordinate array X at (i,j,k) */
+static double dcoord(const dims_t* xd, const double* X, int dir, int i, int j, int k) {
+  int di, dj, dk, s;
+  double g[7];
+  unit(dir, &di, &dj, &dk);
+  for (s = -3; s <= 3; ++s) g[s + 3] = X[xidx(xd, i + s * di, j + s * dj, k + s * dk)];
+  return d6(g);
+}
+/* outer derivative along dout of the product (d/din of coordinate a) * (coordinate b) */
+static double dprod(const dims_t* xd, const double* A, const double* B, int din, int dout,
+                    int i, int j, int k) {
+  int di, dj, dk, s;
+  double g[7];
+  unit(dout, &di, &dj, &dk);
+  for (s = -3; s <= 3; ++s) {
+    int ii = i + s * di, jj = j + s * dj, kk = k + s * dk;
+    g[s + 3] = dcoord(xd, A, din, ii, jj, kk) * B[xidx(xd, ii, jj, kk)];
+  }
+  return d6(g);
+}
+
+int oracle_metrics(const oracle_cfg* c, const double* xyz, double* met) {
+  const dims_t xd = coord_dims(c), sd = state_dims(c);
+  const double* x = xyz;
+  const double* y = xyz + xd.plane;
+  const double* z = xyz + 2 * xd.plane;
+  enum { XI = 0, ETA = 1, ZETA = 2 };
+  int bad = 0;
+  int k;
+#pragma omp parallel for reduction(| : bad) schedule(static)
+  for (k = -HS; k < c->nk + HS; ++k) {
+    int i, j;
+    for (j = -HS; j < c->nj + HS; ++j)
+      for (i = -HS; i < c->ni + HS; ++i) {
+        long p = sidx(&sd, i, j, k);
+        /* Eq 7, term by term as printed */
+        met[0 * sd.plane + p] = dprod(&xd, y, z, ETA, ZETA, i, j, k) - dprod(&xd, y, z, ZETA, ETA, i, j, k);
+        met[1 * sd.plane + p] = dprod(&xd, z, x, ETA, ZETA, i, j, k) - dprod(&xd, z, x, ZETA, ETA, i, j, k);
+        met[2 * sd.plane + p] = dprod(&xd, x, y, ETA, ZETA, i, j, k) - dprod(&xd, x, y, ZETA, ETA, i, j, k);
+        met[3 * sd.plane + p] = dprod(&xd, y, z, ZETA, XI, i, j, k) - dprod(&xd, y, z, XI, ZETA, i, j, k);
+        met[4 * sd.plane + p] = dprod(&xd, z, x, ZETA, XI, i, j, k) - dprod(&xd, z, x, XI, ZETA, i, j, k);
+        met[5 * sd.plane + p] = dprod(&xd, x, y, ZETA, XI, i, j, k) - dprod(&xd, x, y, XI, ZETA, i, j, k);
+        met[6 * sd.plane + p] = dprod(&xd, y, z, XI, ETA, i, j, k) - dprod(&xd, y, z, ETA, XI, i, j, k);
+        met[7 * sd.plane + p] = dprod(&xd, z, x, XI, ETA, i, j, k) - dprod(&xd, z, x, ETA, XI, i, j, k);
+        met[8 * sd.plane + p] = dprod(&xd, x, y, XI, ETA, i, j, k) - dprod(&xd, x, y, ETA, XI, i, j, k);
+        {
+          /* Eq 8 */
+          double xx = dcoord(&xd, x, XI, i, j, k), xe = dcoord(&xd, x, ETA, i, j, k), xz = dcoord(&xd, x, ZETA, i, j, k);
+          double yx = dcoord(&xd, y, XI, i, j, k), ye = dcoord(&xd, y, ETA, i, j, k), yz = dcoord(&xd, y, ZETA, i, j, k);
+          double zx = dcoord(&xd, z, XI, i, j, k), ze = dcoord(&xd, z, ETA, i, j, k), zz = dcoord(&xd, z, ZETA, i, j, k);
+          double jinv = xx * ye * zz - xx * yz * ze + xe * yz * zx - xe * yx * zz + xz * yx * ze - xz * ye * zx;
+          if (!(jinv > 0.0)) bad = 1;
+          met[9 * sd.plane + p] = 1.0 / jinv;
+        }
+      }
+  }
+  return bad ? -5 : 0;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Gas model (Eq 1): primitives from Q = (rho, rho u, rho v, rho w, e)                   */
+/* ------------------------------------------------------------------------------------ */
+typedef struct { double rho, u, v, w, p, T, c, H; } prim_t;
+
+static prim_t primitives(const double* q, double gamma) {
+  prim_t s;
+  s.rho = q[0];
+  s.u = q[1] / q[0];
+  s.v = q[2] / q[0];
+  s.w = q[3] / q[0];
+  s.p = (gamma - 1.0) * (q[4] - 0.5 * s.rho * (s.u * s.u + s.v * s.v + s.w * s.w));
+  s.T = gamma * s.p / s.rho;
+  s.c = sqrt(s.T);                 /* c^2 = gamma p / rho = T */
+  s.H = (q[4] + s.p) / s.rho;      /* total enthalpy          */
+  return s;
+}
+
+/* Reading: Sutherland's law for the nondimensional viscosity with T_inf = 1,
+ * mu = T^{3/2} (1 + S) / (T + S); the paper stores mu without naming its law.            */
+double oracle_viscosity(double T, double suth) {
+  return T * sqrt(T) * (1.0 + suth) / (T + suth);
+}
+
+/* Eq 4: inviscid flux through the hatted metric vector m = (m_x, m_y, m_z)/J.           */
+void oracle_phys_flux(const double* q, const double* m, double gamma, double* F) {
+  prim_t s = primitives(q, gamma);
+  double U = m[0] * s.u + m[1] * s.v + m[2] * s.w;  /* contravariant velocity / J */
+  F[0] = s.rho * U;
+  F[1] = s.rho * s.u * U + m[0] * s.p;
+  F[2] = s.rho * s.v * U + m[1] * s.p;
+  F[3] = s.rho * s.w * U + m[2] * s.p;
+  F[4] = (q[4] + s.p) * U;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Eigenvectors of the flux Jacobian in the unit direction k (characteristic space).    */
+/* Reading: the right eigenvectors of Pulliam & Chaussee (J. Comput. Phys. 39, 1981):   */
+/* columns 1-3 (eigenvalue theta) k_m (1, u, v, w, q) + rho (0, k x e_m, u.(k x e_m)),   */
+/* columns 4-5 (theta +- c) rho/(sqrt2 c) (1, u +- c k, H +- c theta).  L is the plain  */
+/* numerical inverse of R.                                                              */
+/* ------------------------------------------------------------------------------------ */
+static int invert5(const double* A, double* Ainv) {
+  double M[5][10];
+  int r, col, i;
+  for (r = 0; r < 5; ++r)
+    for (col = 0; col < 10; ++col) M[r][col] = col < 5 ? A[r * 5 + col] : (double)(col - 5 == r);
+  for (col = 0; col < 5; ++col) {
+    int piv = col;
+    for (r = col + 1; r < 5; ++r)
+      if (fabs(M[r][col]) > fabs(M[piv][col])) piv = r;
+    if (M[piv][col] == 0.0) return -1;
+    if (piv != col)
+      for (i = 0; i < 10; ++i) { double t = M[col][i]; M[col][i] = M[piv][i]; M[piv][i] = t; }
+    {
+      double s = M[col][col];
+      for (i = 0; i < 10; ++i) M[col][i] /= s;
+    }
+    for (r = 0; r < 5; ++r)
+      if (r != col) {
+        double f = M[r][col];
+        for (i = 0; i < 10; ++i) M[r][i] -= f * M[col][i];
+      }
+  }
+  for (r = 0; r < 5; ++r)
+    for (col = 0; col < 5; ++col) Ainv[r * 5 + col] = M[r][col + 5];
+  return 0;
+}
+
+int oracle_eigvec(const double* q, const double* k, double gamma, double* L, double* R) {
+  prim_t s = primitives(q, gamma);
+  double kx = k[0], ky = k[1], kz = k[2];
+  double qq = 0.5 * (s.u * s.u + s.v * s.v + s.w * s.w);
+  double theta = kx * s.u + ky * s.v + kz * s.w;
+  double a = s.rho / (sqrt(2.0) * s.c);
+  /* R[row*5 + col] */
+  double Rm[25] = {
+      /* row rho   */ kx, ky, kz, a, a,
+      /* row rho u */ kx * s.u, ky * s.u - kz * s.rho, kz * s.u + ky * s.rho, a * (s.u + kx * s.c), a * (s.u - kx * s.c),
+      /* row rho v */ kx * s.v + kz * s.rho, ky * s.v, kz * s.v - kx * s.rho, a * (s.v + ky * s.c), a * (s.v - ky * s.c),
+      /* row rho w */ kx * s.w - ky * s.rho, ky * s.w + kx * s.rho, kz * s.w, a * (s.w + kz * s.c), a * (s.w - kz * s.c),
+      /* row e     */ kx * qq + s.rho * (kz * s.v - ky * s.w), ky * qq + s.rho * (kx * s.w - kz * s.u),
+      kz * qq + s.rho * (ky * s.u - kx * s.v), a * (s.H + theta * s.c), a * (s.H - theta * s.c)};
+  memcpy(R, Rm, sizeof Rm);
+  return invert5(R, L);
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Steger-Warming flux vector splitting (Sec. 2, the monotone flux h of Eq 12).          */
+/* With |m| the metric magnitude, kt = m/|m| and theta = kt.u, the eigenvalues are       */
+/* lambda_{1,2,3} = |m| theta, lambda_{4,5} = |m| (theta +- c); lambda^{+-} =            */
+/* (lambda +- |lambda|)/2 and                                                           */
+/* F^{+-} = rho/(2 gamma) [2(gamma-1) l1 (1,u,v,w,q) + l4 (1, u+c kt, H+c theta)         */
+/*                        + l5 (1, u-c kt, H-c theta)].                                  */
+/* ------------------------------------------------------------------------------------ */
+static void sw_part(const double* q, const double* m, double gamma, int sign, double* F) {
+  prim_t s = primitives(q, gamma);
+  double mag = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+  double kx = m[0] / mag, ky = m[1] / mag, kz = m[2] / mag;
+  double theta = kx * s.u + ky * s.v + kz * s.w;
+  double lam[3] = {mag * theta, mag * (theta + s.c), mag * (theta - s.c)};
+  double l[3];
+  int n;
+  double qq = 0.5 * (s.u * s.u + s.v * s.v + s.w * s.w);
+  double f = s.rho / (2.0 * gamma);
+  for (n = 0; n < 3; ++n) l[n] = 0.5 * (lam[n] + sign * fabs(lam[n]));
+  F[0] = f * (2.0 * (gamma - 1.0) * l[0] + l[1] + l[2]);
+  F[1] = f * (2.0 * (gamma - 1.0) * l[0] * s.u + l[1] * (s.u + s.c * kx) + l[2] * (s.u - s.c * kx));
+  F[2] = f * (2.0 * (gamma - 1.0) * l[0] * s.v + l[1] * (s.v + s.c * ky) + l[2] * (s.v - s.c * ky));
+  F[3] = f * (2.0 * (gamma - 1.0) * l[0] * s.w + l[1] * (s.w + s.c * kz) + l[2] * (s.w - s.c * kz));
+  F[4] = f * (2.0 * (gamma - 1.0) * l[0] * qq + l[1] * (s.H + s.c * theta) + l[2] * (s.H - s.c * theta));
+}
+
+void oracle_split_flux(const double* q, const double* m, double gamma, double* Fp, double* Fm) {
+  sw_part(q, m, gamma, +1, Fp);
+  sw_part(q, m, gamma, -1, Fm);
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* WENO interpolation (Eqs 13-17).                                                       */
+/* Reading: the sub-stencil that carries the ideal weight 1/16 and beta_1 is            */
+/* {i-2,i-1,i} (value 3/8, -5/4, 15/8 at i+1/2); 5/8 goes with {i-1,i,i+1} and 5/16     */
+/* with {i,i+1,i+2}.  Only this pairing makes the linear combination the fifth-order    */
+/* interpolant (3,-20,90,60,-5)/128; Eq 14 lists the three stencils in reverse order.   */
+/* The value at i-1/2 from the same five points is the mirror image (modified AFWENO,   */
+/* Sec. 4.5.1, Figs 10-11): the betas are shared and the ideal weights are reversed.    */
+/* ------------------------------------------------------------------------------------ */
+void oracle_weno5(const double* v, double eps, int linear, double* out, double* beta_out) {
+  const double a = v[0], b = v[1], cc = v[2], d = v[3], e = v[4];
+  double beta[3], sub_p[3], sub_m[3], gam_p[3] = {1.0 / 16.0, 5.0 / 8.0, 5.0 / 16.0};
+  double gam_m[3] = {5.0 / 16.0, 5.0 / 8.0, 1.0 / 16.0};
+  double wp[3], wm[3], sp = 0.0, sm = 0.0;
+  int j;
+  /* Eq 17 */
+  beta[0] = (4.0 * a * a - 19.0 * a * b + 25.0 * b * b + 11.0 * a * cc - 31.0 * b * cc + 10.0 * cc * cc) / 3.0;
+  beta[1] = (4.0 * b * b - 13.0 * b * cc + 13.0 * cc * cc + 5.0 * b * d - 13.0 * cc * d + 4.0 * d * d) / 3.0;
+  beta[2] = (10.0 * cc * cc - 31.0 * cc * d + 25.0 * d * d + 11.0 * cc * e - 19.0 * d * e + 4.0 * e * e) / 3.0;
+  /* Eq 14: quadratic interpolants at i+1/2 ... */
+  sub_p[0] = 3.0 / 8.0 * a - 5.0 / 4.0 * b + 15.0 / 8.0 * cc;
+  sub_p[1] = -1.0 / 8.0 * b + 3.0 / 4.0 * cc + 3.0 / 8.0 * d;
+  sub_p[2] = 3.0 / 8.0 * cc + 3.0 / 4.0 * d - 1.0 / 8.0 * e;
+  /* ... and their mirror images at i-1/2 */
+  sub_m[0] = -1.0 / 8.0 * a + 3.0 / 4.0 * b + 3.0 / 8.0 * cc;
+  sub_m[1] = 3.0 / 8.0 * b + 3.0 / 4.0 * cc - 1.0 / 8.0 * d;
+  sub_m[2] = 15.0 / 8.0 * cc - 5.0 / 4.0 * d + 3.0 / 8.0 * e;
+  /* Eqs 15-16 */
+  for (j = 0; j < 3; ++j) {
+    if (linear) {
+      wp[j] = gam_p[j];
+      wm[j] = gam_m[j];
+    } else {
+      wp[j] = gam_p[j] / ((eps + beta[j]) * (eps + beta[j]));
+      wm[j] = gam_m[j] / ((eps + beta[j]) * (eps + beta[j]));
+    }
+    sp += wp[j];
+    sm += wm[j];
+  }
+  /* Eq 13 */
+  out[0] = (wp[0] * sub_p[0] + wp[1] * sub_p[1] + wp[2] * sub_p[2]) / sp;
+  out[1] = (wm[0] * sub_m[0] + wm[1] * sub_m[1] + wm[2] * sub_m[2]) / sm;
+  if (beta_out) for (j = 0; j < 3; ++j) beta_out[j] = beta[j];
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Viscous fluxes (Eqs 5, 6, 21).  Gradients of (u, v, w, T) by d6 along xi, eta, zeta  */
+/* at interior points, the chain rule with unhatted metrics xi_x = J * (xi_x/J), then   */
+/* tau and beta scaled by Ma/Re, and the nodal viscous flux of each direction through   */
+/* its hatted metrics.  Output V[12]: plane 4*d + (n-1) holds component n = 1..4 of the  */
+/* direction-d viscous flux (component 0, continuity, is zero).                          */
+/* Reading: Stokes' hypothesis lambda = -2/3 mu (Eq 1), Ma/Re multiplies tau and q      */
+/* (Eq 1; Eq 6 prints the flux without it), q = mu/(Pr (gamma-1)) grad T.              */
+/* ------------------------------------------------------------------------------------ */
+static void viscous_fluxes(const oracle_cfg* c, const double* met, const double* Q, double* V) {
+  const dims_t sd = state_dims(c);
+  const double scale = c->mach / c->reynolds;
+  int k;
+#pragma omp parallel for schedule(static)
+  for (k = 0; k < c->nk; ++k) {
+    int i, j;
+    for (j = 0; j < c->nj; ++j)
+      for (i = 0; i < c->ni; ++i) {
+        long p = sidx(&sd, i, j, k);
+        double g[4][3]; /* d(u,v,w,T)/d(xi,eta,zeta) */
+        double dx[4][3]; /* d(u,v,w,T)/d(x,y,z)       */
+        double mh[3][3], mu_, Jp, tau[3][3], bet[3], div, lam;
+        prim_t s0;
+        int dir, n, a, b;
+        for (dir = 0; dir < 3; ++dir) {
+          int di, dj, dk, st;
+          double line[4][7];
+          unit(dir, &di, &dj, &dk);
+          for (st = -3; st <= 3; ++st) {
+            double qv[5];
+            prim_t s;
+            long pp = sidx(&sd, i + st * di, j + st * dj, k + st * dk);
+            for (n = 0; n < 5; ++n) qv[n] = Q[n * sd.plane + pp];
+            s = primitives(qv, c->gamma);
+            line[0][st + 3] = s.u; line[1][st + 3] = s.v; line[2][st + 3] = s.w; line[3][st + 3] = s.T;
+          }
+          for (n = 0; n < 4; ++n) g[n][dir] = d6(line[n]);
+        }
+        Jp = met[9 * sd.plane + p];
+        for (a = 0; a < 3; ++a)
+          for (b = 0; b < 3; ++b) mh[a][b] = met[(3 * a + b) * sd.plane + p];
+        /* Eq 21 */
+        for (n = 0; n < 4; ++n)
+          for (b = 0; b < 3; ++b)
+            dx[n][b] = Jp * (mh[0][b] * g[n][0] + mh[1][b] * g[n][1] + mh[2][b] * g[n][2]);
+        {
+          double qv[5];
+          for (n = 0; n < 5; ++n) qv[n] = Q[n * sd.plane + p];
+          s0 = primitives(qv, c->gamma);
+        }
+        mu_ = oracle_viscosity(s0.T, c->suth);
+        lam = -2.0 / 3.0 * mu_;
+        div = dx[0][0] + dx[1][1] + dx[2][2];
+        /* Eq 6 (x Ma/Re) */
+        for (a = 0; a < 3; ++a)
+          for (b = 0; b < 3; ++b)
+            tau[a][b] = scale * (mu_ * (dx[a][b] + dx[b][a]) + (a == b ? lam * div : 0.0));
+        for (a = 0; a < 3; ++a)
+          bet[a] = s0.u * tau[0][a] + s0.v * tau[1][a] + s0.w * tau[2][a] +
+                   scale * mu_ / (c->prandtl * (c->gamma - 1.0)) * dx[3][a];
+        /* Eq 5 */
+        for (dir = 0; dir < 3; ++dir) {
+          for (n = 0; n < 3; ++n)
+            V[(4 * dir + n) * sd.plane + p] = mh[dir][0] * tau[n][0] + mh[dir][1] * tau[n][1] + mh[dir][2] * tau[n][2];
+          V[(4 * dir + 3) * sd.plane + p] = mh[dir][0] * bet[0] + mh[dir][1] * bet[1] + mh[dir][2] * bet[2];
+        }
+      }
+  }
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Halo handling                                                                         */
+/* ------------------------------------------------------------------------------------ */
+static int wrapi(int i, int n) { return ((i % n) + n) % n; }
+
+void oracle_periodic_wrap(const oracle_cfg* c, double* A, int nvar) {
+  const dims_t sd = state_dims(c);
+  const int per[3] = {c->bc[0] == ORACLE_BC_PERIODIC, c->bc[2] == ORACLE_BC_PERIODIC,
+                      c->bc[4] == ORACLE_BC_PERIODIC};
+  int v;
+  for (v = 0; v < nvar; ++v) {
+    double* P = A + (long)v * sd.plane;
+    int i, j, k;
+    for (k = -HS; k < c->nk + HS; ++k)
+      for (j = -HS; j < c->nj + HS; ++j)
+        for (i = -HS; i < c->ni + HS; ++i) {
+          int si = per[0] ? wrapi(i, c->ni) : i;
+          int sj = per[1] ? wrapi(j, c->nj) : j;
+          int sk = per[2] ? wrapi(k, c->nk) : k;
+          if (si != i || sj != j || sk != k) P[sidx(&sd, i, j, k)] = P[sidx(&sd, si, sj, sk)];
+        }
+  }
+}
+
+/* interior index of the boundary node of face f and the outward step along its axis */
+static void face_geom(const oracle_cfg* c, int f, int* axis, int* wall_idx, int* outward) {
+  *axis = f / 2;
+  *outward = (f % 2) ? +1 : -1;
+  *wall_idx = (f % 2) ? npts(c, *axis) - 1 : 0;
+}
+
+/* Reading (physical boundaries, not specified by the paper): the boundary node itself
+ * is part of the interior.  Isothermal no-slip wall: ghost m mirrors interior node m
+ * with odd velocity, the same pressure and T_g = 2 T_w - T_m; after every stage the wall
+ * node gets zero velocity and T = T_w at its own density.  Far field: ghosts hold qinf.  */
+void oracle_bc_fill(const oracle_cfg* c, double* Q) {
+  const dims_t sd = state_dims(c);
+  int f;
+  for (f = 0; f < 6; ++f) {
+    int axis, w, out, a, b, m, n;
+    int na, nb;
+    if (c->bc[f] != ORACLE_BC_WALL && c->bc[f] != ORACLE_BC_FARFIELD) continue;
+    face_geom(c, f, &axis, &w, &out);
+    na = npts(c, (axis + 1) % 3);
+    nb = npts(c, (axis + 2) % 3);
+    for (b = 0; b < nb; ++b)
+      for (a = 0; a < na; ++a) {
+        int idx[3];
+        long pw;
+        idx[(axis + 1) % 3] = a;
+        idx[(axis + 2) % 3] = b;
+        idx[axis] = w;
+        pw = sidx(&sd, idx[0], idx[1], idx[2]);
+        if (c->bc[f] == ORACLE_BC_WALL) {
+          double rho = Q[pw];
+          Q[1 * sd.plane + pw] = 0.0;
+          Q[2 * sd.plane + pw] = 0.0;
+          Q[3 * sd.plane + pw] = 0.0;
+          Q[4 * sd.plane + pw] = rho * c->t_wall / (c->gamma * (c->gamma - 1.0));
+        }
+        for (m = 1; m <= HS; ++m) {
+          long pg, pm;
+          idx[axis] = w + out * m;
+          pg = sidx(&sd, idx[0], idx[1], idx[2]);
+          idx[axis] = w - out * m;
+          pm = sidx(&sd, idx[0], idx[1], idx[2]);
+          if (c->bc[f] == ORACLE_BC_FARFIELD) {
+            for (n = 0; n < 5; ++n) Q[n * sd.plane + pg] = c->qinf[n];
+          } else {
+            double qm[5];
+            prim_t s;
+            double Tg, rg;
+            for (n = 0; n < 5; ++n) qm[n] = Q[n * sd.plane + pm];
+            s = primitives(qm, c->gamma);
+            Tg = 2.0 * c->t_wall - s.T;
+            rg = c->gamma * s.p / Tg;
+            Q[pg] = rg;
+            Q[1 * sd.plane + pg] = -rg * s.u;
+            Q[2 * sd.plane + pg] = -rg * s.v;
+            Q[3 * sd.plane + pg] = -rg * s.w;
+            Q[4 * sd.plane + pg] = s.p / (c->gamma - 1.0) + 0.5 * rg * (s.u * s.u + s.v * s.v + s.w * s.w);
+          }
+        }
+      }
+  }
+}
+
+/* Reading: at a wall or far-field face the ghost values of the viscous flux are the
+ * odd reflection about the boundary node, F(w+out*m) = 2 F(w) - F(w-out*m), which keeps
+ * linear flux profiles exact.                                                          */
+static void visc_bc_fill(const oracle_cfg* c, double* V) {
+  const dims_t sd = state_dims(c);
+  int f;
+  for (f = 0; f < 6; ++f) {
+    int axis, w, out, a, b, m, n;
+    int na, nb;
+    if (c->bc[f] != ORACLE_BC_WALL && c->bc[f] != ORACLE_BC_FARFIELD) continue;
+    face_geom(c, f, &axis, &w, &out);
+    na = npts(c, (axis + 1) % 3);
+    nb = npts(c, (axis + 2) % 3);
+    for (b = 0; b < nb; ++b)
+      for (a = 0; a < na; ++a) {
+        int idx[3];
+        long pw;
+        idx[(axis + 1) % 3] = a;
+        idx[(axis + 2) % 3] = b;
+        idx[axis] = w;
+        pw = sidx(&sd, idx[0], idx[1], idx[2]);
+        for (m = 1; m <= HS; ++m) {
+          long pg, pm;
+          idx[axis] = w + out * m;
+          pg = sidx(&sd, idx[0], idx[1], idx[2]);
+          idx[axis] = w - out * m;
+          pm = sidx(&sd, idx[0], idx[1], idx[2]);
+          for (n = 0; n < 12; ++n) V[n * sd.plane + pg] = 2.0 * V[n * sd.plane + pw] - V[n * sd.plane + pm];
+        }
+      }
+  }
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Inviscid derivative along one grid line (modified AFWENO, Sec. 4.5.1, Figs 10-11,    */
+/* assembled by Eq 19).  Inputs along the line, index s = node + 3 for node in          */
+/* [-3, n+2]: q[s][5] conserved state, m[s][3] hatted metrics of this direction.        */
+/* Output D[node][5] for node in [0, n).                                                */
+/* ------------------------------------------------------------------------------------ */
+static void afweno_line(const oracle_cfg* c, int n, const double (*q)[5], const double (*m)[3],
+                        double (*D)[5], double (*Fp)[5], double (*Fm)[5], double (*fnode)[5],
+                        double (*fhalf)[5]) {
+  int node, v, t;
+  /* Reading: half-point metrics are the sixth-order central interpolation
+   * (3, -25, 150, 150, -25, 3)/256 of the node metrics; with Eq 19 it reproduces the
+   * sixth-order derivative of the metrics, which keeps a uniform flow exactly uniform.  */
+#define MHALF(node, comp)                                                                     \
+  ((3.0 * m[(node) - 2 + 3][comp] - 25.0 * m[(node) - 1 + 3][comp] + 150.0 * m[(node) + 3][comp] + \
+    150.0 * m[(node) + 1 + 3][comp] - 25.0 * m[(node) + 2 + 3][comp] + 3.0 * m[(node) + 3 + 3][comp]) / 256.0)
+
+  /* split fluxes: F+ at node+1/2 from nodes -1..n-1, F- at node-1/2 from nodes 0..n */
+  for (node = -1; node <= n; ++node) {
+    double L[25], R[25], kt[3], mag, V[5][5], vl[5], vr[5], ul[5], ur[5];
+    int a;
+    mag = sqrt(m[node + 3][0] * m[node + 3][0] + m[node + 3][1] * m[node + 3][1] + m[node + 3][2] * m[node + 3][2]);
+    for (a = 0; a < 3; ++a) kt[a] = m[node + 3][a] / mag;
+    /* left and right eigenvectors at node i */
+    oracle_eigvec(q[node + 3], kt, c->gamma, L, R);
+    /* characteristic variables of the five stencil points, V[t] = L_i Q_{i+t-2} */
+    for (t = 0; t < 5; ++t)
+      for (v = 0; v < 5; ++v) {
+        double acc = 0.0;
+        for (a = 0; a < 5; ++a) acc += L[v * 5 + a] * q[node - 2 + t + 3][a];
+        V[t][v] = acc;
+      }
+    /* WENO interpolation per characteristic field */
+    for (v = 0; v < 5; ++v) {
+      double col[5], out[2];
+      for (t = 0; t < 5; ++t) col[t] = V[t][v];
+      oracle_weno5(col, c->eps, c->linear_weights, out, NULL);
+      vl[v] = out[0];
+      vr[v] = out[1];
+    }
+    /* back to conserved variables with R_i */
+    for (v = 0; v < 5; ++v) {
+      double al = 0.0, ar = 0.0;
+      for (a = 0; a < 5; ++a) { al += R[v * 5 + a] * vl[a]; ar += R[v * 5 + a] * vr[a]; }
+      ul[v] = al;
+      ur[v] = ar;
+    }
+    /* Reading: the left-biased state at i+1/2 feeds F+ and the right-biased state at
+     * i-1/2 feeds F-, so that each split flux is upwinded.                            */
+    if (node <= n - 1) {
+      double mh[3], Fpp[5], Fmm[5];
+      for (a = 0; a < 3; ++a) mh[a] = MHALF(node, a);
+      oracle_split_flux(ul, mh, c->gamma, Fpp, Fmm);
+      for (v = 0; v < 5; ++v) Fp[node + 1][v] = Fpp[v];
+    }
+    if (node >= 0) {
+      double mh[3], Fpp[5], Fmm[5];
+      for (a = 0; a < 3; ++a) mh[a] = MHALF(node - 1, a);
+      oracle_split_flux(ur, mh, c->gamma, Fpp, Fmm);
+      for (v = 0; v < 5; ++v) Fm[node][v] = Fmm[v];
+    }
+  }
+  /* numerical flux at the half points node+1/2, node = -1..n-1:  f = F+(node) + F-(node+1) */
+  for (node = -1; node <= n - 1; ++node)
+    for (v = 0; v < 5; ++v) fhalf[node + 1][v] = Fp[node + 1][v] + Fm[node + 1][v];
+  /* nodal physical flux, Eq 4 */
+  for (node = -3; node <= n + 2; ++node) oracle_phys_flux(q[node + 3], m[node + 3], c->gamma, fnode[node + 3]);
+  /* Eq 19 */
+  for (node = 0; node < n; ++node)
+    for (v = 0; v < 5; ++v) {
+      const double fp = fhalf[node + 1][v], fm = fhalf[node][v];
+      D[node][v] = fp - fm + 17.0 / 256.0 * (fnode[node + 1 + 3][v] - fnode[node - 1 + 3][v]) -
+                   13.0 / 320.0 * (fnode[node + 2 + 3][v] - fnode[node - 2 + 3][v]) +
+                   19.0 / 3840.0 * (fnode[node + 3 + 3][v] - fnode[node - 3 + 3][v]);
+    }
+#undef MHALF
+}
+
+/* Rtilde contributions of all requested terms, then R = J * Rtilde (Eq 2, A: Q is
+ * stored without 1/J and the grid is stationary, so dQ/dt = J * Rtilde).             */
+static void rhs_core(const oracle_cfg* c, const double* met, const double* Q, const double* V,
+                     double* R, unsigned mask, int k0, int k1) {
+  const dims_t sd = state_dims(c);
+  int dir;
+  double* Rt;
+  long p;
+  int i, j, k;
+  Rt = (double*)calloc((size_t)5 * sd.plane, sizeof(double));
+  for (dir = 0; dir < 3; ++dir) {
+    const int n = npts(c, dir);
+    int di, dj, dk, na, nb;
+    int line;
+    if (!(mask & (1u << dir))) continue;
+    unit(dir, &di, &dj, &dk);
+    na = npts(c, (dir + 1) % 3);
+    nb = npts(c, (dir + 2) % 3);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (line = 0; line < na * nb; ++line) {
+      int a = line % na, b = line / na, s, v, node;
+      int base[3];
+      double(*q)[5] = malloc(sizeof(double[5]) * (n + 6));
+      double(*m)[3] = malloc(sizeof(double[3]) * (n + 6));
+      double(*D)[5] = malloc(sizeof(double[5]) * n);
+      double(*Fp)[5] = malloc(sizeof(double[5]) * (n + 1));
+      double(*Fm)[5] = malloc(sizeof(double[5]) * (n + 1));
+      double(*fn)[5] = malloc(sizeof(double[5]) * (n + 6));
+      double(*fh)[5] = malloc(sizeof(double[5]) * (n + 1));
+      base[(dir + 1) % 3] = a;
+      base[(dir + 2) % 3] = b;
+      base[dir] = 0;
+      /* the k-range restriction (used to time a slab of the domain) */
+      if (dir != 2 && (base[2] < k0 || base[2] >= k1)) goto done;
+      for (s = -3; s < n + 3; ++s) {
+        long pp = sidx(&sd, base[0] + s * di, base[1] + s * dj, base[2] + s * dk);
+        for (v = 0; v < 5; ++v) q[s + 3][v] = Q[v * sd.plane + pp];
+        for (v = 0; v < 3; ++v) m[s + 3][v] = met[(3 * dir + v) * sd.plane + pp];
+      }
+      if (mask & ORACLE_INV) {
+        afweno_line(c, n, (const double(*)[5])q, (const double(*)[3])m, D, Fp, Fm, fn, fh);
+      } else {
+        for (node = 0; node < n; ++node)
+          for (v = 0; v < 5; ++v) D[node][v] = 0.0;
+      }
+      for (node = 0; node < n; ++node) {
+        long pp = sidx(&sd, base[0] + node * di, base[1] + node * dj, base[2] + node * dk);
+        int kk = base[2] + node * dk;
+        if (kk < k0 || kk >= k1) continue;
+        /* inviscid part enters with a minus sign (Eq 2) */
+        for (v = 0; v < 5; ++v) Rt[v * sd.plane + pp] -= D[node][v];
+        /* viscous part: d6 along the line of the direction-dir viscous flux */
+        if ((mask & ORACLE_VIS) && c->viscous) {
+          for (v = 1; v < 5; ++v) {
+            double g[7];
+            int st;
+            for (st = -3; st <= 3; ++st)
+              g[st + 3] = V[(4 * dir + v - 1) * sd.plane +
+                            sidx(&sd, base[0] + (node + st) * di, base[1] + (node + st) * dj, base[2] + (node + st) * dk)];
+            Rt[v * sd.plane + pp] += d6(g);
+          }
+        }
+      }
+    done:
+      free(q); free(m); free(D); free(Fp); free(Fm); free(fn); free(fh);
+    }
+  }
+  for (k = k0; k < k1; ++k)
+    for (j = 0; j < c->nj; ++j)
+      for (i = 0; i < c->ni; ++i) {
+        int v;
+        p = sidx(&sd, i, j, k);
+        for (v = 0; v < 5; ++v) R[v * sd.plane + p] = met[9 * sd.plane + p] * Rt[v * sd.plane + p];
+      }
+  free(Rt);
+}
+
+static int check_cfg(const oracle_cfg* c) {
+  if (c->ni < 7 || c->nj < 7 || c->nk < 7) return -1;
+  return 0;
+}
+
+/* Viscous flux planes with halos filled for a single block (periodic wrap + physical
+ * faces).  Interface faces are left for the multi-block driver.                        */
+static double* visc_planes(const oracle_cfg* c, const double* met, const double* Q) {
+  const dims_t sd = state_dims(c);
+  double* V = (double*)calloc((size_t)12 * sd.plane, sizeof(double));
+  viscous_fluxes(c, met, Q, V);
+  oracle_periodic_wrap(c, V, 12);
+  visc_bc_fill(c, V);
+  return V;
+}
+
+int oracle_rhs(const oracle_cfg* c, const double* met, const double* Q, double* R, unsigned mask,
+               int k0, int k1) {
+  double* V = NULL;
+  if (check_cfg(c)) return -1;
+  if (k0 < 0) k0 = 0;
+  if (k1 > c->nk) k1 = c->nk;
+  if ((mask & ORACLE_VIS) && c->viscous) V = visc_planes(c, met, Q);
+  rhs_core(c, met, Q, V, R, mask, k0, k1);
+  free(V);
+  return 0;
+}
+
+/* Eq 20 coefficients (a, b, c) of Qout = a Qn + b Qcur + c dt R(Qcur) */
+static const double RK3[3][3] = {{1.0, 0.0, 1.0}, {3.0 / 4.0, 1.0 / 4.0, 1.0 / 4.0}, {1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0}};
+
+static void rk_combine(const oracle_cfg* c, int stage, double dt, const double* Qn, const double* Qcur,
+                       const double* R, double* Qout) {
+  const dims_t sd = state_dims(c);
+  int i, j, k, v;
+  for (v = 0; v < 5; ++v)
+    for (k = 0; k < c->nk; ++k)
+      for (j = 0; j < c->nj; ++j)
+        for (i = 0; i < c->ni; ++i) {
+          long p = v * sd.plane + sidx(&sd, i, j, k);
+          Qout[p] = RK3[stage][0] * Qn[p] + RK3[stage][1] * Qcur[p] + RK3[stage][2] * dt * R[p];
+        }
+}
+
+int oracle_rk_stage(const oracle_cfg* c, const double* met, int stage, double dt, const double* Qn,
+                    const double* Qcur, double* Qout) {
+  const dims_t sd = state_dims(c);
+  double* R;
+  int rc;
+  if (stage < 0 || stage > 2) return -1;
+  R = (double*)calloc((size_t)5 * sd.plane, sizeof(double));
+  rc = oracle_rhs(c, met, Qcur, R, ORACLE_ALL, 0, c->nk);
+  if (rc == 0) {
+    rk_combine(c, stage, dt, Qn, Qcur, R, Qout);
+    oracle_periodic_wrap(c, Qout, 5);
+    oracle_bc_fill(c, Qout);
+  }
+  free(R);
+  return rc;
+}
+
+int oracle_rk_step(const oracle_cfg* c, const double* met, double dt, double* Q) {
+  const dims_t sd = state_dims(c);
+  size_t bytes = (size_t)5 * sd.plane * sizeof(double);
+  double* A = (double*)malloc(bytes);
+  double* B = (double*)malloc(bytes);
+  int rc;
+  memcpy(A, Q, bytes);
+  memcpy(B, Q, bytes);
+  rc = oracle_rk_stage(c, met, 0, dt, Q, Q, A);
+  if (!rc) rc = oracle_rk_stage(c, met, 1, dt, Q, A, B);
+  if (!rc) rc = oracle_rk_stage(c, met, 2, dt, Q, B, A);
+  if (!rc) memcpy(Q, A, bytes);
+  free(A);
+  free(B);
+  return rc;
+}
+
+/* Reading: dt = CFL / max over interior points of sum_d (|U_d| + c |grad d|) with the
+ * unhatted metrics grad d = J * (hatted metrics of d); the inviscid limit only.         */
+double oracle_dt_cfl(const oracle_cfg* c, const double* met, const double* Q, double cfl) {
+  const dims_t sd = state_dims(c);
+  double smax = 0.0;
+  int k;
+#pragma omp parallel for reduction(max : smax) schedule(static)
+  for (k = 0; k < c->nk; ++k) {
+    int i, j, d, n;
+    for (j = 0; j < c->nj; ++j)
+      for (i = 0; i < c->ni; ++i) {
+        long p = sidx(&sd, i, j, k);
+        double q[5], sum = 0.0, Jp = met[9 * sd.plane + p];
+        prim_t s;
+        for (n = 0; n < 5; ++n) q[n] = Q[n * sd.plane + p];
+        s = primitives(q, c->gamma);
+        for (d = 0; d < 3; ++d) {
+          double mx = Jp * met[(3 * d + 0) * sd.plane + p];
+          double my = Jp * met[(3 * d + 1) * sd.plane + p];
+          double mz = Jp * met[(3 * d + 2) * sd.plane + p];
+          sum += fabs(mx * s.u + my * s.v + mz * s.w) + s.c * sqrt(mx * mx + my * my + mz * mz);
+        }
+        if (sum > smax) smax = sum;
+      }
+  }
+  return cfl / smax;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Multi-block: 1-to-1 aligned faces.  Face f of block a abuts face g of block b; the    */
+/* halo of a across f holds b's interior layers adjacent to g, with the tangential      */
+/* indices identical (identity orientation).                                            */
+/* ------------------------------------------------------------------------------------ */
+static void copy_face(const oracle_cfg* ca, double* A, int fa, const oracle_cfg* cb, const double* B,
+                      int fb, int nvar) {
+  const dims_t da = state_dims(ca), db = state_dims(cb);
+  int axis = fa / 2, outa = (fa % 2) ? +1 : -1, outb = (fb % 2) ? +1 : -1;
+  int wa = (fa % 2) ? npts(ca, axis) - 1 : 0;
+  int wb = (fb % 2) ? npts(cb, axis) - 1 : 0;
+  int na = npts(ca, (axis + 1) % 3), nb = npts(ca, (axis + 2) % 3);
+  int a, b, m, v;
+  for (b = 0; b < nb; ++b)
+    for (a = 0; a < na; ++a)
+      for (m = 1; m <= HS; ++m) {
+        int ia[3], ib[3];
+        ia[(axis + 1) % 3] = a; ia[(axis + 2) % 3] = b; ia[axis] = wa + outa * m;
+        /* ghost m beyond face fa is interior layer m-1 inside face fb */
+        ib[(axis + 1) % 3] = a; ib[(axis + 2) % 3] = b; ib[axis] = wb - outb * (m - 1);
+        for (v = 0; v < nvar; ++v)
+          A[v * da.plane + sidx(&da, ia[0], ia[1], ia[2])] = B[v * db.plane + sidx(&db, ib[0], ib[1], ib[2])];
+      }
+}
+
+int oracle_exchange(const oracle_cfg* cfgs, int nb, double* const* arrays, int nvar,
+                    const oracle_iface* ifc, int nifc) {
+  int n;
+  for (n = 0; n < nifc; ++n) {
+    const oracle_iface* f = &ifc[n];
+    if (f->block_a < 0 || f->block_a >= nb || f->block_b < 0 || f->block_b >= nb) return -1;
+    if (f->face_a / 2 != f->face_b / 2) return -1;
+    copy_face(&cfgs[f->block_a], arrays[f->block_a], f->face_a, &cfgs[f->block_b], arrays[f->block_b], f->face_b, nvar);
+    copy_face(&cfgs[f->block_b], arrays[f->block_b], f->face_b, &cfgs[f->block_a], arrays[f->block_a], f->face_a, nvar);
+  }
+  return 0;
+}
+
+int oracle_rhs_multi(const oracle_cfg* cfgs, int nb, const double* const* met, const double* const* Q,
+                     double* const* R, unsigned mask, const oracle_iface* ifc, int nifc) {
+  double** V = (double**)calloc((size_t)nb, sizeof(double*));
+  int b, rc = 0;
+  for (b = 0; b < nb; ++b)
+    if (check_cfg(&cfgs[b])) rc = -1;
+  if (!rc && (mask & ORACLE_VIS)) {
+    for (b = 0; b < nb; ++b)
+      if (cfgs[b].viscous) V[b] = visc_planes(&cfgs[b], met[b], Q[b]);
+      else V[b] = (double*)calloc((size_t)12 * state_dims(&cfgs[b]).plane, sizeof(double));
+    /* viscous flux layers across interfaces (interior scheme at block interfaces) */
+    rc = oracle_exchange(cfgs, nb, V, 12, ifc, nifc);
+  }
+  if (!rc)
+    for (b = 0; b < nb; ++b) rhs_core(&cfgs[b], met[b], Q[b], V[b], R[b], mask, 0, cfgs[b].nk);
+  for (b = 0; b < nb; ++b) free(V[b]);
+  free(V);
+  return rc;
+}
+
+int oracle_rk_step_multi(const oracle_cfg* cfgs, int nb, const double* const* met, double dt,
+                         double* const* Q, const oracle_iface* ifc, int nifc) {
+  double **Qn = malloc(sizeof(double*) * nb), **A = malloc(sizeof(double*) * nb),
+         **Bq = malloc(sizeof(double*) * nb), **R = malloc(sizeof(double*) * nb);
+  int b, stage, rc = 0;
+  for (b = 0; b < nb; ++b) {
+    size_t bytes = (size_t)5 * state_dims(&cfgs[b]).plane * sizeof(double);
+    Qn[b] = Q[b];
+    A[b] = malloc(bytes);
+    Bq[b] = malloc(bytes);
+    R[b] = calloc(1, bytes);
+    memcpy(A[b], Q[b], bytes);
+    memcpy(Bq[b], Q[b], bytes);
+  }
+  for (stage = 0; stage < 3 && !rc; ++stage) {
+    double** cur = stage == 0 ? Qn : stage == 1 ? A : Bq;
+    double** out = stage == 0 ? A : stage == 1 ? Bq : A;
+    rc = oracle_rhs_multi(cfgs, nb, (const double* const*)met, (const double* const*)cur, R, ORACLE_ALL, ifc, nifc);
+    if (rc) break;
+    for (b = 0; b < nb; ++b) rk_combine(&cfgs[b], stage, dt, Qn[b], cur[b], R[b], out[b]);
+    for (b = 0; b < nb; ++b) oracle_periodic_wrap(&cfgs[b], out[b], 5);
+    rc = oracle_exchange(cfgs, nb, out, 5, ifc, nifc);
+    for (b = 0; b < nb; ++b) oracle_bc_fill(&cfgs[b], out[b]);
+  }
+  for (b = 0; b < nb && !rc; ++b) memcpy(Q[b], A[b], (size_t)5 * state_dims(&cfgs[b]).plane * sizeof(double));
+  for (b = 0; b < nb; ++b) { free(A[b]); free(Bq[b]); free(R[b]); }
+  free(Qn); free(A); free(Bq); free(R);
+  return rc;
+}

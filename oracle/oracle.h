@@ -1,0 +1,115 @@
+/*
+ * oracle.h -- plain FP64 CPU oracle of the curvilinear high-order finite-difference
+ * Navier-Stokes right-hand side and TVD-RK3 stage of Ye et al., "Accelerating CFD
+ * simulation with high order finite difference method on curvilinear coordinates for
+ * modern GPU clusters" (arXiv 2006.07964).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load this library.  It shares no source with the GPU
+ * library; the two meet only through the seeded input arrays.
+ *
+ * Array layout (all host memory, C order, FP64):
+ *   state / metric arrays  A[var][k+3][j+3][i+3], dims (nk+6, nj+6, ni+6), halo 3
+ *   coordinates            X[c][k+6][j+6][i+6],  dims (nk+12, nj+12, ni+12), halo 6
+ *   metrics                met[10][...]: 3*d+c holds the hatted metric (d in xi,eta,zeta;
+ *                          c in x,y,z), i.e. xi_x/J etc. (Sec. 2, Eq 7); met[9] holds J.
+ * Return values: 0 on success, negative on error (see each function).
+ */
+#ifndef CFD_ORACLE_H
+#define CFD_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* face boundary kinds, one per face in the order (i-,i+,j-,j+,k-,k+) */
+enum { ORACLE_BC_PERIODIC = 0, ORACLE_BC_INTERFACE = 1, ORACLE_BC_WALL = 2, ORACLE_BC_FARFIELD = 3 };
+
+typedef struct oracle_cfg {
+  int ni, nj, nk;          /* interior points per direction (>= 7)               */
+  double gamma;            /* ratio of specific heats (Sec. 2)                    */
+  double mach, reynolds;   /* Ma_inf, Re_inf: viscous factor Ma/Re (Eq 1)         */
+  double prandtl;          /* Pr for the heat flux (Eq 6)                         */
+  double suth;             /* Sutherland constant S/T_ref (viscosity law)         */
+  double eps;              /* WENO epsilon (Eq 15)                                */
+  int viscous;             /* 1: add the viscous terms, 0: Euler                  */
+  int linear_weights;      /* 1: ideal weights gamma_j instead of Eq 15           */
+  int bc[6];               /* face kinds (ORACLE_BC_*)                            */
+  double t_wall;           /* isothermal wall temperature                         */
+  double qinf[5];          /* far-field conserved state                           */
+} oracle_cfg;
+
+/* direction / term mask for oracle_rhs */
+#define ORACLE_XI   1u
+#define ORACLE_ETA  2u
+#define ORACLE_ZETA 4u
+#define ORACLE_INV  8u   /* inviscid terms   */
+#define ORACLE_VIS 16u   /* viscous terms    */
+#define ORACLE_ALL 31u
+
+/* Eq 7 and Eq 8: conservative metrics and Jacobian over the halo-3 box from
+ * coordinates with halo 6.  Returns -5 if some J^-1 <= 0.                             */
+int oracle_metrics(const oracle_cfg* c, const double* xyz, double* met);
+
+/* R_Q = J * Rtilde on interior points with k in [k0,k1) (pass 0,nk for all); other
+ * points of R are left untouched.  Q halos must be valid.  Viscous-flux halos are
+ * produced internally with the same face treatment as Q (periodic wrap, or a one-sided
+ * copy of the mirrored ghost state at walls/far field, see oracle.c).                    */
+int oracle_rhs(const oracle_cfg* c, const double* met, const double* Q, double* R,
+               unsigned mask, int k0, int k1);
+
+/* Eq 20 stage s in {0,1,2}: Qout = a*Qn + b*Qcur + cdt*R(Qcur) on the interior, then the
+ * halos of Qout are refilled (periodic wrap and physical ghost fill).                    */
+int oracle_rk_stage(const oracle_cfg* c, const double* met, int stage, double dt,
+                    const double* Qn, const double* Qcur, double* Qout);
+
+/* One full RK3 step in place on Q (three stages), using two scratch state arrays.       */
+int oracle_rk_step(const oracle_cfg* c, const double* met, double dt, double* Q);
+
+/* Fill the halo of nvar planes of a single periodic block by periodic wrap.             */
+void oracle_periodic_wrap(const oracle_cfg* c, double* A, int nvar);
+
+/* Physical ghost fill for wall / far-field faces of one block (after a stage).          */
+void oracle_bc_fill(const oracle_cfg* c, double* Q);
+
+/* CFL time step: cfl / max over interior of sum_d (|U_d| + c |grad d|).                 */
+double oracle_dt_cfl(const oracle_cfg* c, const double* met, const double* Q, double cfl);
+
+/* ---- point-level pieces, exposed so that tests can pin them individually ---------- */
+/* Eqs 13-17 (with the sub-stencil pairing of the 5th-order interpolant): from the five
+ * values v[0..4] at nodes i-2..i+2 return out[0] = left-biased value at i+1/2 and
+ * out[1] = right-biased value at i-1/2; beta[0..2] receives the smoothness indicators. */
+void oracle_weno5(const double* v, double eps, int linear, double* out, double* beta);
+/* Right eigenvectors R (columns, row-major 5x5) and L = R^-1 of the flux Jacobian in
+ * the unit direction k at the conserved state q.                                        */
+int oracle_eigvec(const double* q, const double* k, double gamma, double* L, double* R);
+/* Steger-Warming split fluxes F+ and F- of state q for the hatted metric vector m.     */
+void oracle_split_flux(const double* q, const double* m, double gamma, double* Fp, double* Fm);
+/* Physical (inviscid) flux of Eq 4 for the hatted metric vector m.                     */
+void oracle_phys_flux(const double* q, const double* m, double gamma, double* F);
+/* Sutherland viscosity law used for mu(T).                                             */
+double oracle_viscosity(double T, double suth);
+
+/* ---- multi-block (blocks on one host, 1-to-1 aligned face interfaces) ------------- */
+typedef struct oracle_iface {
+  int block_a, face_a, block_b, face_b;  /* face = 0..5 in (i-,i+,j-,j+,k-,k+) */
+} oracle_iface;
+
+/* Copy the 3-wide halos of nvar planes across every interface (both directions).      */
+int oracle_exchange(const oracle_cfg* cfgs, int nb, double* const* arrays, int nvar,
+                    const oracle_iface* ifc, int nifc);
+
+/* R_Q for all blocks with interface exchange of the viscous flux planes.               */
+int oracle_rhs_multi(const oracle_cfg* cfgs, int nb, const double* const* met,
+                     const double* const* Q, double* const* R, unsigned mask,
+                     const oracle_iface* ifc, int nifc);
+
+/* One RK3 step of all blocks in place (exchanges and ghost fills after every stage).   */
+int oracle_rk_step_multi(const oracle_cfg* cfgs, int nb, const double* const* met,
+                         double dt, double* const* Q, const oracle_iface* ifc, int nifc);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
