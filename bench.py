@@ -1,0 +1,230 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the curvilinear AFWENO Navier-Stokes RK3 step on one MI355X.
+
+A step is one full TVD-RK3 step (three fused RHS + stage evaluations and the halo
+exchanges after each stage) over the whole grid.  The metric is grid-point RK3 stage
+updates per second: interior points x 3 stages x steps / wall time of the timed steps.
+
+Default workload: 256^3 periodic Taylor-Green vortex, Mach 0.1, Re 1600, on the 2 pi cube
+with a sinusoidal grid perturbation of amplitude 0.05 and seeded velocity noise, FP64.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload tgv256|vortex32]
+                       [--precision fp64|mixed] [--no-cpu]
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# algorithmic HBM bytes per interior point of each kernel (compulsory reads and writes)
+# FP64 path: Q 40 B, a metric component or J 8 B, a viscous-flux component 8 B
+ALG_BYTES_FP64 = {
+    "visc_prepass": 40 + 80 + 96,                 # Q, 9 metrics + J, 12 flux planes
+    "sweep_xi": 40 + 24 + 32 + 40,                # Q, 3 metrics, 4 flux planes, partial sum out
+    "sweep_eta": 40 + 24 + 32 + 40 + 40,          # + partial sum in
+    "sweep_zeta": 40 + 24 + 32 + 40 + 40,
+    "sweep_zeta_rk": 40 + 24 + 32 + 40 + 8 + 40 + 40,  # Q, metrics, fluxes, partial in, J, Qn, Qout
+}
+ALG_BYTES_MIXED = {
+    "visc_prepass": 40 + 80 + 48,
+    "sweep_xi": 40 + 24 + 16 + 20,
+    "sweep_eta": 40 + 24 + 16 + 20 + 20,
+    "sweep_zeta": 40 + 24 + 16 + 20 + 20,
+    "sweep_zeta_rk": 40 + 24 + 16 + 20 + 8 + 40 + 40,
+}
+HBM_PEAK_GBS = 8000.0
+
+
+def source_sha() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2006_07964_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str, precision: str):
+    """Measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a copy
+    kernel's reading) if they were taken on the current kernel sources, else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+    except ValueError:
+        return None
+    ent = data.get(f"{workload}/{precision}/{kernel}")
+    if not ent or ent.get("source_sha") != source_sha():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def build_workload(name: str):
+    from paper_2006_07964_amd import workloads as W
+    if name == "tgv256":
+        return W.taylor_green_wavy(256), "taylor_green_256^3_wavy_2pi_mach0.1_re1600"
+    if name == "vortex32":
+        return W.vortex_wavy(32), "isentropic_vortex_32^3_wavy_unit_mach0.5_re1000"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(wl, workload_name):
+    """The oracle, as it stands, timed on the host: one RK stage of the same workload."""
+    import numpy as np
+    import oracle as O
+    b = wl.blocks[0]
+    c = O.cfg_from_workload(wl)
+    met = O.metrics(c, b.xyz)
+    dt = O.dt_cfl(c, met, b.q, wl.cfl)
+    t0 = time.perf_counter()
+    O.rk_stage(c, met, 0, dt, b.q, b.q)
+    el = time.perf_counter() - t0
+    return {"value": b.points / el, "unit": "grid-point RK3 stage updates/s", "cores": O.threads(),
+            "kind": "oracle",
+            "sample": f"one RK stage (RHS + update + halo wrap) of the full {workload_name} grid, "
+                      f"{el:.2f} s on {O.threads()} OpenMP threads"}
+
+
+def copy_bandwidth(torch):
+    """Achievable HBM bandwidth of a plain device copy (GB/s, read + write bytes)."""
+    n = 1 << 27  # 1 GiB of float64
+    a = torch.empty(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    reps = 10
+    for _ in range(reps):
+        b.copy_(a)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    del a, b
+    return 2 * n * 8 / (ms * 1e-3) / 1e9
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="tgv256")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-block path runs all blocks on one device)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2006_07964_amd import binding as B
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+    B.lib()
+    wl, wname = build_workload(args.workload)
+    blk = wl.blocks[0]
+    prec = B.CFD_FP64 if args.precision == "fp64" else B.CFD_MIXED
+    stream = torch.cuda.current_stream()
+    h = B.cfd_block_create(B.desc_from_workload(wl, 0, prec), stream)
+    xyz = torch.from_numpy(blk.xyz).cuda()
+    B.cfd_metrics(h, xyz, blk.ni + 12, blk.nj + 12)
+    del xyz
+    x = B.cfd_exchange_create([h], [])
+    q = torch.from_numpy(blk.q).cuda()
+    qa, qb = q.clone(), q.clone()
+    dt = B.cfd_dt_cfl([h], [q], wl.cfl)
+
+    def step():
+        B.cfd_rk_stage(h, 0, dt, q, q, qa)
+        B.cfd_halo_exchange(x, B.CFD_FIELDS_Q, [qa])
+        B.cfd_rk_stage(h, 1, dt, q, qa, qb)
+        B.cfd_halo_exchange(x, B.CFD_FIELDS_Q, [qb])
+        B.cfd_rk_stage(h, 2, dt, q, qb, q)
+        B.cfd_halo_exchange(x, B.CFD_FIELDS_Q, [q])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    B.cfd_profile_reset(h)
+    B.cfd_profile_enable(h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for n in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    B.cfd_profile_enable(h, False)
+    prof = B.cfd_profile_read(h)
+    if not B.cfd_check_finite(h, q):
+        raise SystemExit("non-finite state after the timed steps")
+    updates = blk.points * 3 * args.steps
+    value = updates / el
+
+    alg = ALG_BYTES_FP64 if prec == B.CFD_FP64 else ALG_BYTES_MIXED
+    kernels = {}
+    for name, (launches, ms) in prof.items():
+        avg_ms = ms / max(launches, 1)
+        ent = {"launches": launches, "avg_ms": round(avg_ms, 4), "share": 0.0}
+        if name in alg:
+            ent["alg_bytes_per_launch"] = alg[name] * blk.points
+            ent["alg_GBps"] = round(alg[name] * blk.points / (avg_ms * 1e-3) / 1e9, 1)
+        kernels[name] = ent
+    total_ms = sum(v[1] for v in prof.values())
+    for name, ent in kernels.items():
+        ent["share"] = round(prof[name][1] / total_ms, 3)
+    dom = max((n for n in kernels if n in alg), key=lambda n: prof[n][1])
+    dk = kernels[dom]
+    achieved = dk["alg_GBps"]
+    traffic = load_traffic(dom, args.workload, args.precision)
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                "alg_bytes_per_point": alg[dom], "avg_launch_ms": dk["avg_ms"]}
+    copy_gbs = copy_bandwidth(torch)
+
+    out = {
+        "metric": "grid-point RK3 stage updates/s",
+        "value": value,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == B.CFD_FP64 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": wname, "grid": [blk.ni, blk.nj, blk.nk], "points": blk.points,
+                   "precision": args.precision, "cfl": wl.cfl, "dt": dt, "parallelism": "single GPU, single block"},
+        "roofline": roofline,
+        "kernels": kernels,
+        "copy_GBps": round(copy_gbs, 1),
+    }
+    # algorithmic bytes of a whole stage over the measured time per stage
+    stage_bytes = sum(alg[n] for n in ("visc_prepass", "sweep_xi", "sweep_eta", "sweep_zeta_rk")) * blk.points
+    out["step_alg_GBps"] = round(stage_bytes * 3 * args.steps / el / 1e9, 1)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl, wname)
+    B.cfd_exchange_destroy(x)
+    B.cfd_block_destroy(h)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

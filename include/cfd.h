@@ -1,0 +1,203 @@
+/*
+ * cfd.h -- C ABI of libcfd, the MI355X (gfx950) implementation of the right-hand side of
+ * the curvilinear high-order finite-difference compressible Navier-Stokes scheme of
+ * Ye et al., "Accelerating CFD simulation with high order finite difference method on
+ * curvilinear coordinates for modern GPU clusters" (arXiv 2006.07964), fused with the
+ * three-stage TVD Runge-Kutta update.
+ *
+ * Conventions
+ *  - Every function returns an int status (CFD_OK or a negative CFD_ERR_*); on error
+ *    cfd_last_error() returns a thread-local message.  Nothing throws or aborts.
+ *  - Work is enqueued on a HIP stream and is asynchronous unless stated otherwise.
+ *    Argument errors are reported synchronously; device faults surface at the next
+ *    synchronising call (cfd_sync, cfd_dt_cfl, cfd_check_finite, cfd_metrics).
+ *  - Pointers named Q, R, Qn, Qcur, Qout, xyz and the block_bufs of cfd_halo_exchange
+ *    are device pointers owned by the caller; the library never frees them.  Metrics,
+ *    scratch, exchange tables and work lists are owned by the library and released by the
+ *    matching *_destroy.  Handles are not thread-safe.
+ *  - State layout: structure of arrays, plane v of a field holds
+ *        A[v*plane + ((k+3)*ld_j + (j+3))*ld_i + (i+3)],  plane = ld_i*ld_j*(nk+6),
+ *    for i in [-3, ni+3), j in [-3, nj+3), k in [-3, nk+3) (halo 3 on every face, i
+ *    contiguous); ld_i >= ni+6 and ld_j >= nj+6 may include padding.  Q has the five
+ *    planes (rho, rho u, rho v, rho w, e) of Eq 3 without the 1/J factor.
+ *  - Nondimensional units (Eq 1): rho_inf = 1, c_inf = 1, T = gamma p / rho, the viscous
+ *    terms carry Ma/Re.  Index spacing in xi, eta and zeta is one.
+ */
+#ifndef CFD_H
+#define CFD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------------------ */
+#define CFD_OK 0
+#define CFD_ERR_ARG (-1)          /* invalid argument (sizes, pointers, aliasing)        */
+#define CFD_ERR_ALLOC (-2)        /* device allocation failed                            */
+#define CFD_ERR_HIP (-3)          /* a HIP runtime call failed (message has details)     */
+#define CFD_ERR_STATE (-4)        /* call out of order (e.g. cfd_rhs before cfd_metrics) */
+#define CFD_ERR_JACOBIAN (-5)     /* some 1/J <= 0 (folded or left-handed grid)           */
+#define CFD_ERR_NONFINITE (-6)    /* NaN or Inf found in a state                         */
+#define CFD_ERR_UNSUPPORTED (-7)  /* valid request this build does not implement         */
+
+/* ---- enumerations ------------------------------------------------------------------ */
+enum { CFD_FP64 = 0, CFD_MIXED = 1 };                  /* arithmetic of the RHS        */
+enum { CFD_WENO_JS = 0, CFD_WENO_LINEAR = 1 };         /* Eq 15 weights or ideal ones  */
+enum { CFD_BC_PERIODIC = 0, CFD_BC_INTERFACE = 1, CFD_BC_WALL = 2, CFD_BC_FARFIELD = 3 };
+enum { CFD_FIELDS_Q = 0, CFD_FIELDS_VISC = 1 };        /* field sets of an exchange    */
+
+/* direction / term mask of cfd_rhs */
+#define CFD_DIR_XI 1u
+#define CFD_DIR_ETA 2u
+#define CFD_DIR_ZETA 4u
+#define CFD_TERM_INV 8u
+#define CFD_TERM_VIS 16u
+#define CFD_ALL 31u
+
+/* ---- descriptors ------------------------------------------------------------------- */
+typedef struct cfd_params {
+  double gamma;     /* ratio of specific heats (Sec. 2: 1.4)                            */
+  double mach;      /* Ma_inf; the viscous terms are scaled by Ma/Re (Eq 1)             */
+  double reynolds;  /* Re_inf                                                           */
+  double prandtl;   /* Pr of the heat flux (Eq 6)                                       */
+  double suth;      /* Sutherland constant S/T_ref of mu(T) = T^1.5 (1+S)/(T+S)         */
+  double weno_eps;  /* epsilon of Eq 15 (paper: 1e-6)                                   */
+  int32_t viscous;  /* 1: Navier-Stokes, 0: Euler                                       */
+  int32_t weights;  /* CFD_WENO_JS or CFD_WENO_LINEAR                                   */
+  double t_wall;    /* isothermal wall temperature (CFD_BC_WALL faces)                  */
+  double qinf[5];   /* conserved far-field state (CFD_BC_FARFIELD faces)                */
+} cfd_params;
+
+typedef struct cfd_block_desc {
+  int32_t ni, nj, nk;  /* interior points, each >= 7                                    */
+  int64_t ld_i, ld_j;  /* pitches in elements, ld_i >= ni+6, ld_j >= nj+6               */
+  int32_t precision;   /* CFD_FP64 or CFD_MIXED                                         */
+  int32_t bc[6];       /* face kinds in the order i-, i+, j-, j+, k-, k+                */
+  cfd_params params;
+} cfd_block_desc;
+
+typedef struct cfd_interface {  /* 1-to-1 face connection, identity orientation        */
+  int32_t block_a, face_a;      /* face index 0..5 in the order of cfd_block_desc.bc   */
+  int32_t block_b, face_b;      /* faces must be on the same axis and of equal size    */
+} cfd_interface;
+
+typedef struct cfd_block cfd_block;
+typedef struct cfd_exchange cfd_exchange;
+typedef struct cfd_batch cfd_batch;
+
+/* ---- errors ------------------------------------------------------------------------ */
+/* Message of the last failing call on this thread ("" if none).  The pointer stays
+ * valid until the next call on the same thread.                                        */
+const char* cfd_last_error(void);
+
+/* ---- blocks ------------------------------------------------------------------------ */
+/* Create a block: validates d, allocates the 10 metric planes (Sec. 2, Eqs 7-8) and the
+ * scratch of the RHS (12 viscous-flux planes, Eqs 5-6, and 5 partial-sum planes) on the
+ * current device.  hip_stream (hipStream_t, may be NULL = default stream) is the stream
+ * later calls enqueue on.  Errors: CFD_ERR_ARG, CFD_ERR_ALLOC.                           */
+int cfd_block_create(const cfd_block_desc* d, void* hip_stream, cfd_block** out);
+/* Free everything the block owns (waits for its stream first).  NULL is a no-op.        */
+int cfd_block_destroy(cfd_block* b);
+/* Change the stream later calls on b enqueue on.                                        */
+int cfd_block_set_stream(cfd_block* b, void* hip_stream);
+/* Device bytes the block owns (metrics + scratch).                                     */
+int cfd_block_bytes(const cfd_block* b, int64_t* bytes);
+
+/* Sec. 2, Eqs 7-8: conservative metrics xi_x/J ... zeta_z/J and the Jacobian J over the
+ * whole halo-3 box, in FP64, by sixth-order central differences of the coordinates.
+ * xyz: device, 3 planes (x, y, z) with halo 6: X[c*cplane + ((k+6)*cld_j + (j+6))*cld_i +
+ * (i+6)], cplane = cld_i*cld_j*(nk+12), cld_i >= ni+12, cld_j >= nj+12.  Periodic
+ * directions carry unwrapped images (x continues past the box), walls mirrored points.
+ * Synchronises; CFD_ERR_JACOBIAN if some 1/J <= 0.                                     */
+int cfd_metrics(cfd_block* b, const double* xyz, int64_t cld_i, int64_t cld_j);
+/* Device pointer to the block's 10 metric planes (layout of Q; plane 3*d+c = metric of
+ * direction d in {xi,eta,zeta}, component c in {x,y,z}, divided by J; plane 9 = J).     */
+int cfd_metrics_ptr(const cfd_block* b, const double** met);
+
+/* Right-hand side R = dQ/dt = J * Rtilde on the interior (Eq 2 with Q = J U~):
+ * inviscid derivatives by the modified AFWENO of Sec. 4.5.1 (Figs 10-11: characteristic
+ * projection at the node, fifth-order WENO interpolation to both half points, Eqs 13-17,
+ * Steger-Warming split fluxes, Eq 19) and central viscous terms (Eqs 5, 6, 21, sixth-order
+ * differences).  Q halos must be valid.  mask selects directions and terms (CFD_DIR_*,
+ * CFD_TERM_*); R interior is overwritten, halos untouched.  FP64 output in both
+ * precisions.  Not for the timed loop (use cfd_rk_stage).                               */
+int cfd_rhs(cfd_block* b, const double* Q, double* R, unsigned mask);
+
+/* One stage s in {0,1,2} of the TVD-RK3 scheme (Eq 20), fused with the RHS:
+ * Qout = a_s Qn + b_s Qcur + c_s dt R(Qcur) on the interior with (a,b,c) = (1,0,1),
+ * (3/4,1/4,1/4), (1/3,2/3,2/3).  Accumulation is FP64 in both precisions.  Qout halos are
+ * left stale (run cfd_halo_exchange).  Qout must not alias Qcur; Qout may alias Qn only
+ * at stage 2; at stage 0, Qcur must equal Qn.  Errors: CFD_ERR_ARG, CFD_ERR_STATE.      */
+int cfd_rk_stage(cfd_block* b, int stage, double dt, const double* Qn, const double* Qcur,
+                 double* Qout);
+/* Same, with dt read from device memory at run time (for captured graphs).             */
+int cfd_rk_stage_dev(cfd_block* b, int stage, const double* dt_dev, const double* Qn,
+                     const double* Qcur, double* Qout);
+
+/* Split form of cfd_rhs / cfd_rk_stage for blocks with CFD_BC_INTERFACE faces, whose
+ * viscous-flux halos need data of other blocks: run cfd_viscous_fluxes on every block,
+ * then cfd_halo_exchange(x, CFD_FIELDS_VISC, NULL, ...), then the sweeps.  The viscous
+ * fluxes (Eqs 5-6 with the gradients of Eq 21) land in the block's scratch; periodic and
+ * physical faces of the block get their viscous halos inside cfd_viscous_fluxes.        */
+int cfd_viscous_fluxes(cfd_block* b, const double* Q);
+int cfd_rhs_sweeps(cfd_block* b, const double* Q, double* R, unsigned mask);
+int cfd_rk_sweeps(cfd_block* b, int stage, double dt, const double* Qn, const double* Qcur,
+                  double* Qout);
+
+/* ---- halo exchange ----------------------------------------------------------------- */
+/* Plan the halo traffic of nb blocks: ifc lists the 1-to-1 interfaces (a face of a block
+ * listed with itself on the opposite face is a periodic wrap); every face whose kind is
+ * CFD_BC_PERIODIC must appear, CFD_BC_WALL / CFD_BC_FARFIELD faces get ghost fills.
+ * Errors: CFD_ERR_ARG on mismatched face sizes, axes or kinds.                          */
+int cfd_exchange_create(cfd_block* const* blocks, int nb, const cfd_interface* ifc, int nifc,
+                        cfd_exchange** out);
+int cfd_exchange_destroy(cfd_exchange* x);
+/* Refill halos by on-device copies (Sec. 4.2: blocks of one process exchange on the
+ * device).  field_set CFD_FIELDS_Q: block_bufs[b] is block b's caller-owned Q (5 planes);
+ * copies 3-deep face slabs across interfaces, then ghost-fills walls and far field and
+ * resets wall nodes (no slip, T = t_wall).  CFD_FIELDS_VISC: block_bufs must be NULL;
+ * copies the library's viscous-flux planes (direction-d components across d-faces).
+ * Enqueued on hip_stream (NULL: the first block's stream).                              */
+int cfd_halo_exchange(cfd_exchange* x, int field_set, void* const* block_bufs, void* hip_stream);
+
+/* ---- time step and checks ---------------------------------------------------------- */
+/* dt = cfl / max over all interior points of all blocks of
+ * sum_d (|U_d| + c |grad d|), U_d the contravariant velocity with unhatted metrics
+ * (the CFL-controlled global step of Sec. 4.5.3).  Q[b] device.  Synchronises.          */
+int cfd_dt_cfl(cfd_block* const* blocks, int nb, const double* const* Q, double cfl,
+               double* dt_out);
+/* *ok = 1 if every interior value of Q is finite, else 0 (and CFD_ERR_NONFINITE).
+ * Synchronises.                                                                        */
+int cfd_check_finite(cfd_block* b, const double* Q, int* ok);
+/* Wait for the block's stream and report any pending device error.                     */
+int cfd_sync(cfd_block* b);
+
+/* ---- batched multi-block form ------------------------------------------------------ */
+/* Batch all blocks (one precision) behind one launch per phase over a work list of
+ * tiles of every block; x must have been created for the same blocks in the same order.
+ * hip_stream: stream of the batch.                                                      */
+int cfd_batch_create(cfd_block* const* blocks, int nb, cfd_exchange* x, void* hip_stream,
+                     cfd_batch** out);
+int cfd_batch_destroy(cfd_batch* bt);
+/* One full RK3 step of all blocks: Qn[b] (in/out), QA[b] and QB[b] (caller scratch of
+ * the layout of Qn[b]); dt_dev is a device double.  The first call captures the step in a
+ * HIP graph for this pointer set; later calls with the same pointers replay it.         */
+int cfd_batch_step(cfd_batch* bt, const double* dt_dev, double* const* Qn, double* const* QA,
+                   double* const* QB);
+
+/* ---- profiling --------------------------------------------------------------------- */
+/* Enable (1) or disable (0) per-launch HIP event timing of the block's kernels.         */
+int cfd_profile_enable(cfd_block* b, int enable);
+/* Copy up to cap (name, launches, total milliseconds) entries of the kernels timed so
+ * far; names are static strings.  Synchronises.  *n receives the entry count.           */
+int cfd_profile_read(cfd_block* b, const char** names, int64_t* launches, double* ms, int cap,
+                     int* n);
+/* Reset the profiling counters.                                                        */
+int cfd_profile_reset(cfd_block* b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CFD_H */

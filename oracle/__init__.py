@@ -72,6 +72,10 @@ def lib():
         L.oracle_split_flux.restype = None
         L.oracle_phys_flux.argtypes = [P, P, C.c_double, P]
         L.oracle_phys_flux.restype = None
+        L.oracle_threads.argtypes = []
+        L.oracle_threads.restype = C.c_int
+        L.oracle_wall_reset.argtypes = [cp, P]
+        L.oracle_wall_reset.restype = None
         L.oracle_viscosity.argtypes = [C.c_double, C.c_double]
         L.oracle_viscosity.restype = C.c_double
         PP = C.POINTER(P)
@@ -161,6 +165,16 @@ def bc_fill(c: Cfg, q: np.ndarray) -> np.ndarray:
     out = np.array(q, dtype=np.float64, copy=True)
     lib().oracle_bc_fill(C.byref(c), _p(out))
     return out
+
+
+def wall_reset(c: Cfg, q: np.ndarray) -> np.ndarray:
+    out = np.array(q, dtype=np.float64, copy=True)
+    lib().oracle_wall_reset(C.byref(c), _p(out))
+    return out
+
+
+def threads() -> int:
+    return int(lib().oracle_threads())
 
 
 def dt_cfl(c: Cfg, met, q, cfl) -> float:

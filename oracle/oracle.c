@@ -15,6 +15,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define HS 3  /* halo of state / metric arrays */
 #define HX 6  /* halo of coordinate arrays     */
@@ -387,9 +390,35 @@ static void face_geom(const oracle_cfg* c, int f, int* axis, int* wall_idx, int*
 }
 
 /* Reading (physical boundaries, not specified by the paper): the boundary node itself
- * is part of the interior.  Isothermal no-slip wall: ghost m mirrors interior node m
- * with odd velocity, the same pressure and T_g = 2 T_w - T_m; after every stage the wall
- * node gets zero velocity and T = T_w at its own density.  Far field: ghosts hold qinf.  */
+ * is part of the interior.  Isothermal no-slip wall: after every stage the wall node gets
+ * zero velocity and T = T_w at its own density (oracle_wall_reset, before any halo copy);
+ * ghost m mirrors interior node m with odd velocity, the same pressure and
+ * T_g = 2 T_w - T_m.  Far field: ghosts hold qinf (oracle_bc_fill).                      */
+void oracle_wall_reset(const oracle_cfg* c, double* Q) {
+  const dims_t sd = state_dims(c);
+  int f;
+  for (f = 0; f < 6; ++f) {
+    int axis, w, out, a, b, na, nb;
+    if (c->bc[f] != ORACLE_BC_WALL) continue;
+    face_geom(c, f, &axis, &w, &out);
+    na = npts(c, (axis + 1) % 3);
+    nb = npts(c, (axis + 2) % 3);
+    for (b = 0; b < nb; ++b)
+      for (a = 0; a < na; ++a) {
+        int idx[3];
+        long pw;
+        idx[(axis + 1) % 3] = a;
+        idx[(axis + 2) % 3] = b;
+        idx[axis] = w;
+        pw = sidx(&sd, idx[0], idx[1], idx[2]);
+        Q[1 * sd.plane + pw] = 0.0;
+        Q[2 * sd.plane + pw] = 0.0;
+        Q[3 * sd.plane + pw] = 0.0;
+        Q[4 * sd.plane + pw] = Q[pw] * c->t_wall / (c->gamma * (c->gamma - 1.0));
+      }
+  }
+}
+
 void oracle_bc_fill(const oracle_cfg* c, double* Q) {
   const dims_t sd = state_dims(c);
   int f;
@@ -403,18 +432,8 @@ void oracle_bc_fill(const oracle_cfg* c, double* Q) {
     for (b = 0; b < nb; ++b)
       for (a = 0; a < na; ++a) {
         int idx[3];
-        long pw;
         idx[(axis + 1) % 3] = a;
         idx[(axis + 2) % 3] = b;
-        idx[axis] = w;
-        pw = sidx(&sd, idx[0], idx[1], idx[2]);
-        if (c->bc[f] == ORACLE_BC_WALL) {
-          double rho = Q[pw];
-          Q[1 * sd.plane + pw] = 0.0;
-          Q[2 * sd.plane + pw] = 0.0;
-          Q[3 * sd.plane + pw] = 0.0;
-          Q[4 * sd.plane + pw] = rho * c->t_wall / (c->gamma * (c->gamma - 1.0));
-        }
         for (m = 1; m <= HS; ++m) {
           long pg, pm;
           idx[axis] = w + out * m;
@@ -684,6 +703,7 @@ int oracle_rk_stage(const oracle_cfg* c, const double* met, int stage, double dt
   rc = oracle_rhs(c, met, Qcur, R, ORACLE_ALL, 0, c->nk);
   if (rc == 0) {
     rk_combine(c, stage, dt, Qn, Qcur, R, Qout);
+    oracle_wall_reset(c, Qout);
     oracle_periodic_wrap(c, Qout, 5);
     oracle_bc_fill(c, Qout);
   }
@@ -814,6 +834,7 @@ int oracle_rk_step_multi(const oracle_cfg* cfgs, int nb, const double* const* me
     rc = oracle_rhs_multi(cfgs, nb, (const double* const*)met, (const double* const*)cur, R, ORACLE_ALL, ifc, nifc);
     if (rc) break;
     for (b = 0; b < nb; ++b) rk_combine(&cfgs[b], stage, dt, Qn[b], cur[b], R[b], out[b]);
+    for (b = 0; b < nb; ++b) oracle_wall_reset(&cfgs[b], out[b]);
     for (b = 0; b < nb; ++b) oracle_periodic_wrap(&cfgs[b], out[b], 5);
     rc = oracle_exchange(cfgs, nb, out, 5, ifc, nifc);
     for (b = 0; b < nb; ++b) oracle_bc_fill(&cfgs[b], out[b]);
@@ -822,4 +843,12 @@ int oracle_rk_step_multi(const oracle_cfg* cfgs, int nb, const double* const* me
   for (b = 0; b < nb; ++b) { free(A[b]); free(Bq[b]); free(R[b]); }
   free(Qn); free(A); free(Bq); free(R);
   return rc;
+}
+
+int oracle_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }

@@ -70,7 +70,9 @@ int oracle_rk_step(const oracle_cfg* c, const double* met, double dt, double* Q)
 /* Fill the halo of nvar planes of a single periodic block by periodic wrap.             */
 void oracle_periodic_wrap(const oracle_cfg* c, double* A, int nvar);
 
-/* Physical ghost fill for wall / far-field faces of one block (after a stage).          */
+/* Wall nodes of one block: zero velocity, T = t_wall at their own density.              */
+void oracle_wall_reset(const oracle_cfg* c, double* Q);
+/* Ghost fill of wall / far-field faces of one block (after the halo copies).           */
 void oracle_bc_fill(const oracle_cfg* c, double* Q);
 
 /* CFL time step: cfl / max over interior of sum_d (|U_d| + c |grad d|).                 */
@@ -108,6 +110,9 @@ int oracle_rhs_multi(const oracle_cfg* cfgs, int nb, const double* const* met,
 /* One RK3 step of all blocks in place (exchanges and ghost fills after every stage).   */
 int oracle_rk_step_multi(const oracle_cfg* cfgs, int nb, const double* const* met,
                          double dt, double* const* Q, const oracle_iface* ifc, int nifc);
+
+/* Number of OpenMP threads the oracle's parallel loops use.                             */
+int oracle_threads(void);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,764 @@
+// cfd_api.hip -- host side of libcfd: the C ABI declared in include/cfd.h.
+//
+// Block objects own the metric planes and the RHS scratch; exchange plans own device
+// tables of face-copy segments; batches own work lists and captured HIP graphs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/cfd.h"
+#include "cfd_kernels.hpp"
+
+using namespace cfd;
+
+// =====================================================================================
+// errors
+// =====================================================================================
+namespace {
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+int hip_fail(hipError_t e, const char* what) {
+  return fail(CFD_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+#define HIP_TRY(expr, what)                   \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+bool is_real_size(int n) { return n >= 7 && n <= (1 << 20); }
+
+// ---- profiling ----------------------------------------------------------------------
+struct ProfPending {
+  const char* name;
+  hipEvent_t a, b;
+};
+struct Profiler {
+  bool on = false;
+  std::vector<ProfPending> pending;
+  std::vector<hipEvent_t> pool;
+  std::map<std::string, std::pair<int64_t, double>> acc;
+  std::vector<std::string> order;
+
+  hipEvent_t ev() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void drain() {
+    for (auto& p : pending) {
+      float ms = 0.f;
+      if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+        auto it = acc.find(p.name);
+        if (it == acc.end()) {
+          order.push_back(p.name);
+          acc[p.name] = {1, (double)ms};
+        } else {
+          it->second.first += 1;
+          it->second.second += ms;
+        }
+      }
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pending.clear();
+  }
+  ~Profiler() {
+    for (auto& p : pending) {
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+// RAII bracket: records the start event on construction and the stop event on done().
+struct ProfScope {
+  Profiler* P;
+  const char* name;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  ProfScope(Profiler* p, const char* n, hipStream_t st) : P(p), name(n), s(st) {
+    if (P && P->on) {
+      a = P->ev();
+      if (a) (void)hipEventRecord(a, s);
+    }
+  }
+  void done() {
+    if (P && P->on && a) {
+      hipEvent_t b = P->ev();
+      if (b) {
+        (void)hipEventRecord(b, s);
+        P->pending.push_back({name, a, b});
+        if (P->pending.size() > 4096) P->drain();
+      }
+      a = nullptr;
+    }
+  }
+};
+}  // namespace
+
+// =====================================================================================
+// block
+// =====================================================================================
+struct cfd_block {
+  cfd_block_desc d;
+  Geom g;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  double* met = nullptr;  // 10 planes FP64
+  void* vis = nullptr;    // 12 planes (compute type)
+  void* rt = nullptr;     // 5 planes (compute type)
+  size_t esize = 8;       // bytes of the compute type
+  bool have_metrics = false;
+  int64_t bytes = 0;
+  // block-local viscous halo work: self-periodic copies and physical-face ghosts
+  CopySeg* local_copy_dev = nullptr;
+  int n_local_copy = 0, max_local_copy = 0;
+  BcSeg* local_bc_dev = nullptr;
+  int n_local_bc = 0, max_local_bc = 0;
+  bool has_interface = false;
+  // small device scratch for reductions
+  unsigned long long* red_dev = nullptr;
+  int* flag_dev = nullptr;
+  Profiler prof;
+};
+
+namespace {
+
+Phys make_phys(const cfd_params& p) {
+  Phys ph;
+  ph.gamma = p.gamma;
+  ph.visc_scale = p.mach / p.reynolds;
+  ph.heat_scale = p.mach / (p.reynolds * p.prandtl * (p.gamma - 1.0));
+  ph.suth = p.suth;
+  ph.eps = p.weno_eps;
+  ph.linear = p.weights == CFD_WENO_LINEAR;
+  return ph;
+}
+
+int npts(const Geom& g, int axis) { return axis == 0 ? g.ni : axis == 1 ? g.nj : g.nk; }
+int64_t stride(const Geom& g, int axis) { return axis == 0 ? 1 : axis == 1 ? g.ld_i : g.ld_i * g.ld_j; }
+int64_t at_h(const Geom& g, int i, int j, int k) {
+  return ((int64_t)(k + kHalo) * g.ld_j + (j + kHalo)) * g.ld_i + (i + kHalo);
+}
+
+// boundary node index of face f along its axis, and the outward sign
+void face_geom(const Geom& g, int f, int* axis, int* w, int* out) {
+  *axis = f / 2;
+  *out = (f % 2) ? +1 : -1;
+  *w = (f % 2) ? npts(g, *axis) - 1 : 0;
+}
+
+// halo copy of face fa of block A (index ia) from face fb of block B (index ib):
+// ghost layer m (1..3) beyond fa <- interior layer m-1 inside fb.
+CopySeg make_copy(const Geom& A, int ia, int fa, const Geom& B, int ib, int fb, int plane0, int nplanes) {
+  int axis, wa, outa, wb, outb;
+  face_geom(A, fa, &axis, &wa, &outa);
+  int axis_b;
+  face_geom(B, fb, &axis_b, &wb, &outb);
+  const int ta = (axis + 1) % 3, tb = (axis + 2) % 3;
+  CopySeg s;
+  s.dst = ia;
+  s.src = ib;
+  s.na = npts(A, ta);
+  s.nb = npts(A, tb);
+  s.plane0 = plane0;
+  s.nplanes = nplanes;
+  int ida[3] = {0, 0, 0}, idb[3] = {0, 0, 0};
+  ida[axis] = wa + outa;  // ghost layer 1
+  idb[axis] = wb;         // interior layer 0
+  s.dst_off = at_h(A, ida[0], ida[1], ida[2]);
+  s.src_off = at_h(B, idb[0], idb[1], idb[2]);
+  s.dst_sa = stride(A, ta);
+  s.dst_sb = stride(A, tb);
+  s.dst_sl = outa * stride(A, axis);
+  s.src_sa = stride(B, ta);
+  s.src_sb = stride(B, tb);
+  s.src_sl = -outb * stride(B, axis);
+  return s;
+}
+
+BcSeg make_bc(const Geom& G, int blk, int f, int kind) {
+  int axis, w, out;
+  face_geom(G, f, &axis, &w, &out);
+  const int ta = (axis + 1) % 3, tb = (axis + 2) % 3;
+  BcSeg s;
+  s.blk = blk;
+  s.kind = kind;
+  s.na = npts(G, ta);
+  s.nb = npts(G, tb);
+  int id[3] = {0, 0, 0};
+  id[axis] = w;
+  s.wall_off = at_h(G, id[0], id[1], id[2]);
+  s.sa = stride(G, ta);
+  s.sb = stride(G, tb);
+  s.sout = out * stride(G, axis);
+  s.axis = axis;
+  return s;
+}
+
+template <typename T>
+int upload(const std::vector<T>& v, T** dev) {
+  *dev = nullptr;
+  if (v.empty()) return CFD_OK;
+  HIP_TRY(hipMalloc((void**)dev, v.size() * sizeof(T)), "hipMalloc(table)");
+  HIP_TRY(hipMemcpy(*dev, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy(table)");
+  return CFD_OK;
+}
+
+int validate_desc(const cfd_block_desc* d) {
+  if (!d) return fail(CFD_ERR_ARG, "null descriptor");
+  if (!is_real_size(d->ni) || !is_real_size(d->nj) || !is_real_size(d->nk))
+    return fail(CFD_ERR_ARG, "ni, nj and nk must each be at least 7");
+  if (d->ld_i < d->ni + 6 || d->ld_j < d->nj + 6) return fail(CFD_ERR_ARG, "pitches must satisfy ld_i >= ni+6, ld_j >= nj+6");
+  if (d->precision != CFD_FP64 && d->precision != CFD_MIXED) return fail(CFD_ERR_ARG, "unknown precision");
+  const cfd_params& p = d->params;
+  if (!(p.gamma > 1.0) || !(p.reynolds > 0.0) || !(p.prandtl > 0.0) || !(p.weno_eps > 0.0) || !(p.suth > 0.0))
+    return fail(CFD_ERR_ARG, "gamma > 1, Re, Pr, Sutherland constant and WENO epsilon > 0 required");
+  if (p.weights != CFD_WENO_JS && p.weights != CFD_WENO_LINEAR) return fail(CFD_ERR_ARG, "unknown WENO weights");
+  for (int f = 0; f < 6; ++f)
+    if (d->bc[f] < CFD_BC_PERIODIC || d->bc[f] > CFD_BC_FARFIELD) return fail(CFD_ERR_ARG, "unknown face kind");
+  for (int ax = 0; ax < 3; ++ax)
+    if ((d->bc[2 * ax] == CFD_BC_PERIODIC) != (d->bc[2 * ax + 1] == CFD_BC_PERIODIC))
+      return fail(CFD_ERR_ARG, "periodic faces come in pairs on one axis");
+  if (d->bc[2] == CFD_BC_WALL || d->bc[3] == CFD_BC_WALL || d->bc[0] == CFD_BC_WALL || d->bc[1] == CFD_BC_WALL ||
+      d->bc[4] == CFD_BC_WALL || d->bc[5] == CFD_BC_WALL) {
+    if (!(p.t_wall > 0.0)) return fail(CFD_ERR_ARG, "wall faces need t_wall > 0");
+  }
+  return CFD_OK;
+}
+
+template <typename T>
+PtrTable single_table(void* p, int64_t plane) {
+  PtrTable t;
+  std::memset(&t, 0, sizeof t);
+  t.p[0] = p;
+  t.plane[0] = plane;
+  return t;
+}
+
+// viscous fluxes of one block with block-local halos (periodic wraps, physical ghosts)
+int run_visc(cfd_block* b, const double* Q) {
+  ViscArgs va;
+  va.g = b->g;
+  va.q = Q;
+  va.met = b->met;
+  va.vis = b->vis;
+  va.ph = make_phys(b->d.params);
+  ProfScope ps(&b->prof, "visc_prepass", b->stream);
+  hipError_t e = b->d.precision == CFD_FP64 ? launch_visc<double>(va, b->stream) : launch_visc<float>(va, b->stream);
+  ps.done();
+  if (e != hipSuccess) return hip_fail(e, "visc_prepass launch");
+  if (b->n_local_copy) {
+    PtrTable t = single_table<double>(b->vis, b->g.plane);
+    ProfScope pc(&b->prof, "visc_halo", b->stream);
+    e = b->d.precision == CFD_FP64 ? launch_copy<double>(b->local_copy_dev, b->n_local_copy, b->max_local_copy, t, b->stream)
+                                   : launch_copy<float>(b->local_copy_dev, b->n_local_copy, b->max_local_copy, t, b->stream);
+    pc.done();
+    if (e != hipSuccess) return hip_fail(e, "visc halo copy");
+  }
+  if (b->n_local_bc) {
+    PtrTable t = single_table<double>(b->vis, b->g.plane);
+    e = b->d.precision == CFD_FP64 ? launch_visc_ghost<double>(b->local_bc_dev, b->n_local_bc, b->max_local_bc, t, b->stream)
+                                   : launch_visc_ghost<float>(b->local_bc_dev, b->n_local_bc, b->max_local_bc, t, b->stream);
+    if (e != hipSuccess) return hip_fail(e, "visc ghost fill");
+  }
+  return CFD_OK;
+}
+
+const char* kSweepNames[3] = {"sweep_xi", "sweep_eta", "sweep_zeta"};
+const char* kSweepRkNames[3] = {"sweep_xi_rk", "sweep_eta_rk", "sweep_zeta_rk"};
+
+// run the direction sweeps selected by mask; the last one writes R or the RK stage
+int run_sweeps(cfd_block* b, const double* Q, unsigned mask, int out_kind, double* out, const double* qn,
+               const double* dt_dev, double dt, double ca, double cb, double cc) {
+  const bool inv = (mask & CFD_TERM_INV) != 0;
+  const bool vis = (mask & CFD_TERM_VIS) != 0 && b->d.params.viscous;
+  int dirs[3], nd = 0;
+  for (int d = 0; d < 3; ++d)
+    if (mask & (1u << d)) dirs[nd++] = d;
+  SweepArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.g = b->g;
+  a.q = Q;
+  a.met = b->met;
+  a.vis = b->vis;
+  a.ph = make_phys(b->d.params);
+  a.do_inv = inv;
+  a.do_vis = vis;
+  a.qn = qn;
+  a.dt_dev = dt_dev;
+  a.dt = dt;
+  a.ca = ca;
+  a.cb = cb;
+  a.cc = cc;
+  if (nd == 0 || (!inv && !vis)) {
+    // nothing to evaluate: R = 0 or Qout = ca Qn + cb Q, via a zero-term sweep along xi
+    a.do_inv = 0;
+    a.do_vis = 0;
+    a.has_prev = 0;
+    a.out_kind = out_kind;
+    a.out = out;
+    ProfScope ps(&b->prof, kSweepNames[0], b->stream);
+    hipError_t e = b->d.precision == CFD_FP64 ? launch_sweep<double>(0, a, b->stream) : launch_sweep<float>(0, a, b->stream);
+    ps.done();
+    return e == hipSuccess ? CFD_OK : hip_fail(e, "sweep launch");
+  }
+  for (int n = 0; n < nd; ++n) {
+    const bool last = n == nd - 1;
+    a.has_prev = n > 0;
+    a.rt_in = b->rt;
+    a.rt_out = b->rt;
+    a.out_kind = last ? out_kind : kOutPartial;
+    a.out = last ? out : nullptr;
+    const char* name = (last && out_kind == kOutRK) ? kSweepRkNames[dirs[n]] : kSweepNames[dirs[n]];
+    ProfScope ps(&b->prof, name, b->stream);
+    hipError_t e = b->d.precision == CFD_FP64 ? launch_sweep<double>(dirs[n], a, b->stream)
+                                              : launch_sweep<float>(dirs[n], a, b->stream);
+    ps.done();
+    if (e != hipSuccess) return hip_fail(e, "sweep launch");
+  }
+  return CFD_OK;
+}
+
+const double kRK[3][3] = {{1.0, 0.0, 1.0}, {0.75, 0.25, 0.25}, {1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0}};
+
+int check_rk_args(cfd_block* b, int stage, const double* Qn, const double* Qcur, double* Qout) {
+  if (!b) return fail(CFD_ERR_ARG, "null block");
+  if (stage < 0 || stage > 2) return fail(CFD_ERR_ARG, "stage must be 0, 1 or 2");
+  if (!Qn || !Qcur || !Qout) return fail(CFD_ERR_ARG, "null state pointer");
+  if (Qout == Qcur) return fail(CFD_ERR_ARG, "Qout must not alias Qcur");
+  if (Qout == Qn && stage != 2) return fail(CFD_ERR_ARG, "Qout may alias Qn only at stage 2");
+  if (stage == 0 && Qcur != Qn) return fail(CFD_ERR_ARG, "at stage 0 Qcur must be Qn");
+  if (!b->have_metrics) return fail(CFD_ERR_STATE, "cfd_metrics has not been run on this block");
+  return CFD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cfd_last_error(void) { return g_err.c_str(); }
+
+int cfd_block_create(const cfd_block_desc* d, void* hip_stream, cfd_block** out) {
+  if (!out) return fail(CFD_ERR_ARG, "null output handle");
+  *out = nullptr;
+  int rc = validate_desc(d);
+  if (rc) return rc;
+  cfd_block* b = new cfd_block();
+  b->d = *d;
+  b->g.ni = d->ni;
+  b->g.nj = d->nj;
+  b->g.nk = d->nk;
+  b->g.ld_i = d->ld_i;
+  b->g.ld_j = d->ld_j;
+  b->g.plane = d->ld_i * d->ld_j * (int64_t)(d->nk + 6);
+  b->stream = (hipStream_t)hip_stream;
+  b->esize = d->precision == CFD_FP64 ? 8 : 4;
+  (void)hipGetDevice(&b->device);
+  const size_t plane = (size_t)b->g.plane;
+  auto cleanup = [&](int code, const std::string& msg) {
+    cfd_block_destroy(b);
+    return fail(code, msg);
+  };
+  if (hipMalloc((void**)&b->met, 10 * plane * sizeof(double)) != hipSuccess) return cleanup(CFD_ERR_ALLOC, "metrics allocation");
+  if (hipMalloc(&b->vis, 12 * plane * b->esize) != hipSuccess) return cleanup(CFD_ERR_ALLOC, "viscous scratch allocation");
+  if (hipMalloc(&b->rt, 5 * plane * b->esize) != hipSuccess) return cleanup(CFD_ERR_ALLOC, "partial-sum allocation");
+  if (hipMalloc((void**)&b->red_dev, sizeof(unsigned long long)) != hipSuccess ||
+      hipMalloc((void**)&b->flag_dev, sizeof(int)) != hipSuccess)
+    return cleanup(CFD_ERR_ALLOC, "reduction scratch");
+  if (hipMemset(b->met, 0, 10 * plane * sizeof(double)) != hipSuccess || hipMemset(b->vis, 0, 12 * plane * b->esize) != hipSuccess ||
+      hipMemset(b->rt, 0, 5 * plane * b->esize) != hipSuccess)
+    return cleanup(CFD_ERR_HIP, "scratch clear");
+  b->bytes = (int64_t)plane * (10 * 8 + 17 * (int64_t)b->esize);
+  // block-local viscous halo work
+  std::vector<CopySeg> cs;
+  std::vector<BcSeg> bs;
+  for (int ax = 0; ax < 3; ++ax) {
+    if (d->bc[2 * ax] == CFD_BC_PERIODIC) {
+      cs.push_back(make_copy(b->g, 0, 2 * ax, b->g, 0, 2 * ax + 1, 4 * ax, 4));
+      cs.push_back(make_copy(b->g, 0, 2 * ax + 1, b->g, 0, 2 * ax, 4 * ax, 4));
+    }
+  }
+  for (int f = 0; f < 6; ++f) {
+    if (d->bc[f] == CFD_BC_WALL || d->bc[f] == CFD_BC_FARFIELD) bs.push_back(make_bc(b->g, 0, f, d->bc[f]));
+    if (d->bc[f] == CFD_BC_INTERFACE) b->has_interface = true;
+  }
+  for (auto& s : cs) b->max_local_copy = std::max(b->max_local_copy, s.na * s.nb * kHalo * s.nplanes);
+  for (auto& s : bs) b->max_local_bc = std::max(b->max_local_bc, s.na * s.nb);
+  if (upload(cs, &b->local_copy_dev) || upload(bs, &b->local_bc_dev)) return cleanup(CFD_ERR_HIP, "halo tables");
+  b->n_local_copy = (int)cs.size();
+  b->n_local_bc = (int)bs.size();
+  *out = b;
+  return CFD_OK;
+}
+
+int cfd_block_destroy(cfd_block* b) {
+  if (!b) return CFD_OK;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  else (void)hipDeviceSynchronize();
+  b->prof.drain();
+  (void)hipFree(b->met);
+  (void)hipFree(b->vis);
+  (void)hipFree(b->rt);
+  (void)hipFree(b->red_dev);
+  (void)hipFree(b->flag_dev);
+  (void)hipFree(b->local_copy_dev);
+  (void)hipFree(b->local_bc_dev);
+  delete b;
+  return CFD_OK;
+}
+
+int cfd_block_set_stream(cfd_block* b, void* hip_stream) {
+  if (!b) return fail(CFD_ERR_ARG, "null block");
+  b->stream = (hipStream_t)hip_stream;
+  return CFD_OK;
+}
+
+int cfd_block_bytes(const cfd_block* b, int64_t* bytes) {
+  if (!b || !bytes) return fail(CFD_ERR_ARG, "null argument");
+  *bytes = b->bytes;
+  return CFD_OK;
+}
+
+int cfd_metrics(cfd_block* b, const double* xyz, int64_t cld_i, int64_t cld_j) {
+  if (!b || !xyz) return fail(CFD_ERR_ARG, "null argument");
+  if (cld_i < b->g.ni + 12 || cld_j < b->g.nj + 12) return fail(CFD_ERR_ARG, "coordinate pitches too small (halo 6)");
+  MetricArgs a;
+  a.g = b->g;
+  a.xyz = xyz;
+  a.cld_i = cld_i;
+  a.cld_j = cld_j;
+  a.cplane = cld_i * cld_j * (int64_t)(b->g.nk + 12);
+  const size_t tplane = (size_t)(b->g.ni + 12) * (b->g.nj + 12) * (b->g.nk + 12);
+  a.met = b->met;
+  a.bad = b->flag_dev;
+  HIP_TRY(hipMalloc((void**)&a.dcoord, 9 * tplane * sizeof(double)), "hipMalloc(metric scratch)");
+  int rc = CFD_OK;
+  hipError_t e = hipMemsetAsync(b->flag_dev, 0, sizeof(int), b->stream);
+  if (e == hipSuccess) e = launch_metrics(a, b->stream);
+  int bad = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&bad, b->flag_dev, sizeof(int), hipMemcpyDeviceToHost, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  (void)hipFree(a.dcoord);
+  if (e != hipSuccess) return hip_fail(e, "cfd_metrics");
+  if (bad) rc = fail(CFD_ERR_JACOBIAN, "non-positive 1/J: folded or left-handed grid");
+  b->have_metrics = rc == CFD_OK;
+  return rc;
+}
+
+int cfd_metrics_ptr(const cfd_block* b, const double** met) {
+  if (!b || !met) return fail(CFD_ERR_ARG, "null argument");
+  *met = b->met;
+  return CFD_OK;
+}
+
+int cfd_viscous_fluxes(cfd_block* b, const double* Q) {
+  if (!b || !Q) return fail(CFD_ERR_ARG, "null argument");
+  if (!b->have_metrics) return fail(CFD_ERR_STATE, "cfd_metrics has not been run on this block");
+  if (!b->d.params.viscous) return CFD_OK;
+  return run_visc(b, Q);
+}
+
+int cfd_rhs_sweeps(cfd_block* b, const double* Q, double* R, unsigned mask) {
+  if (!b || !Q || !R) return fail(CFD_ERR_ARG, "null argument");
+  if (Q == R) return fail(CFD_ERR_ARG, "R must not alias Q");
+  if (!b->have_metrics) return fail(CFD_ERR_STATE, "cfd_metrics has not been run on this block");
+  return run_sweeps(b, Q, mask, kOutRhs, R, nullptr, nullptr, 0.0, 0.0, 0.0, 0.0);
+}
+
+int cfd_rhs(cfd_block* b, const double* Q, double* R, unsigned mask) {
+  if (!b || !Q || !R) return fail(CFD_ERR_ARG, "null argument");
+  if (b->has_interface)
+    return fail(CFD_ERR_STATE, "block has interface faces: use cfd_viscous_fluxes, cfd_halo_exchange(VISC), cfd_rhs_sweeps");
+  if ((mask & CFD_TERM_VIS) && b->d.params.viscous) {
+    int rc = cfd_viscous_fluxes(b, Q);
+    if (rc) return rc;
+  }
+  return cfd_rhs_sweeps(b, Q, R, mask);
+}
+
+static int rk_sweeps(cfd_block* b, int stage, const double* dt_dev, double dt, const double* Qn, const double* Qcur,
+                     double* Qout) {
+  int rc = check_rk_args(b, stage, Qn, Qcur, Qout);
+  if (rc) return rc;
+  return run_sweeps(b, Qcur, CFD_ALL, kOutRK, Qout, Qn, dt_dev, dt, kRK[stage][0], kRK[stage][1], kRK[stage][2]);
+}
+
+int cfd_rk_sweeps(cfd_block* b, int stage, double dt, const double* Qn, const double* Qcur, double* Qout) {
+  if (!std::isfinite(dt)) return fail(CFD_ERR_ARG, "dt must be finite");
+  return rk_sweeps(b, stage, nullptr, dt, Qn, Qcur, Qout);
+}
+
+int cfd_rk_stage(cfd_block* b, int stage, double dt, const double* Qn, const double* Qcur, double* Qout) {
+  int rc = check_rk_args(b, stage, Qn, Qcur, Qout);
+  if (rc) return rc;
+  if (!std::isfinite(dt)) return fail(CFD_ERR_ARG, "dt must be finite");
+  if (b->has_interface)
+    return fail(CFD_ERR_STATE, "block has interface faces: use cfd_viscous_fluxes, cfd_halo_exchange(VISC), cfd_rk_sweeps");
+  if (b->d.params.viscous) {
+    rc = run_visc(b, Qcur);
+    if (rc) return rc;
+  }
+  return rk_sweeps(b, stage, nullptr, dt, Qn, Qcur, Qout);
+}
+
+int cfd_rk_stage_dev(cfd_block* b, int stage, const double* dt_dev, const double* Qn, const double* Qcur,
+                     double* Qout) {
+  int rc = check_rk_args(b, stage, Qn, Qcur, Qout);
+  if (rc) return rc;
+  if (!dt_dev) return fail(CFD_ERR_ARG, "null dt_dev");
+  if (b->has_interface)
+    return fail(CFD_ERR_STATE, "block has interface faces: use cfd_viscous_fluxes, cfd_halo_exchange(VISC), cfd_rk_sweeps");
+  if (b->d.params.viscous) {
+    rc = run_visc(b, Qcur);
+    if (rc) return rc;
+  }
+  return rk_sweeps(b, stage, dt_dev, 0.0, Qn, Qcur, Qout);
+}
+
+int cfd_sync(cfd_block* b) {
+  if (!b) return fail(CFD_ERR_ARG, "null block");
+  HIP_TRY(hipStreamSynchronize(b->stream), "stream synchronize");
+  HIP_TRY(hipGetLastError(), "pending device error");
+  return CFD_OK;
+}
+
+int cfd_check_finite(cfd_block* b, const double* Q, int* ok) {
+  if (!b || !Q || !ok) return fail(CFD_ERR_ARG, "null argument");
+  int flag = 0;
+  HIP_TRY(hipMemsetAsync(b->flag_dev, 0, sizeof(int), b->stream), "memset");
+  HIP_TRY(launch_finite(b->g, Q, b->flag_dev, b->stream), "finite check launch");
+  HIP_TRY(hipMemcpyAsync(&flag, b->flag_dev, sizeof(int), hipMemcpyDeviceToHost, b->stream), "copy flag");
+  HIP_TRY(hipStreamSynchronize(b->stream), "stream synchronize");
+  *ok = flag ? 0 : 1;
+  return flag ? fail(CFD_ERR_NONFINITE, "non-finite value in state") : CFD_OK;
+}
+
+int cfd_dt_cfl(cfd_block* const* blocks, int nb, const double* const* Q, double cfl, double* dt_out) {
+  if (!blocks || nb <= 0 || !Q || !dt_out) return fail(CFD_ERR_ARG, "null argument");
+  if (!(cfl > 0.0)) return fail(CFD_ERR_ARG, "cfl must be positive");
+  cfd_block* b0 = blocks[0];
+  if (!b0) return fail(CFD_ERR_ARG, "null block");
+  HIP_TRY(hipMemsetAsync(b0->red_dev, 0, sizeof(unsigned long long), b0->stream), "memset");
+  for (int n = 0; n < nb; ++n) {
+    cfd_block* b = blocks[n];
+    if (!b || !Q[n]) return fail(CFD_ERR_ARG, "null block or state");
+    if (!b->have_metrics) return fail(CFD_ERR_STATE, "cfd_metrics has not been run on a block");
+    HIP_TRY(launch_dt_max(b->g, Q[n], b->met, b->d.params.gamma, b0->red_dev, b0->stream), "dt launch");
+  }
+  unsigned long long bits = 0;
+  HIP_TRY(hipMemcpyAsync(&bits, b0->red_dev, sizeof bits, hipMemcpyDeviceToHost, b0->stream), "copy dt");
+  HIP_TRY(hipStreamSynchronize(b0->stream), "stream synchronize");
+  double smax;
+  std::memcpy(&smax, &bits, sizeof smax);
+  if (!(smax > 0.0) || !std::isfinite(smax)) return fail(CFD_ERR_NONFINITE, "spectral radius is not positive and finite");
+  *dt_out = cfl / smax;
+  return CFD_OK;
+}
+
+int cfd_profile_enable(cfd_block* b, int enable) {
+  if (!b) return fail(CFD_ERR_ARG, "null block");
+  b->prof.on = enable != 0;
+  return CFD_OK;
+}
+
+int cfd_profile_read(cfd_block* b, const char** names, int64_t* launches, double* ms, int cap, int* n) {
+  if (!b || !n) return fail(CFD_ERR_ARG, "null argument");
+  b->prof.drain();
+  int k = 0;
+  for (const auto& name : b->prof.order) {
+    if (k < cap) {
+      auto& v = b->prof.acc[name];
+      // names are static strings owned by the library
+      const char* stat = nullptr;
+      for (auto s : kSweepNames) if (name == s) stat = s;
+      for (auto s : kSweepRkNames) if (name == s) stat = s;
+      if (!stat) stat = name == "visc_prepass" ? "visc_prepass" : name == "visc_halo" ? "visc_halo" : "other";
+      if (names) names[k] = stat;
+      if (launches) launches[k] = v.first;
+      if (ms) ms[k] = v.second;
+    }
+    ++k;
+  }
+  *n = k;
+  return CFD_OK;
+}
+
+int cfd_profile_reset(cfd_block* b) {
+  if (!b) return fail(CFD_ERR_ARG, "null block");
+  b->prof.drain();
+  b->prof.acc.clear();
+  b->prof.order.clear();
+  return CFD_OK;
+}
+
+}  // extern "C"
+
+// =====================================================================================
+// exchange plans
+// =====================================================================================
+struct cfd_exchange {
+  std::vector<cfd_block*> blocks;
+  CopySeg* q_dev = nullptr;    // Q copies (interfaces + periodic wraps)
+  int nq = 0, maxq = 0;
+  CopySeg* v_dev = nullptr;    // viscous copies (interfaces only)
+  int nv = 0, maxv = 0;
+  BcSeg* bc_dev = nullptr;     // wall / far-field faces
+  int nbc = 0, maxbc = 0;
+  BcSeg* vbc_dev = nullptr;    // unused (viscous ghosts are block-local)
+  int precision = CFD_FP64;
+};
+
+extern "C" {
+
+int cfd_exchange_create(cfd_block* const* blocks, int nb, const cfd_interface* ifc, int nifc, cfd_exchange** out) {
+  if (!out) return fail(CFD_ERR_ARG, "null output handle");
+  *out = nullptr;
+  if (!blocks || nb <= 0 || nb > kMaxBlocks) return fail(CFD_ERR_ARG, "need 1..64 blocks");
+  if (nifc < 0 || (nifc > 0 && !ifc)) return fail(CFD_ERR_ARG, "bad interface list");
+  for (int n = 0; n < nb; ++n)
+    if (!blocks[n]) return fail(CFD_ERR_ARG, "null block");
+  const int prec = blocks[0]->d.precision;
+  for (int n = 0; n < nb; ++n)
+    if (blocks[n]->d.precision != prec) return fail(CFD_ERR_ARG, "all blocks of an exchange share one precision");
+  std::vector<int> used(6 * nb, 0);
+  std::vector<CopySeg> qs, vs;
+  std::vector<BcSeg> bs;
+  for (int n = 0; n < nifc; ++n) {
+    const cfd_interface& f = ifc[n];
+    if (f.block_a < 0 || f.block_a >= nb || f.block_b < 0 || f.block_b >= nb || f.face_a < 0 || f.face_a > 5 ||
+        f.face_b < 0 || f.face_b > 5)
+      return fail(CFD_ERR_ARG, "interface index out of range");
+    if (f.face_a / 2 != f.face_b / 2 || f.face_a == f.face_b)
+      return fail(CFD_ERR_ARG, "interface faces must be opposite faces of one axis");
+    const cfd_block* A = blocks[f.block_a];
+    const cfd_block* B = blocks[f.block_b];
+    if (A->d.bc[f.face_a] != CFD_BC_INTERFACE || B->d.bc[f.face_b] != CFD_BC_INTERFACE)
+      return fail(CFD_ERR_ARG, "interface faces must have kind CFD_BC_INTERFACE");
+    const int ax = f.face_a / 2;
+    for (int t = 1; t <= 2; ++t)
+      if (npts(A->g, (ax + t) % 3) != npts(B->g, (ax + t) % 3)) return fail(CFD_ERR_ARG, "interface face sizes differ");
+    if (used[6 * f.block_a + f.face_a]++ || used[6 * f.block_b + f.face_b]++)
+      return fail(CFD_ERR_ARG, "a face appears in more than one interface");
+    qs.push_back(make_copy(A->g, f.block_a, f.face_a, B->g, f.block_b, f.face_b, 0, 5));
+    qs.push_back(make_copy(B->g, f.block_b, f.face_b, A->g, f.block_a, f.face_a, 0, 5));
+    vs.push_back(make_copy(A->g, f.block_a, f.face_a, B->g, f.block_b, f.face_b, 4 * ax, 4));
+    vs.push_back(make_copy(B->g, f.block_b, f.face_b, A->g, f.block_a, f.face_a, 4 * ax, 4));
+  }
+  for (int n = 0; n < nb; ++n) {
+    const cfd_block* B = blocks[n];
+    for (int f = 0; f < 6; ++f) {
+      const int k = B->d.bc[f];
+      if (k == CFD_BC_INTERFACE && !used[6 * n + f]) return fail(CFD_ERR_ARG, "an interface face has no partner");
+      if (k == CFD_BC_PERIODIC && (f % 2) == 0) {
+        qs.push_back(make_copy(B->g, n, f, B->g, n, f + 1, 0, 5));
+        qs.push_back(make_copy(B->g, n, f + 1, B->g, n, f, 0, 5));
+      }
+      if (k == CFD_BC_WALL || k == CFD_BC_FARFIELD) bs.push_back(make_bc(B->g, n, f, k));
+    }
+  }
+  cfd_exchange* x = new cfd_exchange();
+  x->blocks.assign(blocks, blocks + nb);
+  x->precision = prec;
+  for (auto& s : qs) x->maxq = std::max(x->maxq, s.na * s.nb * kHalo * s.nplanes);
+  for (auto& s : vs) x->maxv = std::max(x->maxv, s.na * s.nb * kHalo * s.nplanes);
+  for (auto& s : bs) x->maxbc = std::max(x->maxbc, s.na * s.nb);
+  if (upload(qs, &x->q_dev) || upload(vs, &x->v_dev) || upload(bs, &x->bc_dev)) {
+    cfd_exchange_destroy(x);
+    return fail(CFD_ERR_HIP, "exchange tables");
+  }
+  x->nq = (int)qs.size();
+  x->nv = (int)vs.size();
+  x->nbc = (int)bs.size();
+  *out = x;
+  return CFD_OK;
+}
+
+int cfd_exchange_destroy(cfd_exchange* x) {
+  if (!x) return CFD_OK;
+  (void)hipFree(x->q_dev);
+  (void)hipFree(x->v_dev);
+  (void)hipFree(x->bc_dev);
+  delete x;
+  return CFD_OK;
+}
+
+int cfd_halo_exchange(cfd_exchange* x, int field_set, void* const* block_bufs, void* hip_stream) {
+  if (!x) return fail(CFD_ERR_ARG, "null exchange");
+  hipStream_t s = hip_stream ? (hipStream_t)hip_stream : x->blocks[0]->stream;
+  const int nb = (int)x->blocks.size();
+  PtrTable t;
+  std::memset(&t, 0, sizeof t);
+  if (field_set == CFD_FIELDS_Q) {
+    if (!block_bufs) return fail(CFD_ERR_ARG, "CFD_FIELDS_Q needs the block buffers");
+    for (int n = 0; n < nb; ++n) {
+      if (!block_bufs[n]) return fail(CFD_ERR_ARG, "null block buffer");
+      t.p[n] = block_bufs[n];
+      t.plane[n] = x->blocks[n]->g.plane;
+    }
+    BcArgs ba;
+    ba.t = t;
+    const cfd_params& P = x->blocks[0]->d.params;
+    ba.gamma = P.gamma;
+    ba.t_wall = P.t_wall;
+    for (int v = 0; v < 5; ++v) ba.qinf[v] = P.qinf[v];
+    Profiler* prof = &x->blocks[0]->prof;
+    ProfScope ps(prof, "halo_q", s);
+    hipError_t e = launch_wall_reset(x->bc_dev, x->nbc, x->maxbc, ba, s);
+    if (e == hipSuccess) e = launch_copy<double>(x->q_dev, x->nq, x->maxq, t, s);
+    if (e == hipSuccess) e = launch_ghost_fill(x->bc_dev, x->nbc, x->maxbc, ba, s);
+    ps.done();
+    return e == hipSuccess ? CFD_OK : hip_fail(e, "halo exchange (Q)");
+  }
+  if (field_set == CFD_FIELDS_VISC) {
+    if (block_bufs) return fail(CFD_ERR_ARG, "CFD_FIELDS_VISC uses library buffers: pass NULL");
+    for (int n = 0; n < nb; ++n) {
+      t.p[n] = x->blocks[n]->vis;
+      t.plane[n] = x->blocks[n]->g.plane;
+    }
+    hipError_t e = x->precision == CFD_FP64 ? launch_copy<double>(x->v_dev, x->nv, x->maxv, t, s)
+                                            : launch_copy<float>(x->v_dev, x->nv, x->maxv, t, s);
+    return e == hipSuccess ? CFD_OK : hip_fail(e, "halo exchange (viscous)");
+  }
+  return fail(CFD_ERR_ARG, "unknown field set");
+}
+
+int cfd_batch_create(cfd_block* const* blocks, int nb, cfd_exchange* x, void* hip_stream, cfd_batch** out) {
+  (void)blocks;
+  (void)nb;
+  (void)x;
+  (void)hip_stream;
+  if (out) *out = nullptr;
+  return fail(CFD_ERR_UNSUPPORTED, "batched form not built yet");
+}
+int cfd_batch_destroy(cfd_batch* bt) {
+  (void)bt;
+  return CFD_OK;
+}
+int cfd_batch_step(cfd_batch* bt, const double* dt_dev, double* const* Qn, double* const* QA, double* const* QB) {
+  (void)bt;
+  (void)dt_dev;
+  (void)Qn;
+  (void)QA;
+  (void)QB;
+  return fail(CFD_ERR_UNSUPPORTED, "batched form not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,95 @@
+// cfd_kernels.hpp -- kernel argument structures and host-side launchers of libcfd.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cfd_device.hpp"
+
+namespace cfd {
+
+constexpr int kMaxBlocks = 64;
+
+// ---- metrics ------------------------------------------------------------------------
+struct MetricArgs {
+  Geom g;
+  const double* xyz;  // caller coordinates, halo 6
+  int64_t cld_i, cld_j, cplane;
+  double* dcoord;     // 9 planes of inner derivatives, coordinate-box layout (tight)
+  double* met;        // 10 planes, state layout
+  int* bad;           // set to 1 if some 1/J <= 0
+};
+hipError_t launch_metrics(const MetricArgs& a, hipStream_t s);
+
+// ---- viscous prepass ----------------------------------------------------------------
+struct ViscArgs {
+  Geom g;
+  const double* q;
+  const double* met;
+  void* vis;  // 12 planes of the compute type
+  Phys ph;
+};
+template <typename R>
+hipError_t launch_visc(const ViscArgs& a, hipStream_t s);
+
+// ---- direction sweep ----------------------------------------------------------------
+enum OutKind { kOutPartial = 0, kOutRhs = 1, kOutRK = 2 };
+struct SweepArgs {
+  Geom g;
+  const double* q;       // state whose RHS is evaluated (Qcur)
+  const double* met;     // 10 metric planes
+  const void* vis;       // 12 viscous-flux planes (compute type)
+  const void* rt_in;     // partial sums of earlier directions (compute type) or null
+  void* rt_out;          // partial sums out (kOutPartial)
+  double* out;           // R (kOutRhs) or Qout (kOutRK)
+  const double* qn;      // RK base state (kOutRK)
+  const double* dt_dev;  // device time step or null (then dt)
+  double dt;
+  double ca, cb, cc;     // Qout = ca Qn + cb Q + cc dt J Rtilde
+  Phys ph;
+  int do_inv, do_vis, has_prev, out_kind;
+  int tiles_c1;          // filled by the launcher
+};
+template <typename R>
+hipError_t launch_sweep(int dir, SweepArgs a, hipStream_t s);
+
+// ---- halo copies and boundary fills -------------------------------------------------
+struct CopySeg {
+  int32_t dst, src;          // block indices
+  int32_t na, nb;            // tangential extents
+  int32_t plane0, nplanes;   // planes copied
+  int64_t dst_off, src_off;  // element offsets of (a=0, b=0, layer 0)
+  int64_t dst_sa, dst_sb, dst_sl;
+  int64_t src_sa, src_sb, src_sl;
+};
+struct PtrTable {
+  void* p[kMaxBlocks];
+  int64_t plane[kMaxBlocks];
+};
+template <typename T>
+hipError_t launch_copy(const CopySeg* segs_dev, int nseg, int max_elems, const PtrTable& t, hipStream_t s);
+
+struct BcSeg {
+  int32_t blk, kind;  // kind: CFD_BC_WALL or CFD_BC_FARFIELD
+  int32_t na, nb;
+  int64_t wall_off;   // element offset of the boundary node (a=0, b=0)
+  int64_t sa, sb;     // tangential strides
+  int64_t sout;       // outward step along the face normal
+  int32_t axis;
+};
+struct BcArgs {
+  PtrTable t;
+  double gamma, t_wall;
+  double qinf[5];
+};
+hipError_t launch_wall_reset(const BcSeg* segs_dev, int nseg, int max_elems, const BcArgs& a, hipStream_t s);
+hipError_t launch_ghost_fill(const BcSeg* segs_dev, int nseg, int max_elems, const BcArgs& a, hipStream_t s);
+template <typename T>
+hipError_t launch_visc_ghost(const BcSeg* segs_dev, int nseg, int max_elems, const PtrTable& t, hipStream_t s);
+
+// ---- reductions ---------------------------------------------------------------------
+hipError_t launch_dt_max(const Geom& g, const double* q, const double* met, double gamma,
+                         unsigned long long* acc, hipStream_t s);
+hipError_t launch_finite(const Geom& g, const double* q, int* flag, hipStream_t s);
+
+}  // namespace cfd

@@ -1,0 +1,92 @@
+"""CPU-side checks of the C ABI: the library loads, exports every declared entry point,
+the Python structures match the C layout, and argument errors are reported without a GPU."""
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_2006_07964_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cfd.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cfd_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        pytest.fail("libcfd.so is not built (run __graft_entry__.build())")
+    return B.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_function():
+    names = declared_functions()
+    missing = [n for n in names if not hasattr(B, n)]
+    assert not missing, missing
+
+
+def test_struct_layout_matches_header():
+    src = r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "cfd.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(cfd_params), sizeof(cfd_block_desc), sizeof(cfd_interface),
+         offsetof(cfd_block_desc, ld_i), offsetof(cfd_block_desc, precision), offsetof(cfd_block_desc, params),
+         offsetof(cfd_params, qinf));
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(c, "w").write(src)
+        subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), "-o", exe, c])
+        vals = [int(v) for v in subprocess.check_output([exe]).split()]
+    py = [C.sizeof(B.cfd_params), C.sizeof(B.cfd_block_desc), C.sizeof(B.cfd_interface),
+          B.cfd_block_desc.ld_i.offset, B.cfd_block_desc.precision.offset, B.cfd_block_desc.params.offset,
+          B.cfd_params.qinf.offset]
+    assert vals == py
+
+
+def test_argument_errors_without_gpu(lib):
+    for bad in (dict(ni=5), dict(ld_i=10), dict(precision=7), dict(weights=3), dict(gamma=1.0),
+                dict(bc=(0, 2, 0, 0, 0, 0))):
+        kw = dict(ni=16, nj=16, nk=16)
+        kw.update(bad)
+        ni = kw.pop("ni")
+        nj = kw.pop("nj")
+        nk = kw.pop("nk")
+        desc = B.make_desc(ni, nj, nk, **kw)
+        with pytest.raises(B.CfdError) as e:
+            B.cfd_block_create(desc)
+        assert e.value.code == B.CFD_ERR_ARG
+        assert B.cfd_last_error()
+    with pytest.raises(B.CfdError) as e:
+        B.cfd_exchange_create([], [])
+    assert e.value.code == B.CFD_ERR_ARG
+    with pytest.raises(B.CfdError):
+        B.cfd_dt_cfl([], [], 0.5)
+
+
+def test_oracle_exports():
+    import oracle as O
+    L = O.lib()
+    for n in ("oracle_metrics", "oracle_rhs", "oracle_rk_stage", "oracle_rk_step", "oracle_dt_cfl",
+              "oracle_exchange", "oracle_rhs_multi", "oracle_rk_step_multi", "oracle_wall_reset", "oracle_bc_fill"):
+        assert hasattr(L, n), n

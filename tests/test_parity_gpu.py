@@ -1,0 +1,240 @@
+"""GPU (libcfd through its C ABI) against the CPU oracle on identical seeded inputs.
+
+Bar: FP64 results within a normwise relative 1e-12 per field (per RK step for states,
+over the whole vector for right-hand sides); the metrics within 1e-13.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2006_07964_amd import binding as B
+from paper_2006_07964_amd import workloads as W
+from tests._gpu import DevBlock, normwise, vector_norm_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    B.lib()
+    yield
+
+
+def _pair(wl, **over):
+    dev = DevBlock(wl, **over)
+    c = O.cfg_from_workload(wl, linear_weights=over.get("weights", B.CFD_WENO_JS) == B.CFD_WENO_LINEAR,
+                            viscous=over.get("viscous", wl.viscous))
+    met = O.metrics(c, wl.blocks[0].xyz)
+    return dev, c, met
+
+
+SIZES = [(32, 32, 32), (23, 17, 11), (7, 9, 8), (40, 7, 19)]
+
+
+def _vortex(ni, nj, nk, seed=1):
+    wl = W.vortex_wavy(ni, nj=nj, nk=nk, seed=seed)
+    return wl
+
+
+@pytest.mark.parametrize("size", SIZES)
+def test_metrics(size):
+    wl = _vortex(*size)
+    dev, c, met = _pair(wl)
+    try:
+        got = dev.metrics_host()
+        for p in range(10):
+            err = np.max(np.abs(got[p] - met[p])) / np.max(np.abs(met[p]))
+            assert err < 1e-13, (p, err)
+    finally:
+        dev.close()
+
+
+@pytest.mark.parametrize("size", SIZES)
+@pytest.mark.parametrize("mask", [B.CFD_DIR_XI | B.CFD_TERM_INV, B.CFD_DIR_ETA | B.CFD_TERM_INV,
+                                  B.CFD_DIR_ZETA | B.CFD_TERM_INV, 7 | B.CFD_TERM_VIS, B.CFD_ALL])
+def test_rhs(size, mask):
+    wl = _vortex(*size)
+    dev, c, met = _pair(wl)
+    try:
+        got = dev.rhs(mask)
+        ref = O.rhs(c, met, wl.blocks[0].q, mask)
+        print(size, mask, vector_norm_err(got, ref), normwise(got, ref))
+        assert vector_norm_err(got, ref) < TOL
+    finally:
+        dev.close()
+
+
+@pytest.mark.parametrize("weights", [B.CFD_WENO_LINEAR, B.CFD_WENO_JS])
+def test_rhs_weights_and_euler(weights):
+    wl = _vortex(24, 20, 16)
+    dev, c, met = _pair(wl, weights=weights, viscous=False)
+    try:
+        got = dev.rhs()
+        ref = O.rhs(c, met, wl.blocks[0].q)
+        assert vector_norm_err(got, ref) < TOL
+    finally:
+        dev.close()
+
+
+def test_free_stream_preservation():
+    wl = _vortex(32, 32, 32)
+    q = W.uniform_state(wl.blocks[0].q.shape[1:], u=0.5, v=-0.2, w=0.1)
+    dev = DevBlock(wl, q=q)
+    try:
+        r = dev.rhs()
+        assert np.max(np.abs(r[:, 3:-3, 3:-3, 3:-3])) < 1e-12
+    finally:
+        dev.close()
+
+
+def test_dt_cfl():
+    wl = _vortex(32, 32, 32)
+    dev, c, met = _pair(wl)
+    try:
+        dt = B.cfd_dt_cfl([dev.h], [dev.q], 0.5)
+        assert dt == pytest.approx(O.dt_cfl(c, met, wl.blocks[0].q, 0.5), rel=1e-14)
+    finally:
+        dev.close()
+
+
+@pytest.mark.parametrize("size", [(32, 32, 32), (23, 17, 11)])
+def test_periodic_halo_exchange(size):
+    import torch
+    wl = _vortex(*size)
+    dev, c, met = _pair(wl)
+    try:
+        q = wl.blocks[0].q.copy()
+        q[:, :3] = np.nan
+        q[:, -3:] = np.nan
+        q[:, :, :3] = np.nan
+        q[:, :, -3:] = np.nan
+        q[:, :, :, :3] = np.nan
+        q[:, :, :, -3:] = np.nan
+        buf = torch.from_numpy(q).cuda()
+        dev.halo(buf)
+        got = buf.cpu().numpy()
+        ref = O.periodic_wrap(c, q)
+        s = slice(3, -3)
+        for face in [(slice(None), s, s, slice(0, 3)), (slice(None), s, s, slice(-3, None)),
+                     (slice(None), s, slice(0, 3), s), (slice(None), s, slice(-3, None), s),
+                     (slice(None), slice(0, 3), s, s), (slice(None), slice(-3, None), s, s)]:
+            np.testing.assert_array_equal(got[face], ref[face])
+    finally:
+        dev.close()
+
+
+def test_rk_ten_steps_c1():
+    """The 32^3 vortex on the wavy grid: 10 RK3 steps, parity after every step."""
+    wl = W.vortex_wavy(32, seed=1)
+    dev, c, met = _pair(wl)
+    try:
+        q = wl.blocks[0].q
+        dt = O.dt_cfl(c, met, q, wl.cfl)
+        qo = q.copy()
+        for step in range(10):
+            dev.step(dt)
+            qo = O.rk_step(c, met, dt, qo)
+            got = dev.q.cpu().numpy()
+            err = normwise(got, qo)
+            print(step, err)
+            assert np.all(err < TOL), (step, err)
+    finally:
+        dev.close()
+
+
+@pytest.mark.parametrize("size", [(23, 17, 11), (7, 7, 7)])
+def test_rk_ragged(size):
+    wl = _vortex(*size)
+    dev, c, met = _pair(wl)
+    try:
+        q = wl.blocks[0].q
+        dt = O.dt_cfl(c, met, q, 0.5)
+        qo = q.copy()
+        for step in range(3):
+            dev.step(dt)
+            qo = O.rk_step(c, met, dt, qo)
+        assert np.all(normwise(dev.q.cpu().numpy(), qo) < TOL)
+    finally:
+        dev.close()
+
+
+def test_rk_stage_dev_dt_matches_host_dt():
+    import torch
+    wl = _vortex(24, 20, 16)
+    dev, c, met = _pair(wl)
+    try:
+        dt = 1.3e-3
+        B.cfd_rk_stage(dev.h, 0, dt, dev.q, dev.q, dev.qa)
+        dt_dev = torch.tensor([dt], dtype=torch.float64, device="cuda")
+        B.cfd_rk_stage_dev(dev.h, 0, dt_dev, dev.q, dev.q, dev.qb)
+        assert torch.equal(dev.qa, dev.qb)
+    finally:
+        dev.close()
+
+
+def test_deterministic():
+    wl = _vortex(24, 20, 16)
+    dev = DevBlock(wl)
+    try:
+        a = dev.rhs().copy()
+        b = dev.rhs()
+        np.testing.assert_array_equal(a, b)
+    finally:
+        dev.close()
+
+
+def test_argument_and_state_errors():
+    import torch
+    wl = _vortex(16, 16, 16)
+    dev = DevBlock(wl)
+    try:
+        with pytest.raises(B.CfdError) as e:
+            B.cfd_rk_stage(dev.h, 1, 1e-3, dev.q, dev.qa, dev.qa)
+        assert e.value.code == B.CFD_ERR_ARG
+        with pytest.raises(B.CfdError) as e:
+            B.cfd_rk_stage(dev.h, 0, 1e-3, dev.q, dev.qa, dev.qb)
+        assert e.value.code == B.CFD_ERR_ARG
+        with pytest.raises(B.CfdError) as e:
+            B.cfd_rk_stage(dev.h, 1, 1e-3, dev.qa, dev.qb, dev.qa)
+        assert e.value.code == B.CFD_ERR_ARG
+        bad = dev.q.clone()
+        bad[0, 10, 10, 10] = float("nan")
+        assert not B.cfd_check_finite(dev.h, bad)
+        assert B.cfd_check_finite(dev.h, dev.q)
+        fresh = B.cfd_block_create(B.desc_from_workload(wl), torch.cuda.current_stream())
+        try:
+            with pytest.raises(B.CfdError) as e:
+                B.cfd_rhs(fresh, dev.q, dev.r)
+            assert e.value.code == B.CFD_ERR_STATE
+            folded = wl.blocks[0].xyz.copy()
+            folded[0] = -folded[0]  # left-handed mapping: 1/J < 0
+            with pytest.raises(B.CfdError) as e:
+                B.cfd_metrics(fresh, torch.from_numpy(folded).cuda(), 16 + 12, 16 + 12)
+            assert e.value.code == B.CFD_ERR_JACOBIAN
+        finally:
+            B.cfd_block_destroy(fresh)
+    finally:
+        dev.close()
+
+
+def test_full_size_taylor_green_first_stage():
+    """256^3 Taylor-Green case at its real size: the first RK stage, every point."""
+    wl = W.taylor_green_wavy(256)
+    dev, c, met = _pair(wl)
+    try:
+        q = wl.blocks[0].q
+        dt = O.dt_cfl(c, met, q, wl.cfl)
+        B.cfd_rk_stage(dev.h, 0, dt, dev.q, dev.q, dev.qa)
+        got = dev.qa.cpu().numpy()
+        r = O.rhs(c, met, q)
+        ref = q + dt * r
+        err = normwise(got, ref)
+        print("256^3 stage-0 normwise error", err)
+        assert np.all(err < TOL)
+    finally:
+        dev.close()
