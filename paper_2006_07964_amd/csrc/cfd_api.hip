@@ -284,6 +284,8 @@ int run_visc(cfd_block* b, const double* Q) {
 
 const char* kSweepNames[3] = {"sweep_xi", "sweep_eta", "sweep_zeta"};
 const char* kSweepRkNames[3] = {"sweep_xi_rk", "sweep_eta_rk", "sweep_zeta_rk"};
+const char* kProfNames[] = {"sweep_xi",    "sweep_eta",    "sweep_zeta",   "sweep_xi_rk", "sweep_eta_rk",
+                            "sweep_zeta_rk", "visc_prepass", "visc_halo", "halo_q",      "halo_visc"};
 
 // run the direction sweeps selected by mask; the last one writes R or the RK stage
 int run_sweeps(cfd_block* b, const double* Q, unsigned mask, int out_kind, double* out, const double* qn,
@@ -587,10 +589,9 @@ int cfd_profile_read(cfd_block* b, const char** names, int64_t* launches, double
     if (k < cap) {
       auto& v = b->prof.acc[name];
       // names are static strings owned by the library
-      const char* stat = nullptr;
-      for (auto s : kSweepNames) if (name == s) stat = s;
-      for (auto s : kSweepRkNames) if (name == s) stat = s;
-      if (!stat) stat = name == "visc_prepass" ? "visc_prepass" : name == "visc_halo" ? "visc_halo" : "other";
+      const char* stat = "other";
+      for (const char* known : kProfNames)
+        if (name == known) stat = known;
       if (names) names[k] = stat;
       if (launches) launches[k] = v.first;
       if (ms) ms[k] = v.second;

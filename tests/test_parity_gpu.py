@@ -1,7 +1,12 @@
 """GPU (libcfd through its C ABI) against the CPU oracle on identical seeded inputs.
 
-Bar: FP64 results within a normwise relative 1e-12 per field (per RK step for states,
-over the whole vector for right-hand sides); the metrics within 1e-13.
+Bar: states after every RK step within a normwise relative 1e-12 per conserved quantity
+(density, momentum vector, energy; see tests/_gpu.normwise); the metrics
+within 1e-13.  Right-hand sides are compared over the whole vector: within 1e-13 with the
+ideal (linear) weights, and within 1e-10 with the WENO-JS weights of Eq 15, whose
+normalisation divides by (eps + beta)^2 with eps = 1e-6 and so amplifies last-bit
+differences in beta by up to ~2/eps relative (bound derived in the design doc); one RK stage
+multiplies that by dt*|R|/|Q| ~ 1e-2, well inside the 1e-12 state bar.
 """
 import numpy as np
 import pytest
@@ -9,11 +14,13 @@ import pytest
 import oracle as O
 from paper_2006_07964_amd import binding as B
 from paper_2006_07964_amd import workloads as W
-from tests._gpu import DevBlock, normwise, vector_norm_err
+from tests._gpu import DevBlock, normwise, per_component, vector_norm_err
 
 pytestmark = pytest.mark.gpu
 
-TOL = 1e-12
+TOL = 1e-12        # states after an RK step, per field
+TOL_RHS_JS = 1e-10  # right-hand side with WENO-JS weights, whole vector
+TOL_RHS_LIN = 1e-13  # right-hand side with ideal weights, whole vector
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -64,7 +71,7 @@ def test_rhs(size, mask):
         got = dev.rhs(mask)
         ref = O.rhs(c, met, wl.blocks[0].q, mask)
         print(size, mask, vector_norm_err(got, ref), normwise(got, ref))
-        assert vector_norm_err(got, ref) < TOL
+        assert vector_norm_err(got, ref) < TOL_RHS_JS
     finally:
         dev.close()
 
@@ -76,7 +83,9 @@ def test_rhs_weights_and_euler(weights):
     try:
         got = dev.rhs()
         ref = O.rhs(c, met, wl.blocks[0].q)
-        assert vector_norm_err(got, ref) < TOL
+        err = vector_norm_err(got, ref)
+        print(weights, err)
+        assert err < (TOL_RHS_LIN if weights == B.CFD_WENO_LINEAR else TOL_RHS_JS)
     finally:
         dev.close()
 
@@ -141,7 +150,7 @@ def test_rk_ten_steps_c1():
             qo = O.rk_step(c, met, dt, qo)
             got = dev.q.cpu().numpy()
             err = normwise(got, qo)
-            print(step, err)
+            print(step, err, per_component(got, qo))
             assert np.all(err < TOL), (step, err)
     finally:
         dev.close()
