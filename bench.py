@@ -8,8 +8,9 @@ updates per second: interior points x 3 stages x steps / wall time of the timed 
 Default workload: 256^3 periodic Taylor-Green vortex, Mach 0.1, Re 1600, on the 2 pi cube
 with a sinusoidal grid perturbation of amplitude 0.05 and seeded velocity noise, FP64.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload tgv256|vortex32]
-                       [--precision fp64|mixed] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+                       [--workload tgv256|vortex32|ogrid24|channel]
+                       [--precision fp64|mixed] [--form single|perblock|batched] [--no-cpu]
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -69,12 +70,25 @@ def load_traffic(kernel: str, workload: str, precision: str):
     return ent.get("bytes_per_launch")
 
 
+WORKLOADS = {
+    "tgv256": "taylor_green_256^3_wavy_2pi_mach0.1_re1600",
+    "vortex32": "isentropic_vortex_32^3_wavy_unit_mach0.5_re1000",
+    "ogrid24": "o_grid_24_uneven_blocks_mach0.2_vortices_wall_farfield",
+    "channel": "channel_512x512x384_tanh2.5_bump0.02_mach0.3",
+}
+
+
 def build_workload(name: str):
     from paper_2006_07964_amd import workloads as W
     if name == "tgv256":
-        return W.taylor_green_wavy(256), "taylor_green_256^3_wavy_2pi_mach0.1_re1600"
+        return W.taylor_green_wavy(256), WORKLOADS[name]
     if name == "vortex32":
-        return W.vortex_wavy(32), "isentropic_vortex_32^3_wavy_unit_mach0.5_re1000"
+        return W.vortex_wavy(32), WORKLOADS[name]
+    if name == "ogrid24":
+        wl = W.o_grid_vortices()
+        return wl, WORKLOADS[name] + f"_{wl.points}pts"
+    if name == "channel":
+        return W.channel(), WORKLOADS[name]
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -123,6 +137,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="tgv256")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--form", default=None, choices=["single", "perblock", "batched"],
+                    help="single-block calls, per-block launches, or the batched graph form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -138,65 +154,122 @@ def main():
     torch.cuda.set_device(0)
     B.lib()
     wl, wname = build_workload(args.workload)
-    blk = wl.blocks[0]
     prec = B.CFD_FP64 if args.precision == "fp64" else B.CFD_MIXED
     stream = torch.cuda.current_stream()
-    h = B.cfd_block_create(B.desc_from_workload(wl, 0, prec), stream)
-    xyz = torch.from_numpy(blk.xyz).cuda()
-    B.cfd_metrics(h, xyz, blk.ni + 12, blk.nj + 12)
-    del xyz
-    x = B.cfd_exchange_create([h], [])
-    q = torch.from_numpy(blk.q).cuda()
-    qa, qb = q.clone(), q.clone()
-    dt = B.cfd_dt_cfl([h], [q], wl.cfl)
+    nb = len(wl.blocks)
+    form = args.form or ("single" if nb == 1 else "perblock")
+    if form == "single" and nb != 1:
+        raise SystemExit("--form single needs a single-block workload")
+    descs, hs, qs, qas, qbs = [], [], [], [], []
+    for bi, blk in enumerate(wl.blocks):
+        # rows padded to 16 doubles and offset so that interior rows start 128-byte lines
+        desc = B.desc_from_workload(wl, bi, prec, ld_i=B.aligned_pitch(blk.ni))
+        h = B.cfd_block_create(desc, stream)
+        xyz = torch.from_numpy(blk.xyz).cuda()
+        B.cfd_metrics(h, xyz, blk.ni + 12, blk.nj + 12)
+        del xyz
+        descs.append(desc)
+        hs.append(h)
+        qs.append(B.upload_state(desc, blk.q))
+        qas.append(B.upload_state(desc, blk.q))
+        qbs.append(B.upload_state(desc, blk.q))
+    x = B.cfd_exchange_create(hs, wl.interfaces)
+    B.cfd_halo_exchange(x, B.CFD_FIELDS_Q, qs)
+    dt = B.cfd_dt_cfl(hs, qs, wl.cfl)
+    dt_dev = torch.tensor([dt], dtype=torch.float64, device="cuda")
+    points = wl.points
+    bt = None
+    if form == "batched":
+        bt = B.cfd_batch_create(hs, x, stream)
+    h = hs[0]
+    q, qa, qb = qs[0], qas[0], qbs[0]
+    blk = wl.blocks[0]
+
+    def stage(st, cur, out):
+        for hb, c in zip(hs, cur):
+            B.cfd_viscous_fluxes(hb, c)
+        B.cfd_halo_exchange(x, B.CFD_FIELDS_VISC, None)
+        for hb, qn, c, o in zip(hs, qs, cur, out):
+            B.cfd_rk_sweeps(hb, st, dt, qn, c, o)
+        B.cfd_halo_exchange(x, B.CFD_FIELDS_Q, out)
 
     def step():
-        B.cfd_rk_stage(h, 0, dt, q, q, qa)
-        B.cfd_halo_exchange(x, B.CFD_FIELDS_Q, [qa])
-        B.cfd_rk_stage(h, 1, dt, q, qa, qb)
-        B.cfd_halo_exchange(x, B.CFD_FIELDS_Q, [qb])
-        B.cfd_rk_stage(h, 2, dt, q, qb, q)
-        B.cfd_halo_exchange(x, B.CFD_FIELDS_Q, [q])
+        if form == "batched":
+            B.cfd_batch_step(bt, dt_dev, qs, qas, qbs)
+        elif form == "perblock":
+            stage(0, qs, qas)
+            stage(1, qas, qbs)
+            stage(2, qbs, qs)
+        else:
+            B.cfd_rk_stage(h, 0, dt, q, q, qa)
+            B.cfd_halo_exchange(x, B.CFD_FIELDS_Q, [qa])
+            B.cfd_rk_stage(h, 1, dt, q, qa, qb)
+            B.cfd_halo_exchange(x, B.CFD_FIELDS_Q, [qb])
+            B.cfd_rk_stage(h, 2, dt, q, qb, q)
+            B.cfd_halo_exchange(x, B.CFD_FIELDS_Q, [q])
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    B.cfd_profile_reset(h)
-    B.cfd_profile_enable(h, True)
+    profiled = form != "batched"  # a captured graph is timed as a whole
+    for hb in hs:
+        B.cfd_profile_reset(hb)
+        B.cfd_profile_enable(hb, profiled)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for n in range(args.steps):
         step()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    B.cfd_profile_enable(h, False)
-    prof = B.cfd_profile_read(h)
-    if not B.cfd_check_finite(h, q):
-        raise SystemExit("non-finite state after the timed steps")
-    updates = blk.points * 3 * args.steps
+    prof = {}
+    for hb in hs:
+        B.cfd_profile_enable(hb, False)
+        for name, (launches, ms) in B.cfd_profile_read(hb).items():
+            l0, m0 = prof.get(name, (0, 0.0))
+            prof[name] = (l0 + launches, m0 + ms)
+    for hb, qb_ in zip(hs, qs):
+        if not B.cfd_check_finite(hb, qb_):
+            raise SystemExit("non-finite state after the timed steps")
+    updates = points * 3 * args.steps
     value = updates / el
 
     alg = ALG_BYTES_FP64 if prec == B.CFD_FP64 else ALG_BYTES_MIXED
+    stage_bytes = sum(alg[n] for n in ("visc_prepass", "sweep_xi", "sweep_eta", "sweep_zeta_rk")) * points
     kernels = {}
     for name, (launches, ms) in prof.items():
         avg_ms = ms / max(launches, 1)
         ent = {"launches": launches, "avg_ms": round(avg_ms, 4), "share": 0.0}
         if name in alg:
-            ent["alg_bytes_per_launch"] = alg[name] * blk.points
-            ent["alg_GBps"] = round(alg[name] * blk.points / (avg_ms * 1e-3) / 1e9, 1)
+            # each block launches every kernel equally often
+            total_bytes = alg[name] * points * launches / nb
+            ent["alg_bytes_per_launch"] = int(total_bytes / launches)
+            ent["alg_GBps"] = round(total_bytes / (ms * 1e-3) / 1e9, 1)
         kernels[name] = ent
     total_ms = sum(v[1] for v in prof.values())
     for name, ent in kernels.items():
         ent["share"] = round(prof[name][1] / total_ms, 3)
-    dom = max((n for n in kernels if n in alg), key=lambda n: prof[n][1])
-    dk = kernels[dom]
-    achieved = dk["alg_GBps"]
-    traffic = load_traffic(dom, args.workload, args.precision)
-    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-                "alg_bytes_per_point": alg[dom], "avg_launch_ms": dk["avg_ms"]}
+    if kernels:
+        dom = max((n for n in kernels if n in alg), key=lambda n: prof[n][1])
+        dk = kernels[dom]
+        achieved = dk["alg_GBps"]
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": load_traffic(dom, args.workload, args.precision), "kernel": dom,
+                    "alg_bytes_per_point": alg[dom], "avg_launch_ms": dk["avg_ms"]}
+    else:  # a captured graph: the whole step against its algorithmic bytes
+        achieved = round(stage_bytes * 3 * args.steps / el / 1e9, 1)
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "whole RK step (graph)",
+                    "alg_bytes_per_point": 3 * stage_bytes // points}
     copy_gbs = copy_bandwidth(torch)
 
+    cfg = {"workload": wname, "blocks": nb, "points": points, "precision": args.precision, "form": form,
+           "cfl": wl.cfl, "dt": dt, "parallelism": "single GPU"}
+    if nb == 1:
+        cfg["grid"] = [blk.ni, blk.nj, blk.nk]
+    if bt is not None:
+        tc, tp = B.cfd_batch_tuning(bt)
+        cfg["tuned_tiles"] = {"cfg": tc, "persistent": tp}
     out = {
         "metric": "grid-point RK3 stage updates/s",
         "value": value,
@@ -210,19 +283,20 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prec == B.CFD_FP64 else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": wname, "grid": [blk.ni, blk.nj, blk.nk], "points": blk.points,
-                   "precision": args.precision, "cfl": wl.cfl, "dt": dt, "parallelism": "single GPU, single block"},
+        "config": cfg,
         "roofline": roofline,
         "kernels": kernels,
         "copy_GBps": round(copy_gbs, 1),
+        # algorithmic bytes of whole stages over the measured time
+        "step_alg_GBps": round(stage_bytes * 3 * args.steps / el / 1e9, 1),
     }
-    # algorithmic bytes of a whole stage over the measured time per stage
-    stage_bytes = sum(alg[n] for n in ("visc_prepass", "sweep_xi", "sweep_eta", "sweep_zeta_rk")) * blk.points
-    out["step_alg_GBps"] = round(stage_bytes * 3 * args.steps / el / 1e9, 1)
-    if not args.no_cpu:
+    if not args.no_cpu and nb == 1:
         out["cpu_baseline"] = cpu_baseline(wl, wname)
+    if bt is not None:
+        B.cfd_batch_destroy(bt)
     B.cfd_exchange_destroy(x)
-    B.cfd_block_destroy(h)
+    for hb in hs:
+        B.cfd_block_destroy(hb)
     print(json.dumps(out), flush=True)
 
 

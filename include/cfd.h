@@ -187,6 +187,13 @@ int cfd_batch_destroy(cfd_batch* bt);
 int cfd_batch_step(cfd_batch* bt, const double* dt_dev, double* const* Qn, double* const* QA,
                    double* const* QB);
 
+/* Tile configuration chosen per sweep direction (cfg[d] indexes the library's tile
+ * shapes, persist[d] = 1 for the persistent schedule).  Before the first step these are
+ * the defaults; the first cfd_batch_step times every candidate and keeps the fastest.   */
+int cfd_batch_tuning(const cfd_batch* bt, int* cfg, int* persist);
+/* Override the tiling (skips the autotuner; the next step re-captures its graph).       */
+int cfd_batch_set_tuning(cfd_batch* bt, const int* cfg, const int* persist);
+
 /* ---- profiling --------------------------------------------------------------------- */
 /* Enable (1) or disable (0) per-launch HIP event timing of the block's kernels.         */
 int cfd_profile_enable(cfd_block* b, int enable);

@@ -87,6 +87,8 @@ def lib():
         "cfd_batch_create": ([C.POINTER(_VP), C.c_int, _VP, _VP, C.POINTER(_VP)], C.c_int),
         "cfd_batch_destroy": ([_VP], C.c_int),
         "cfd_batch_step": ([_VP, _VP, C.POINTER(_VP), C.POINTER(_VP), C.POINTER(_VP)], C.c_int),
+        "cfd_batch_tuning": ([_VP, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
+        "cfd_batch_set_tuning": ([_VP, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
         "cfd_profile_enable": ([_VP, C.c_int], C.c_int),
         "cfd_profile_read": ([_VP, C.POINTER(C.c_char_p), C.POINTER(C.c_int64), _DP, C.c_int, C.POINTER(C.c_int)], C.c_int),
         "cfd_profile_reset": ([_VP], C.c_int),
@@ -239,6 +241,19 @@ def cfd_batch_step(bt: int, dt_dev, qn: Sequence, qa: Sequence, qb: Sequence) ->
     _check(lib().cfd_batch_step(bt, _ptr(dt_dev), _vp_array(qn), _vp_array(qa), _vp_array(qb)))
 
 
+def cfd_batch_tuning(bt: int):
+    cfg = (C.c_int * 3)()
+    per = (C.c_int * 3)()
+    _check(lib().cfd_batch_tuning(bt, cfg, per))
+    return list(cfg), list(per)
+
+
+def cfd_batch_set_tuning(bt: int, cfg, persist) -> None:
+    c = (C.c_int * 3)(*cfg)
+    p = (C.c_int * 3)(*persist)
+    _check(lib().cfd_batch_set_tuning(bt, c, p))
+
+
 def cfd_profile_enable(b: int, on: bool = True) -> None:
     _check(lib().cfd_profile_enable(b, int(on)))
 
@@ -254,6 +269,36 @@ def cfd_profile_read(b: int, cap: int = 64):
 
 def cfd_profile_reset(b: int) -> None:
     _check(lib().cfd_profile_reset(b))
+
+
+# ---- layout helpers ------------------------------------------------------------------------
+def aligned_pitch(n: int) -> int:
+    """Row pitch (elements) with halo 3 rounded up to 16 doubles (one 128-byte line)."""
+    return ((n + 6 + 15) // 16) * 16
+
+
+def state_tensor(desc: "cfd_block_desc", nvar: int = 5, device="cuda"):
+    """Zeroed FP64 device tensor (nvar, nk+6, ld_j, ld_i) in the block's pitched layout, offset
+    so that the first interior point of every row starts a 128-byte line when ld_i is a
+    multiple of 16 (the same alignment libcfd gives its own planes)."""
+    import torch
+    plane = desc.ld_i * desc.ld_j * (desc.nk + 6)
+    flat = torch.zeros(nvar * plane + 64, dtype=torch.float64, device=device)
+    off = (-(flat.data_ptr() // 8 + 3)) % 16  # element offset putting (i=0) on a 128-byte line
+    return flat[off:off + nvar * plane].view(nvar, desc.nk + 6, desc.ld_j, desc.ld_i)
+
+
+def upload_state(desc: "cfd_block_desc", arr, device="cuda"):
+    """Copy a tight host array (nvar, nk+6, nj+6, ni+6) into a new pitched device tensor."""
+    import torch
+    t = state_tensor(desc, arr.shape[0], device)
+    t[:, :, :arr.shape[2], :arr.shape[3]].copy_(torch.from_numpy(arr))
+    return t
+
+
+def download_state(desc: "cfd_block_desc", t):
+    """Tight host copy (nvar, nk+6, nj+6, ni+6) of a pitched device tensor."""
+    return t[:, :, :desc.nj + 6, :desc.ni + 6].cpu().numpy()
 
 
 # ---- descriptor helpers (plain data) -------------------------------------------------------

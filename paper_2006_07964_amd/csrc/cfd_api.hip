@@ -124,6 +124,9 @@ struct cfd_block {
   double* met = nullptr;  // 10 planes FP64
   void* vis = nullptr;    // 12 planes (compute type)
   void* rt = nullptr;     // 5 planes (compute type)
+  void* met_raw = nullptr;  // allocations behind met, vis, rt (see aligned_planes)
+  void* vis_raw = nullptr;
+  void* rt_raw = nullptr;
   size_t esize = 8;       // bytes of the compute type
   bool have_metrics = false;
   int64_t bytes = 0;
@@ -144,6 +147,9 @@ namespace {
 Phys make_phys(const cfd_params& p) {
   Phys ph;
   ph.gamma = p.gamma;
+  ph.gm1 = p.gamma - 1.0;
+  ph.gm1inv = 1.0 / (p.gamma - 1.0);
+  ph.inv2g = 1.0 / (2.0 * p.gamma);
   ph.visc_scale = p.mach / p.reynolds;
   ph.heat_scale = p.mach / (p.reynolds * p.prandtl * (p.gamma - 1.0));
   ph.suth = p.suth;
@@ -213,6 +219,17 @@ BcSeg make_bc(const Geom& G, int blk, int f, int kind) {
   return s;
 }
 
+// Allocate nplanes planes of esize-byte elements.  The base is shifted so that the first
+// interior point of every row, element ((k+3)*ld_j + j+3)*ld_i + 3, starts a 128-byte cache
+// line whenever ld_i*esize is a multiple of 128 (the layout callers are advised to use).
+int aligned_planes(size_t plane, int nplanes, size_t esize, void** raw, void** base) {
+  const size_t pad = (128 - 3 * esize) / esize;
+  if (hipMalloc(raw, (nplanes * plane + pad + 64) * esize) != hipSuccess) return CFD_ERR_ALLOC;
+  *base = static_cast<char*>(*raw) + pad * esize;
+  if (hipMemset(*raw, 0, (nplanes * plane + pad + 64) * esize) != hipSuccess) return CFD_ERR_HIP;
+  return CFD_OK;
+}
+
 template <typename T>
 int upload(const std::vector<T>& v, T** dev) {
   *dev = nullptr;
@@ -227,6 +244,9 @@ int validate_desc(const cfd_block_desc* d) {
   if (!is_real_size(d->ni) || !is_real_size(d->nj) || !is_real_size(d->nk))
     return fail(CFD_ERR_ARG, "ni, nj and nk must each be at least 7");
   if (d->ld_i < d->ni + 6 || d->ld_j < d->nj + 6) return fail(CFD_ERR_ARG, "pitches must satisfy ld_i >= ni+6, ld_j >= nj+6");
+  // kernels address one plane with 32-bit byte offsets
+  if (d->ld_i * d->ld_j * (int64_t)(d->nk + 6) >= ((int64_t)1 << 29))
+    return fail(CFD_ERR_UNSUPPORTED, "a block plane must hold fewer than 2^29 points (split larger grids into blocks)");
   if (d->precision != CFD_FP64 && d->precision != CFD_MIXED) return fail(CFD_ERR_ARG, "unknown precision");
   const cfd_params& p = d->params;
   if (!(p.gamma > 1.0) || !(p.reynolds > 0.0) || !(p.prandtl > 0.0) || !(p.weno_eps > 0.0) || !(p.suth > 0.0))
@@ -379,15 +399,14 @@ int cfd_block_create(const cfd_block_desc* d, void* hip_stream, cfd_block** out)
     cfd_block_destroy(b);
     return fail(code, msg);
   };
-  if (hipMalloc((void**)&b->met, 10 * plane * sizeof(double)) != hipSuccess) return cleanup(CFD_ERR_ALLOC, "metrics allocation");
-  if (hipMalloc(&b->vis, 12 * plane * b->esize) != hipSuccess) return cleanup(CFD_ERR_ALLOC, "viscous scratch allocation");
-  if (hipMalloc(&b->rt, 5 * plane * b->esize) != hipSuccess) return cleanup(CFD_ERR_ALLOC, "partial-sum allocation");
+  void* mbase = nullptr;
+  if (aligned_planes(plane, 10, sizeof(double), &b->met_raw, &mbase)) return cleanup(CFD_ERR_ALLOC, "metrics allocation");
+  b->met = static_cast<double*>(mbase);
+  if (aligned_planes(plane, 12, b->esize, &b->vis_raw, &b->vis)) return cleanup(CFD_ERR_ALLOC, "viscous scratch allocation");
+  if (aligned_planes(plane, 5, b->esize, &b->rt_raw, &b->rt)) return cleanup(CFD_ERR_ALLOC, "partial-sum allocation");
   if (hipMalloc((void**)&b->red_dev, sizeof(unsigned long long)) != hipSuccess ||
       hipMalloc((void**)&b->flag_dev, sizeof(int)) != hipSuccess)
     return cleanup(CFD_ERR_ALLOC, "reduction scratch");
-  if (hipMemset(b->met, 0, 10 * plane * sizeof(double)) != hipSuccess || hipMemset(b->vis, 0, 12 * plane * b->esize) != hipSuccess ||
-      hipMemset(b->rt, 0, 5 * plane * b->esize) != hipSuccess)
-    return cleanup(CFD_ERR_HIP, "scratch clear");
   b->bytes = (int64_t)plane * (10 * 8 + 17 * (int64_t)b->esize);
   // block-local viscous halo work
   std::vector<CopySeg> cs;
@@ -416,9 +435,9 @@ int cfd_block_destroy(cfd_block* b) {
   if (b->stream) (void)hipStreamSynchronize(b->stream);
   else (void)hipDeviceSynchronize();
   b->prof.drain();
-  (void)hipFree(b->met);
-  (void)hipFree(b->vis);
-  (void)hipFree(b->rt);
+  (void)hipFree(b->met_raw);
+  (void)hipFree(b->vis_raw);
+  (void)hipFree(b->rt_raw);
   (void)hipFree(b->red_dev);
   (void)hipFree(b->flag_dev);
   (void)hipFree(b->local_copy_dev);
@@ -623,9 +642,351 @@ struct cfd_exchange {
   int nv = 0, maxv = 0;
   BcSeg* bc_dev = nullptr;     // wall / far-field faces
   int nbc = 0, maxbc = 0;
-  BcSeg* vbc_dev = nullptr;    // unused (viscous ghosts are block-local)
   int precision = CFD_FP64;
+  std::vector<CopySeg> qs_host, vs_host;  // host copies of the segment tables
+  std::vector<BcSeg> bc_host;
 };
+
+
+// =====================================================================================
+// batched multi-block form
+// =====================================================================================
+struct cfd_batch {
+  std::vector<cfd_block*> blocks;
+  cfd_exchange* x = nullptr;
+  hipStream_t stream = nullptr;
+  int precision = CFD_FP64;
+  bool viscous = true;
+  // work lists
+  TileList visc_tl{};
+  TileList sweep_tl[3]{};
+  int cfg[3] = {0, 0, 0};       // tile configuration per direction
+  int persist[3] = {0, 0, 0};   // persistent schedule per direction
+  bool tuned = false;
+  int persist_wgs = 2048;       // workgroups of a persistent launch
+  // combined viscous halo work of all blocks: self-periodic + interface copies, ghosts
+  CopySeg* vcopy_dev = nullptr;
+  int nvcopy = 0, maxvcopy = 0;
+  BcSeg* vbc_dev = nullptr;
+  int nvbc = 0, maxvbc = 0;
+  // argument tables of the captured pointer set: 3 stages x (visc + 3 sweeps)
+  ViscArgs* visc_args_dev = nullptr;    // [3][nb]
+  SweepArgs* sweep_args_dev = nullptr;  // [3][3][nb]
+  std::vector<const void*> key;         // pointers the graph was captured for
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+int batch_destroy(cfd_batch* bt) {
+  if (!bt) return CFD_OK;
+  if (bt->stream) (void)hipStreamSynchronize(bt->stream);
+  if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+  if (bt->graph) (void)hipGraphDestroy(bt->graph);
+  (void)hipFree(bt->vcopy_dev);
+  (void)hipFree(bt->vbc_dev);
+  (void)hipFree(bt->visc_args_dev);
+  (void)hipFree(bt->sweep_args_dev);
+  delete bt;
+  return CFD_OK;
+}
+
+void fill_tiles(cfd_batch* bt) {
+  const int nb = (int)bt->blocks.size();
+  bt->visc_tl.nblk = nb;
+  bt->visc_tl.prefix[0] = 0;
+  for (int b = 0; b < nb; ++b) {
+    int t;
+    visc_tiling(bt->blocks[b]->g, &t);
+    bt->visc_tl.prefix[b + 1] = bt->visc_tl.prefix[b] + t;
+  }
+  for (int d = 0; d < 3; ++d) {
+    TileList& tl = bt->sweep_tl[d];
+    tl.nblk = nb;
+    tl.prefix[0] = 0;
+    for (int b = 0; b < nb; ++b) {
+      const Geom& g = bt->blocks[b]->g;
+      int tc1, td, tlen;
+      sweep_tiling(d, bt->cfg[d], g, &tc1, &td, &tlen);
+      const int n2 = d == 2 ? g.nj : g.nk;
+      tl.prefix[b + 1] = tl.prefix[b] + tc1 * td * n2;
+    }
+  }
+}
+
+int batch_create(cfd_block* const* blocks, int nb, cfd_exchange* x, void* hip_stream, cfd_batch** out) {
+  if (!out) return fail(CFD_ERR_ARG, "null output handle");
+  *out = nullptr;
+  if (!blocks || nb <= 0 || nb > kMaxBlocks || !x) return fail(CFD_ERR_ARG, "need 1..64 blocks and an exchange plan");
+  if ((int)x->blocks.size() != nb) return fail(CFD_ERR_ARG, "exchange plan was made for a different block list");
+  for (int b = 0; b < nb; ++b) {
+    if (!blocks[b] || blocks[b] != x->blocks[b]) return fail(CFD_ERR_ARG, "exchange plan was made for a different block list");
+    if (!blocks[b]->have_metrics) return fail(CFD_ERR_STATE, "cfd_metrics has not been run on every block");
+    if (blocks[b]->d.precision != blocks[0]->d.precision) return fail(CFD_ERR_ARG, "blocks of a batch share one precision");
+    if (blocks[b]->d.params.viscous != blocks[0]->d.params.viscous)
+      return fail(CFD_ERR_ARG, "blocks of a batch are all viscous or all inviscid");
+  }
+  cfd_batch* bt = new cfd_batch();
+  bt->blocks.assign(blocks, blocks + nb);
+  bt->x = x;
+  bt->stream = (hipStream_t)hip_stream;
+  bt->precision = blocks[0]->d.precision;
+  bt->viscous = blocks[0]->d.params.viscous != 0;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, blocks[0]->device) == hipSuccess) bt->persist_wgs = prop.multiProcessorCount * 8;
+  // viscous halo work of the whole batch
+  std::vector<CopySeg> vc = x->vs_host;
+  std::vector<BcSeg> vb;
+  for (int b = 0; b < nb; ++b) {
+    const cfd_block* B = blocks[b];
+    for (int ax = 0; ax < 3; ++ax)
+      if (B->d.bc[2 * ax] == CFD_BC_PERIODIC) {
+        vc.push_back(make_copy(B->g, b, 2 * ax, B->g, b, 2 * ax + 1, 4 * ax, 4));
+        vc.push_back(make_copy(B->g, b, 2 * ax + 1, B->g, b, 2 * ax, 4 * ax, 4));
+      }
+    for (int f = 0; f < 6; ++f)
+      if (B->d.bc[f] == CFD_BC_WALL || B->d.bc[f] == CFD_BC_FARFIELD) vb.push_back(make_bc(B->g, b, f, B->d.bc[f]));
+  }
+  for (auto& c : vc) bt->maxvcopy = std::max(bt->maxvcopy, c.na * c.nb * kHalo * c.nplanes);
+  for (auto& c : vb) bt->maxvbc = std::max(bt->maxvbc, c.na * c.nb);
+  if (upload(vc, &bt->vcopy_dev) || upload(vb, &bt->vbc_dev)) {
+    batch_destroy(bt);
+    return fail(CFD_ERR_HIP, "batch halo tables");
+  }
+  bt->nvcopy = (int)vc.size();
+  bt->nvbc = (int)vb.size();
+  if (hipMalloc((void**)&bt->visc_args_dev, 3 * nb * sizeof(ViscArgs)) != hipSuccess ||
+      hipMalloc((void**)&bt->sweep_args_dev, 9 * nb * sizeof(SweepArgs)) != hipSuccess) {
+    batch_destroy(bt);
+    return fail(CFD_ERR_ALLOC, "batch argument tables");
+  }
+  fill_tiles(bt);
+  *out = bt;
+  return CFD_OK;
+}
+
+// per-block argument tables for stage s reading Qcur[b] and writing Qout[b]
+void build_args(cfd_batch* bt, double* const* Qn, double* const* QA, double* const* QB, std::vector<ViscArgs>& va,
+                std::vector<SweepArgs>& sa) {
+  const int nb = (int)bt->blocks.size();
+  va.assign(3 * nb, ViscArgs{});
+  sa.assign(9 * nb, SweepArgs{});
+  for (int st = 0; st < 3; ++st) {
+    double* const* cur = st == 0 ? Qn : st == 1 ? QA : QB;
+    double* const* outp = st == 0 ? QA : st == 1 ? QB : Qn;
+    for (int b = 0; b < nb; ++b) {
+      cfd_block* B = bt->blocks[b];
+      ViscArgs& v = va[st * nb + b];
+      v.g = B->g;
+      v.q = cur[b];
+      v.met = B->met;
+      v.vis = B->vis;
+      v.ph = make_phys(B->d.params);
+      for (int d = 0; d < 3; ++d) {
+        SweepArgs& a = sa[(st * 3 + d) * nb + b];
+        std::memset(&a, 0, sizeof a);
+        a.g = B->g;
+        a.q = cur[b];
+        a.met = B->met;
+        a.vis = B->vis;
+        a.rt_in = B->rt;
+        a.rt_out = B->rt;
+        a.ph = make_phys(B->d.params);
+        a.do_inv = 1;
+        a.do_vis = bt->viscous;
+        a.has_prev = d > 0;
+        a.out_kind = d == 2 ? kOutRK : kOutPartial;
+        a.out = d == 2 ? outp[b] : nullptr;
+        a.qn = Qn[b];
+        a.ca = kRK[st][0];
+        a.cb = kRK[st][1];
+        a.cc = kRK[st][2];
+        sweep_tiling(d, bt->cfg[d], B->g, &a.tiles_c1, &a.tiles_d, &a.tile_len);
+      }
+    }
+  }
+}
+
+hipError_t launch_batch_sweep(cfd_batch* bt, int st, int d, const SweepArgs* args_dev) {
+  const int nb = (int)bt->blocks.size();
+  const TileList& tl = bt->sweep_tl[d];
+  const int ntiles = tl.prefix[nb];
+  const int nwg = bt->persist[d] ? std::min(ntiles, bt->persist_wgs) : ntiles;
+  const SweepArgs* a = args_dev + (st * 3 + d) * nb;
+  return bt->precision == CFD_FP64 ? launch_sweep_batch<double>(d, bt->cfg[d], bt->persist[d] != 0, a, tl, nwg, bt->stream)
+                                   : launch_sweep_batch<float>(d, bt->cfg[d], bt->persist[d] != 0, a, tl, nwg, bt->stream);
+}
+
+// one RK stage of every block (all launches on bt->stream)
+hipError_t enqueue_stage(cfd_batch* bt, int st, double* const* outp) {
+  const int nb = (int)bt->blocks.size();
+  hipError_t e = hipSuccess;
+  if (bt->viscous) {
+    const ViscArgs* va = bt->visc_args_dev + st * nb;
+    const int nv = bt->visc_tl.prefix[nb];
+    e = bt->precision == CFD_FP64 ? launch_visc_batch<double>(va, bt->visc_tl, nv, bt->stream)
+                                  : launch_visc_batch<float>(va, bt->visc_tl, nv, bt->stream);
+    if (e != hipSuccess) return e;
+    PtrTable t;
+    std::memset(&t, 0, sizeof t);
+    for (int b = 0; b < nb; ++b) {
+      t.p[b] = bt->blocks[b]->vis;
+      t.plane[b] = bt->blocks[b]->g.plane;
+    }
+    e = bt->precision == CFD_FP64 ? launch_copy<double>(bt->vcopy_dev, bt->nvcopy, bt->maxvcopy, t, bt->stream)
+                                  : launch_copy<float>(bt->vcopy_dev, bt->nvcopy, bt->maxvcopy, t, bt->stream);
+    if (e != hipSuccess) return e;
+    e = bt->precision == CFD_FP64 ? launch_visc_ghost<double>(bt->vbc_dev, bt->nvbc, bt->maxvbc, t, bt->stream)
+                                  : launch_visc_ghost<float>(bt->vbc_dev, bt->nvbc, bt->maxvbc, t, bt->stream);
+    if (e != hipSuccess) return e;
+  }
+  for (int d = 0; d < 3 && e == hipSuccess; ++d) e = launch_batch_sweep(bt, st, d, bt->sweep_args_dev);
+  if (e != hipSuccess) return e;
+  // Q halos of every block: wall reset, interface / periodic copies, ghost fills
+  BcArgs ba;
+  std::memset(&ba, 0, sizeof ba);
+  for (int b = 0; b < nb; ++b) {
+    ba.t.p[b] = outp[b];
+    ba.t.plane[b] = bt->blocks[b]->g.plane;
+  }
+  const cfd_params& P = bt->blocks[0]->d.params;
+  ba.gamma = P.gamma;
+  ba.t_wall = P.t_wall;
+  for (int v = 0; v < 5; ++v) ba.qinf[v] = P.qinf[v];
+  cfd_exchange* x = bt->x;
+  e = launch_wall_reset(x->bc_dev, x->nbc, x->maxbc, ba, bt->stream);
+  if (e == hipSuccess) e = launch_copy<double>(x->q_dev, x->nq, x->maxq, ba.t, bt->stream);
+  if (e == hipSuccess) e = launch_ghost_fill(x->bc_dev, x->nbc, x->maxbc, ba, bt->stream);
+  return e;
+}
+
+int upload_args(cfd_batch* bt, double* const* Qn, double* const* QA, double* const* QB, const double* dt_dev) {
+  std::vector<ViscArgs> va;
+  std::vector<SweepArgs> sa;
+  build_args(bt, Qn, QA, QB, va, sa);
+  for (auto& a : sa) a.dt_dev = dt_dev;
+  HIP_TRY(hipMemcpy(bt->visc_args_dev, va.data(), va.size() * sizeof(ViscArgs), hipMemcpyHostToDevice), "upload args");
+  HIP_TRY(hipMemcpy(bt->sweep_args_dev, sa.data(), sa.size() * sizeof(SweepArgs), hipMemcpyHostToDevice), "upload args");
+  return CFD_OK;
+}
+
+// Autotuner: time every (tile configuration, schedule) candidate of each direction's
+// batched sweep on the current state (stage 0 arguments; the RK sweep writes QA, which is
+// scratch at this point) and keep the fastest.
+int autotune(cfd_batch* bt, double* const* Qn, double* const* QA, double* const* QB, const double* dt_dev) {
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0), "event");
+  HIP_TRY(hipEventCreate(&e1), "event");
+  int rc = CFD_OK;
+  if (bt->viscous) {  // the sweeps read the viscous-flux planes of the state being tuned on
+    if ((rc = upload_args(bt, Qn, QA, QB, dt_dev)) != CFD_OK) return rc;
+    const int nb = (int)bt->blocks.size();
+    hipError_t e = bt->precision == CFD_FP64
+                       ? launch_visc_batch<double>(bt->visc_args_dev, bt->visc_tl, bt->visc_tl.prefix[nb], bt->stream)
+                       : launch_visc_batch<float>(bt->visc_args_dev, bt->visc_tl, bt->visc_tl.prefix[nb], bt->stream);
+    if (e != hipSuccess) rc = hip_fail(e, "tuning prepass");
+  }
+  for (int d = 0; d < 3 && rc == CFD_OK; ++d) {
+    float best = 1e30f;
+    int best_cfg = 0, best_p = 0;
+    for (int c = 0; c < kTileCfgs && rc == CFD_OK; ++c)
+      for (int p = 0; p < 2 && rc == CFD_OK; ++p) {
+        bt->cfg[d] = c;
+        bt->persist[d] = p;
+        fill_tiles(bt);
+        if ((rc = upload_args(bt, Qn, QA, QB, dt_dev)) != CFD_OK) break;
+        float ms = 0.f, total = 0.f;
+        for (int rep = 0; rep < 3 && rc == CFD_OK; ++rep) {
+          hipError_t e = hipEventRecord(e0, bt->stream);
+          if (e == hipSuccess) e = launch_batch_sweep(bt, 0, d, bt->sweep_args_dev);
+          if (e == hipSuccess) e = hipEventRecord(e1, bt->stream);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (e != hipSuccess) rc = hip_fail(e, "tuning launch");
+          if (rep > 0) total += ms;  // first launch warms caches and code
+        }
+        if (rc == CFD_OK && total < best) {
+          best = total;
+          best_cfg = c;
+          best_p = p;
+        }
+      }
+    bt->cfg[d] = best_cfg;
+    bt->persist[d] = best_p;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  fill_tiles(bt);
+  bt->tuned = rc == CFD_OK;
+  return rc;
+}
+
+int batch_step(cfd_batch* bt, const double* dt_dev, double* const* Qn, double* const* QA, double* const* QB) {
+  if (!bt || !dt_dev || !Qn || !QA || !QB) return fail(CFD_ERR_ARG, "null argument");
+  const int nb = (int)bt->blocks.size();
+  std::vector<const void*> key;
+  key.push_back(dt_dev);
+  for (int b = 0; b < nb; ++b) {
+    if (!Qn[b] || !QA[b] || !QB[b]) return fail(CFD_ERR_ARG, "null state pointer");
+    if (Qn[b] == QA[b] || Qn[b] == QB[b] || QA[b] == QB[b]) return fail(CFD_ERR_ARG, "Qn, QA and QB must be distinct");
+    key.push_back(Qn[b]);
+    key.push_back(QA[b]);
+    key.push_back(QB[b]);
+  }
+  if (key != bt->key || !bt->exec) {
+    if (!bt->tuned) {
+      int rc = autotune(bt, Qn, QA, QB, dt_dev);
+      if (rc) return rc;
+    }
+    int rc = upload_args(bt, Qn, QA, QB, dt_dev);
+    if (rc) return rc;
+    if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+    if (bt->graph) (void)hipGraphDestroy(bt->graph);
+    bt->exec = nullptr;
+    bt->graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(bt->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    hipError_t e = hipSuccess;
+    for (int st = 0; st < 3 && e == hipSuccess; ++st) e = enqueue_stage(bt, st, st == 0 ? QA : st == 1 ? QB : Qn);
+    hipGraph_t g = nullptr;
+    hipError_t ec = hipStreamEndCapture(bt->stream, &g);
+    if (e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return hip_fail(e, "capture of the RK step");
+    }
+    if (ec != hipSuccess) return hip_fail(ec, "end capture");
+    bt->graph = g;
+    HIP_TRY(hipGraphInstantiate(&bt->exec, bt->graph, nullptr, nullptr, 0), "graph instantiate");
+    bt->key = key;
+  }
+  HIP_TRY(hipGraphLaunch(bt->exec, bt->stream), "graph launch");
+  return CFD_OK;
+}
+
+int batch_tuning(const cfd_batch* bt, int* cfg, int* persist) {
+  if (!bt || !cfg || !persist) return fail(CFD_ERR_ARG, "null argument");
+  for (int d = 0; d < 3; ++d) {
+    cfg[d] = bt->cfg[d];
+    persist[d] = bt->persist[d];
+  }
+  return CFD_OK;
+}
+
+int batch_set_tuning(cfd_batch* bt, const int* cfg, const int* persist) {
+  if (!bt || !cfg || !persist) return fail(CFD_ERR_ARG, "null argument");
+  for (int d = 0; d < 3; ++d)
+    if (cfg[d] < 0 || cfg[d] >= kTileCfgs) return fail(CFD_ERR_ARG, "tile configuration out of range");
+  for (int d = 0; d < 3; ++d) {
+    bt->cfg[d] = cfg[d];
+    bt->persist[d] = persist[d] != 0;
+  }
+  fill_tiles(bt);
+  bt->tuned = true;
+  bt->key.clear();  // recapture with the new tiling
+  return CFD_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -688,6 +1049,9 @@ int cfd_exchange_create(cfd_block* const* blocks, int nb, const cfd_interface* i
   x->nq = (int)qs.size();
   x->nv = (int)vs.size();
   x->nbc = (int)bs.size();
+  x->qs_host = qs;
+  x->vs_host = vs;
+  x->bc_host = bs;
   *out = x;
   return CFD_OK;
 }
@@ -742,24 +1106,13 @@ int cfd_halo_exchange(cfd_exchange* x, int field_set, void* const* block_bufs, v
 }
 
 int cfd_batch_create(cfd_block* const* blocks, int nb, cfd_exchange* x, void* hip_stream, cfd_batch** out) {
-  (void)blocks;
-  (void)nb;
-  (void)x;
-  (void)hip_stream;
-  if (out) *out = nullptr;
-  return fail(CFD_ERR_UNSUPPORTED, "batched form not built yet");
+  return batch_create(blocks, nb, x, hip_stream, out);
 }
-int cfd_batch_destroy(cfd_batch* bt) {
-  (void)bt;
-  return CFD_OK;
-}
+int cfd_batch_destroy(cfd_batch* bt) { return batch_destroy(bt); }
 int cfd_batch_step(cfd_batch* bt, const double* dt_dev, double* const* Qn, double* const* QA, double* const* QB) {
-  (void)bt;
-  (void)dt_dev;
-  (void)Qn;
-  (void)QA;
-  (void)QB;
-  return fail(CFD_ERR_UNSUPPORTED, "batched form not built yet");
+  return batch_step(bt, dt_dev, Qn, QA, QB);
 }
+int cfd_batch_tuning(const cfd_batch* bt, int* cfg, int* persist) { return batch_tuning(bt, cfg, persist); }
+int cfd_batch_set_tuning(cfd_batch* bt, const int* cfg, const int* persist) { return batch_set_tuning(bt, cfg, persist); }
 
 }  // extern "C"

@@ -25,15 +25,52 @@ __device__ __forceinline__ int64_t at(const Geom& g, int i, int j, int k) {
   return ((int64_t)(k + kHalo) * g.ld_j + (j + kHalo)) * g.ld_i + (i + kHalo);
 }
 
-// Physical constants of one block, converted to the compute type by the kernels.
+// Physical constants of one block (FP64 on the host side of the kernel arguments).
 struct Phys {
   double gamma;
+  double gm1;         // gamma - 1
+  double gm1inv;      // 1 / (gamma - 1)
+  double inv2g;       // 1 / (2 gamma)
   double visc_scale;  // Ma / Re
   double heat_scale;  // Ma / (Re Pr (gamma - 1))
   double suth;
   double eps;
   int linear;  // ideal WENO weights
 };
+
+// The same constants in the compute type.
+template <typename R>
+struct Gas {
+  R gamma, gm1, gm1inv, inv2g;
+  __device__ __forceinline__ explicit Gas(const Phys& p)
+      : gamma(R(p.gamma)), gm1(R(p.gm1)), gm1inv(R(p.gm1inv)), inv2g(R(p.inv2g)) {}
+};
+
+// ---- reciprocal and reciprocal square root ------------------------------------------
+// Hardware estimate refined by Newton-Raphson steps (r <- r (2 - x r) and
+// y <- y (3 - x y^2) / 2); two steps give full double precision, one step for float.
+__device__ __forceinline__ double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ float rcp(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+__device__ __forceinline__ double rsq(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-x * y, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+__device__ __forceinline__ float rsq(float x) {
+  float y = __builtin_amdgcn_rsqf(x);
+  return fmaf(0.5f * y, fmaf(-x * y, y, 1.0f), y);
+}
 
 // ---- sixth-order central difference (Sec. 2 after Eq 8), unit spacing ---------------
 // g(m) returns the value at offset m in [-3, 3] (the centre is not used).
@@ -45,34 +82,15 @@ __device__ __forceinline__ R d6(F g) {
 // ---- Sutherland viscosity, mu(T) = T^1.5 (1+S)/(T+S) ------------------------------------
 template <typename R>
 __device__ __forceinline__ R viscosity(R T, R suth) {
-  return T * sqrt(T) * (R(1) + suth) / (T + suth);
-}
-
-// ---- primitive state ----------------------------------------------------------------
-template <typename R>
-struct Prim {
-  R rho, rinv, u, v, w, p, c;
-};
-
-template <typename R>
-__device__ __forceinline__ Prim<R> primitive(const R q[5], R gamma) {
-  Prim<R> s;
-  s.rho = q[0];
-  s.rinv = R(1) / q[0];
-  s.u = q[1] * s.rinv;
-  s.v = q[2] * s.rinv;
-  s.w = q[3] * s.rinv;
-  s.p = (gamma - R(1)) * (q[4] - R(0.5) * s.rho * (s.u * s.u + s.v * s.v + s.w * s.w));
-  s.c = sqrt(gamma * s.p * s.rinv);  // c^2 = gamma p / rho = T
-  return s;
+  return T * sqrt(T) * (R(1) + suth) * rcp(T + suth);
 }
 
 // ---- Eq 4: inviscid flux through the hatted metric vector (mx, my, mz) --------------
 template <typename R>
-__device__ __forceinline__ void phys_flux(const R q[5], R mx, R my, R mz, R gamma, R F[5]) {
-  const R rinv = R(1) / q[0];
+__device__ __forceinline__ void phys_flux(const R q[5], R mx, R my, R mz, const Gas<R>& G, R F[5]) {
+  const R rinv = rcp(q[0]);
   const R u = q[1] * rinv, v = q[2] * rinv, w = q[3] * rinv;
-  const R p = (gamma - R(1)) * (q[4] - R(0.5) * (q[1] * u + q[2] * v + q[3] * w));
+  const R p = G.gm1 * (q[4] - R(0.5) * (q[1] * u + q[2] * v + q[3] * w));
   const R U = mx * u + my * v + mz * w;
   F[0] = q[0] * U;
   F[1] = q[1] * U + mx * p;
@@ -82,33 +100,37 @@ __device__ __forceinline__ void phys_flux(const R q[5], R mx, R my, R mz, R gamm
 }
 
 // ---- Steger-Warming split flux of one sign (SIGN = +1 or -1) -------------------------
-// lambda_{1,2,3} = |m| theta, lambda_{4,5} = |m| (theta +- c), lambda^{+-} = (lambda +- |lambda|)/2,
+// With |m| the metric magnitude, k = m/|m| and theta = k.u:
+// lambda_{1,2,3} = |m| theta = m.u, lambda_{4,5} = |m| (theta +- c),
+// lambda^{+-} = (lambda +- |lambda|)/2 and
 // F = rho/(2 gamma) [2 (gamma-1) l1 (1,u,v,w,|u|^2/2) + l4 (1, u + c k, H + c theta)
 //                    + l5 (1, u - c k, H - c theta)].
 template <int SIGN, typename R>
-__device__ __forceinline__ void sw_flux(const R q[5], R mx, R my, R mz, R gamma, R F[5]) {
-  const R rinv = R(1) / q[0];
+__device__ __forceinline__ void sw_flux(const R q[5], R mx, R my, R mz, const Gas<R>& G, R F[5]) {
+  const R rinv = rcp(q[0]);
   const R u = q[1] * rinv, v = q[2] * rinv, w = q[3] * rinv;
   const R ke = R(0.5) * (u * u + v * v + w * w);
-  const R p = (gamma - R(1)) * (q[4] - q[0] * ke);
-  const R c = sqrt(gamma * p * rinv);
-  const R mag = sqrt(mx * mx + my * my + mz * mz);
-  const R minv = R(1) / mag;
-  const R kx = mx * minv, ky = my * minv, kz = mz * minv;
-  const R theta = kx * u + ky * v + kz * w;
+  const R p = G.gm1 * (q[4] - q[0] * ke);
+  const R c2 = G.gamma * p * rinv;
+  const R c = c2 * rsq(c2);
+  const R m2 = mx * mx + my * my + mz * mz;
+  const R minv = rsq(m2);
+  const R mag = m2 * minv;
+  const R mu = mx * u + my * v + mz * w;  // |m| theta
   const R H = (q[4] + p) * rinv;
-  const R l1 = mag * theta, l4 = mag * (theta + c), l5 = mag * (theta - c);
+  const R l1 = mu, l4 = mu + mag * c, l5 = mu - mag * c;
   const R a1 = R(0.5) * (l1 + R(SIGN) * fabs(l1));
   const R a4 = R(0.5) * (l4 + R(SIGN) * fabs(l4));
   const R a5 = R(0.5) * (l5 + R(SIGN) * fabs(l5));
-  const R f = q[0] / (R(2) * gamma);
-  const R e1 = R(2) * (gamma - R(1)) * a1;
-  const R s45 = a4 + a5, d45 = (a4 - a5) * c;
+  const R f = q[0] * G.inv2g;
+  const R e1 = R(2) * G.gm1 * a1;
+  const R s45 = a4 + a5;
+  const R d45 = (a4 - a5) * c * minv;  // multiplies m (= |m| k)
   F[0] = f * (e1 + s45);
-  F[1] = f * (e1 * u + s45 * u + d45 * kx);
-  F[2] = f * (e1 * v + s45 * v + d45 * ky);
-  F[3] = f * (e1 * w + s45 * w + d45 * kz);
-  F[4] = f * (e1 * ke + s45 * H + d45 * theta);
+  F[1] = f * ((e1 + s45) * u + d45 * mx);
+  F[2] = f * ((e1 + s45) * v + d45 * my);
+  F[3] = f * ((e1 + s45) * w + d45 * mz);
+  F[4] = f * (e1 * ke + s45 * H + d45 * mu);
 }
 
 // ---- characteristic basis at a node (Pulliam-Chaussee right eigenvectors) ------------
@@ -117,77 +139,88 @@ __device__ __forceinline__ void sw_flux(const R q[5], R mx, R my, R mz, R gamma,
 // for theta +- c; L = R^-1 = R_W^-1 M^-1 in closed form.
 template <typename R>
 struct Basis {
-  R kx, ky, kz;
-  R rho, rinv, u, v, w, ke, gm1;
-  R c2inv;   // 1 / c^2
-  R rcinv;   // 1 / (rho c)
-  R a;       // rho / (sqrt2 c)
-  R b;       // rho c / sqrt2
-  R gm1inv;  // 1 / (gamma - 1)
+  R kx, ky, kz;     // unit direction
+  R rkx, rky, rkz;  // k / rho          (projection of velocity differences)
+  R skx, sky, skz;  // k / (sqrt2 rho)  (acoustic projection)
+  R u, v, w, ke;
+  R gc2;            // (gamma-1) / c^2
+  R gpr;            // (gamma-1) / (sqrt2 rho c)
+  R rho, a, b;      // rho, rho / (sqrt2 c), rho c / sqrt2
+  R kr1, kr2, kr3;  // rho k (back-projection)
 };
 
 template <typename R>
-__device__ __forceinline__ Basis<R> make_basis(const R q[5], R mx, R my, R mz, R gamma) {
+__device__ __forceinline__ Basis<R> make_basis(const R q[5], R mx, R my, R mz, const Gas<R>& G) {
   Basis<R> B;
-  const R minv = R(1) / sqrt(mx * mx + my * my + mz * mz);
+  const R minv = rsq(mx * mx + my * my + mz * mz);
   B.kx = mx * minv;
   B.ky = my * minv;
   B.kz = mz * minv;
   B.rho = q[0];
-  B.rinv = R(1) / q[0];
-  B.u = q[1] * B.rinv;
-  B.v = q[2] * B.rinv;
-  B.w = q[3] * B.rinv;
+  const R rinv = rcp(q[0]);
+  B.u = q[1] * rinv;
+  B.v = q[2] * rinv;
+  B.w = q[3] * rinv;
   B.ke = R(0.5) * (B.u * B.u + B.v * B.v + B.w * B.w);
-  B.gm1 = gamma - R(1);
-  const R p = B.gm1 * (q[4] - B.rho * B.ke);
-  const R c2 = gamma * p * B.rinv;
-  const R c = sqrt(c2);
-  B.c2inv = R(1) / c2;
-  B.rcinv = R(1) / (B.rho * c);
+  const R p = G.gm1 * (q[4] - B.rho * B.ke);
+  const R c2 = G.gamma * p * rinv;
+  const R cinv = rsq(c2);
+  const R c = c2 * cinv;
   const R s2 = R(0.70710678118654752440);  // 1/sqrt2
-  B.a = B.rho * s2 / c;
+  B.rkx = B.kx * rinv;
+  B.rky = B.ky * rinv;
+  B.rkz = B.kz * rinv;
+  B.skx = B.rkx * s2;
+  B.sky = B.rky * s2;
+  B.skz = B.rkz * s2;
+  B.gc2 = G.gm1 * cinv * cinv;
+  B.gpr = G.gm1 * rinv * cinv * s2;
+  B.a = B.rho * s2 * cinv;
   B.b = B.rho * c * s2;
-  B.gm1inv = R(1) / B.gm1;
+  B.kr1 = B.rho * B.kx;
+  B.kr2 = B.rho * B.ky;
+  B.kr3 = B.rho * B.kz;
   return B;
 }
 
-// V = L Q' for a conserved vector Q' (characteristic projection).
+// V = L Q' for a conserved vector Q' (characteristic projection).  With
+// y = (Q'_1 - u Q'_0, Q'_2 - v Q'_0, Q'_3 - w Q'_0) (rho times the velocity perturbation)
+// and P = (gamma-1) times the pressure perturbation:
+//   V_{0..2} = k (Q'_0 - P/c^2) + (y x k)/rho,  V_{3,4} = (P/(rho c) +- k.y/rho)/sqrt2.
 template <typename R>
-__device__ __forceinline__ void project(const Basis<R>& B, const R qp[5], R V[5]) {
-  const R yr = qp[0];
-  const R yu = (qp[1] - B.u * qp[0]) * B.rinv;
-  const R yv = (qp[2] - B.v * qp[0]) * B.rinv;
-  const R yw = (qp[3] - B.w * qp[0]) * B.rinv;
-  const R yp = B.gm1 * (B.ke * qp[0] - B.u * qp[1] - B.v * qp[2] - B.w * qp[3] + qp[4]);
-  const R s = yr - yp * B.c2inv;
-  V[0] = B.kx * s + (yv * B.kz - yw * B.ky);
-  V[1] = B.ky * s + (yw * B.kx - yu * B.kz);
-  V[2] = B.kz * s + (yu * B.ky - yv * B.kx);
-  const R kd = B.kx * yu + B.ky * yv + B.kz * yw;
-  const R pr = yp * B.rcinv;
-  const R s2 = R(0.70710678118654752440);
-  V[3] = (pr + kd) * s2;
-  V[4] = (pr - kd) * s2;
+__device__ __forceinline__ void project(const Basis<R>& B, const Gas<R>& G, const R qp[5], R V[5]) {
+  (void)G;
+  const R yu = qp[1] - B.u * qp[0];
+  const R yv = qp[2] - B.v * qp[0];
+  const R yw = qp[3] - B.w * qp[0];
+  const R pp = B.ke * qp[0] - B.u * qp[1] - B.v * qp[2] - B.w * qp[3] + qp[4];  // P / (gamma-1)
+  const R s = qp[0] - pp * B.gc2;
+  V[0] = B.kx * s + (yv * B.rkz - yw * B.rky);
+  V[1] = B.ky * s + (yw * B.rkx - yu * B.rkz);
+  V[2] = B.kz * s + (yu * B.rky - yv * B.rkx);
+  const R kd = B.skx * yu + B.sky * yv + B.skz * yw;
+  const R pr = pp * B.gpr;
+  V[3] = pr + kd;
+  V[4] = pr - kd;
 }
 
 // Q' = R v (back to conserved variables).
 template <typename R>
-__device__ __forceinline__ void unproject(const Basis<R>& B, const R V[5], R qp[5]) {
+__device__ __forceinline__ void unproject(const Basis<R>& B, const Gas<R>& G, const R V[5], R qp[5]) {
   const R s2 = R(0.70710678118654752440);
   const R kv = B.kx * V[0] + B.ky * V[1] + B.kz * V[2];
   const R sp = V[3] + V[4];
   const R sm = (V[3] - V[4]) * s2;
   const R yr = kv + B.a * sp;
-  const R yu = (B.ky * V[2] - B.kz * V[1]) + B.kx * sm;
-  const R yv = (B.kz * V[0] - B.kx * V[2]) + B.ky * sm;
-  const R yw = (B.kx * V[1] - B.ky * V[0]) + B.kz * sm;
-  const R yp = B.b * sp;
+  // rho times the velocity components of R v
+  const R yu = B.rho * (B.ky * V[2] - B.kz * V[1]) + B.kr1 * sm;
+  const R yv = B.rho * (B.kz * V[0] - B.kx * V[2]) + B.kr2 * sm;
+  const R yw = B.rho * (B.kx * V[1] - B.ky * V[0]) + B.kr3 * sm;
   qp[0] = yr;
-  qp[1] = B.u * yr + B.rho * yu;
-  qp[2] = B.v * yr + B.rho * yv;
-  qp[3] = B.w * yr + B.rho * yw;
-  qp[4] = B.ke * yr + B.rho * (B.u * yu + B.v * yv + B.w * yw) + yp * B.gm1inv;
+  qp[1] = B.u * yr + yu;
+  qp[2] = B.v * yr + yv;
+  qp[3] = B.w * yr + yw;
+  qp[4] = B.ke * yr + (B.u * yu + B.v * yv + B.w * yw) + (B.b * sp) * G.gm1inv;
 }
 
 // ---- WENO interpolation to both half points from one 5-point stencil ----------------
@@ -197,27 +230,46 @@ __device__ __forceinline__ void unproject(const Basis<R>& B, const R V[5], R qp[
 // the same betas (modified AFWENO, Sec. 4.5.1).
 template <typename R>
 __device__ __forceinline__ void weno_pair(R a, R b, R c, R d, R e, R eps, bool linear, R& vl, R& vr) {
-  const R p0 = R(0.375) * a - R(1.25) * b + R(1.875) * c;
-  const R p1 = R(-0.125) * b + R(0.75) * c + R(0.375) * d;
-  const R p2 = R(0.375) * c + R(0.75) * d - R(0.125) * e;
-  const R m0 = R(-0.125) * a + R(0.75) * b + R(0.375) * c;
-  const R m1 = R(0.375) * b + R(0.75) * c - R(0.125) * d;
-  const R m2 = R(1.875) * c - R(1.25) * d + R(0.375) * e;
+  // quadratic interpolants of Eq 14 at i+1/2 (p) and their mirror images at i-1/2 (m),
+  // pre-multiplied by their ideal weights (1/16, 5/8, 5/16) and (5/16, 5/8, 1/16)
+  const R p0 = R(3.0 / 128.0) * a - R(5.0 / 64.0) * b + R(15.0 / 128.0) * c;
+  const R p1 = R(-5.0 / 64.0) * b + R(15.0 / 32.0) * c + R(15.0 / 64.0) * d;
+  const R p2 = R(15.0 / 128.0) * c + R(15.0 / 64.0) * d - R(5.0 / 128.0) * e;
+  const R m0 = R(-5.0 / 128.0) * a + R(15.0 / 64.0) * b + R(15.0 / 128.0) * c;
+  const R m1 = R(15.0 / 64.0) * b + R(15.0 / 32.0) * c - R(5.0 / 64.0) * d;
+  const R m2 = R(15.0 / 128.0) * c - R(5.0 / 64.0) * d + R(3.0 / 128.0) * e;
   if (linear) {
-    vl = R(0.0625) * p0 + R(0.625) * p1 + R(0.3125) * p2;
-    vr = R(0.3125) * m0 + R(0.625) * m1 + R(0.0625) * m2;
+    vl = p0 + p1 + p2;
+    vr = m0 + m1 + m2;
     return;
   }
-  const R third = R(1.0 / 3.0);
-  const R b0 = (R(4) * a * a - R(19) * a * b + R(25) * b * b + R(11) * a * c - R(31) * b * c + R(10) * c * c) * third;
-  const R b1 = (R(4) * b * b - R(13) * b * c + R(13) * c * c + R(5) * b * d - R(13) * c * d + R(4) * d * d) * third;
-  const R b2 = (R(10) * c * c - R(31) * c * d + R(25) * d * d + R(11) * c * e - R(19) * d * e + R(4) * e * e) * third;
-  const R t0 = eps + b0, t1 = eps + b1, t2 = eps + b2;
-  const R r0 = R(1) / (t0 * t0), r1 = R(1) / (t1 * t1), r2 = R(1) / (t2 * t2);
-  const R wl0 = R(0.0625) * r0, wl1 = R(0.625) * r1, wl2 = R(0.3125) * r2;
-  const R wr0 = R(0.3125) * r0, wr1 = R(0.625) * r1, wr2 = R(0.0625) * r2;
-  vl = (wl0 * p0 + wl1 * p1 + wl2 * p2) / (wl0 + wl1 + wl2);
-  vr = (wr0 * m0 + wr1 * m1 + wr2 * m2) / (wr0 + wr1 + wr2);
+  // smoothness indicators of Eq 17 written as sums of squares of the second and first
+  // differences (13/12 (.)^2 + 1/4 (.)^2, algebraically identical); the differences cancel
+  // before squaring, so beta carries a relative rounding error instead of one of |v|^2.
+  const R d0 = a - R(2) * b + c, e0 = a - R(4) * b + R(3) * c;
+  const R d1 = b - R(2) * c + d, e1 = b - d;
+  const R d2 = c - R(2) * d + e, e2 = R(3) * c - R(4) * d + e;
+  const R k13 = R(13.0 / 12.0), k14 = R(0.25);
+  const R t0 = eps + (k13 * d0 * d0 + k14 * e0 * e0);
+  const R t1 = eps + (k13 * d1 * d1 + k14 * e1 * e1);
+  const R t2 = eps + (k13 * d2 * d2 + k14 * e2 * e2);
+  // Eq 15 over a common denominator: w_j ~ gamma_j / s_j with s_j = t_j^2 equals
+  // gamma_j * prod_{k != j} s_k up to a common factor, which the normalisation removes.
+  const R s0 = t0 * t0, s1 = t1 * t1, s2 = t2 * t2;
+  const R q0 = s1 * s2, q1 = s0 * s2, q2 = s0 * s1;
+  const R nl = q0 * p0 + q1 * p1 + q2 * p2;
+  const R nr = q0 * m0 + q1 * m1 + q2 * m2;
+  const R dl = R(0.0625) * q0 + R(0.625) * q1 + R(0.3125) * q2;
+  const R dr = R(0.3125) * q0 + R(0.625) * q1 + R(0.0625) * q2;
+  if constexpr (sizeof(R) == 8) {
+    // one reciprocal for both sides (the product stays far inside the double range)
+    const R inv = rcp(dl * dr);
+    vl = nl * dr * inv;
+    vr = nr * dl * inv;
+  } else {
+    vl = nl * rcp(dl);
+    vr = nr * rcp(dr);
+  }
 }
 
 // ---- sixth-order half-point interpolation of node metrics ---------------------------

@@ -9,6 +9,27 @@
 
 namespace cfd {
 
+// Workgroups are handed to the eight XCDs round-robin (id mod 8).  Remap the id so that
+// each XCD walks a contiguous range of logical tiles; with the sweep-direction tile index
+// fastest, tiles that share halo rows run back to back on the same L2.
+__device__ __forceinline__ int xcd_remap(int wg, int nwg) {
+  const int x = wg & 7, local = wg >> 3;
+  const int q = nwg >> 3, r = nwg & 7;
+  return x * q + (x < r ? x : r) + local;
+}
+
+// Persistent schedule: the `total` work items are split into eight contiguous ranges, one
+// per XCD; this workgroup is number *lane_wg of the *nwg_x workgroups on its XCD.
+__device__ __forceinline__ void xcd_range(int total, int* start, int* count, int* lane_wg, int* nwg_x) {
+  const int x = blockIdx.x & 7;
+  const int q = total >> 3, r = total & 7;
+  *start = x * q + (x < r ? x : r);
+  *count = q + (x < r ? 1 : 0);
+  *lane_wg = blockIdx.x >> 3;
+  const int G = gridDim.x;
+  *nwg_x = (G >> 3) + (x < (G & 7) ? 1 : 0);
+}
+
 // =====================================================================================
 // Metrics (Sec. 2, Eqs 7-8), FP64, setup only.
 // =====================================================================================
@@ -97,12 +118,8 @@ hipError_t launch_metrics(const MetricArgs& a, hipStream_t s) {
 // Plane 4*d + (n-1) holds component n = 1..4 of the direction-d flux, divided by J.
 // =====================================================================================
 template <typename R>
-__global__ __launch_bounds__(256) void k_visc(ViscArgs a) {
+__device__ __forceinline__ void visc_point(const ViscArgs& a, int i, int j, int k) {
   const Geom& g = a.g;
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
-  const int k = blockIdx.z;
-  if (i >= g.ni || j >= g.nj) return;
   const int64_t p = at(g, i, j, k);
   const R gamma = R(a.ph.gamma), gm1 = gamma - R(1);
   const int64_t st[3] = {1, g.ld_i, g.ld_i * g.ld_j};
@@ -120,7 +137,7 @@ __global__ __launch_bounds__(256) void k_visc(ViscArgs a) {
       R q[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) q[v] = R(a.q[v * g.plane + pp]);
-      const R rinv = R(1) / q[0];
+      const R rinv = rcp(q[0]);
       const R u = q[1] * rinv, v = q[2] * rinv, w = q[3] * rinv;
       const R T = gamma * gm1 * (q[4] * rinv - R(0.5) * (u * u + v * v + w * w));
       const R f = sgn * wgt;
@@ -144,7 +161,7 @@ __global__ __launch_bounds__(256) void k_visc(ViscArgs a) {
   R q0[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) q0[v] = R(a.q[v * g.plane + p]);
-  const R rinv = R(1) / q0[0];
+  const R rinv = rcp(q0[0]);
   const R u = q0[1] * rinv, v = q0[2] * rinv, w = q0[3] * rinv;
   const R T = gamma * gm1 * (q0[4] * rinv - R(0.5) * (u * u + v * v + w * w));
   const R mu = viscosity(T, R(a.ph.suth));
@@ -171,6 +188,36 @@ __global__ __launch_bounds__(256) void k_visc(ViscArgs a) {
 }
 
 template <typename R>
+__global__ __launch_bounds__(256) void k_visc(ViscArgs a) {
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (i >= a.g.ni || j >= a.g.nj) return;
+  visc_point<R>(a, i, j, blockIdx.z);
+}
+
+// tiles of 64 x 4 points of one k plane, i-tile fastest, then j-tile, then k
+void visc_tiling(const Geom& g, int* tiles) { *tiles = ((g.ni + 63) / 64) * ((g.nj + 3) / 4) * g.nk; }
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_visc_batch(const ViscArgs* args, TileList tl) {
+  const int total = tl.prefix[tl.nblk];
+  int start, count, lane_wg, nwg_x;
+  xcd_range(total, &start, &count, &lane_wg, &nwg_x);
+  int blk = 0;
+  for (int u = lane_wg; u < count; u += nwg_x) {
+    const int t = start + u;
+    while (t >= tl.prefix[blk + 1]) ++blk;
+    const ViscArgs& a = args[blk];
+    const int lt = t - tl.prefix[blk];
+    const int ti = (a.g.ni + 63) / 64, tj = (a.g.nj + 3) / 4;
+    const int i = (lt % ti) * 64 + (threadIdx.x & 63);
+    const int j = ((lt / ti) % tj) * 4 + (threadIdx.x >> 6);
+    const int k = lt / (ti * tj);
+    if (i < a.g.ni && j < a.g.nj) visc_point<R>(a, i, j, k);
+  }
+}
+
+template <typename R>
 hipError_t launch_visc(const ViscArgs& a, hipStream_t s) {
   dim3 grid((a.g.ni + 63) / 64, (a.g.nj + 3) / 4, a.g.nk);
   hipLaunchKernelGGL(k_visc<R>, grid, dim3(256), 0, s, a);
@@ -178,6 +225,14 @@ hipError_t launch_visc(const ViscArgs& a, hipStream_t s) {
 }
 template hipError_t launch_visc<double>(const ViscArgs&, hipStream_t);
 template hipError_t launch_visc<float>(const ViscArgs&, hipStream_t);
+
+template <typename R>
+hipError_t launch_visc_batch(const ViscArgs* args_dev, const TileList& tl, int nwg, hipStream_t s) {
+  hipLaunchKernelGGL(k_visc_batch<R>, dim3(nwg), dim3(256), 0, s, args_dev, tl);
+  return hipGetLastError();
+}
+template hipError_t launch_visc_batch<double>(const ViscArgs*, const TileList&, int, hipStream_t);
+template hipError_t launch_visc_batch<float>(const ViscArgs*, const TileList&, int, hipStream_t);
 
 // =====================================================================================
 // Direction sweep: modified AFWENO inviscid derivative (Sec. 4.5.1, Figs 10-11, Eq 19),
@@ -198,98 +253,115 @@ struct LdsIdx {
   }
 };
 
-template <int DIR, typename R, int TW, int TS>
-__global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
-  constexpr int NW = TS + 2;  // nodes with a WENO evaluation
-  constexpr int NN = TS + 6;  // nodes with a nodal flux
-  constexpr int NH = TS + 1;  // half points
-  __shared__ R sFp[5 * TW * NH];
-  __shared__ R sFm[5 * TW * NH];
-  __shared__ R sFn[5 * TW * NN];
+
+
+template <int TW, int TS>
+struct SweepLds {
+  static constexpr int NH = TS + 1;  // half points
+  static constexpr int NN = TS + 6;  // nodes with a nodal flux
+  static constexpr int NW = TS + 2;  // nodes with a WENO evaluation
+};
+
+// One tile of a direction sweep: t is the logical tile index inside the block (sweep-
+// direction tile fastest, then the cross tile c1, then the cross index c2).
+template <int DIR, typename R, int TW, int TS, int NT>
+__device__ __forceinline__ void sweep_tile(const SweepArgs& a, int t, R* sFp, R* sFm, R* sFn) {
+  constexpr int NH = SweepLds<TW, TS>::NH;
+  constexpr int NN = SweepLds<TW, TS>::NN;
+  constexpr int NW = SweepLds<TW, TS>::NW;
   using L = LdsIdx<DIR, TW>;
 
   const Geom& g = a.g;
   const int nd = DIR == 0 ? g.ni : DIR == 1 ? g.nj : g.nk;
   const int n1 = DIR == 0 ? g.nj : g.ni;
-  const int64_t sd = DIR == 0 ? 1 : DIR == 1 ? g.ld_i : g.ld_i * g.ld_j;
-  const int64_t s1 = DIR == 0 ? g.ld_i : 1;
-  const int64_t s2 = DIR == 2 ? g.ld_i : g.ld_i * g.ld_j;
-  const int tile1 = blockIdx.x % a.tiles_c1;
-  const int tiled = blockIdx.x / a.tiles_c1;
+  // element offsets inside one plane fit in 32 bits (checked on the host); every array
+  // is addressed as a uniform plane base plus a 32-bit per-lane offset
+  const uint32_t sd = DIR == 0 ? 1u : DIR == 1 ? (uint32_t)g.ld_i : (uint32_t)(g.ld_i * g.ld_j);
+  const uint32_t s1 = DIR == 0 ? (uint32_t)g.ld_i : 1u;
+  const uint32_t s2 = DIR == 2 ? (uint32_t)g.ld_i : (uint32_t)(g.ld_i * g.ld_j);
+  const int ts = a.tile_len;  // output nodes per tile along the sweep (<= TS)
+  const int nw = ts + 2;      // WENO nodes
+  const int nn = ts + 6;      // nodal-flux nodes
+  const int tiled = t % a.tiles_d;
+  const int rest = t / a.tiles_d;
+  const int tile1 = rest % a.tiles_c1;
+  const int c2 = rest / a.tiles_c1;
   const int c1_0 = tile1 * TW;
-  const int d0 = tiled * TS;
-  const int64_t origin = at(g, 0, 0, 0) + (int64_t)blockIdx.y * s2;
-  const double* Q = a.q;
-  const double* met = a.met;
+  const int d0 = tiled * ts;
+  // offset of (c1 = 0, c2, n = 0)
+  const uint32_t origin = (uint32_t)at(g, 0, 0, 0) + (uint32_t)c2 * s2;
   const int64_t plane = g.plane;
-  const R gamma = R(a.ph.gamma);
+  const double* Q = a.q;
+  const Gas<R> G(a.ph);
   const R eps = R(a.ph.eps);
   const bool linear = a.ph.linear != 0;
-  const double* mx = met + (3 * DIR + 0) * plane;
-  const double* my = met + (3 * DIR + 1) * plane;
-  const double* mz = met + (3 * DIR + 2) * plane;
+  const double* mx = a.met + (3 * DIR + 0) * plane;
+  const double* my = a.met + (3 * DIR + 1) * plane;
+  const double* mz = a.met + (3 * DIR + 2) * plane;
 
   if (a.do_inv) {
     // ---- nodal fluxes, Eq 4 -----------------------------------------------------------
-    for (int e = threadIdx.x; e < TW * NN; e += 256) {
+    // items are laid out with the compile-time extents NN / NW / TS so that the index
+    // split needs no runtime division; slots beyond the tile's actual length idle
+    for (int e = threadIdx.x; e < TW * NN; e += NT) {
       const int s = DIR == 0 ? e % NN : e / TW;
       const int w = DIR == 0 ? e / NN : e % TW;
       const int n = d0 - 3 + s;
       const int c1 = c1_0 + w;
-      if (c1 >= n1 || n > nd + 2) continue;
-      const int64_t p = origin + c1 * s1 + n * sd;
+      if (s >= nn || c1 >= n1 || n > nd + 2) continue;
+      const uint32_t p = origin + (uint32_t)c1 * s1 + (uint32_t)n * sd;
       R q[5], F[5];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) q[v] = R(Q[v * plane + p]);
-      phys_flux(q, R(mx[p]), R(my[p]), R(mz[p]), gamma, F);
+      for (int v = 0; v < 5; ++v) q[v] = R((Q + v * plane)[p]);
+      phys_flux(q, R(mx[p]), R(my[p]), R(mz[p]), G, F);
 #pragma unroll
       for (int v = 0; v < 5; ++v) sFn[L::f(v, w, s, NN)] = F[v];
     }
     // ---- characteristic WENO pair and split fluxes ------------------------------------
-    for (int e = threadIdx.x; e < TW * NW; e += 256) {
+    for (int e = threadIdx.x; e < TW * NW; e += NT) {
       const int s = DIR == 0 ? e % NW : e / TW;
       const int w = DIR == 0 ? e / NW : e % TW;
       const int n = d0 - 1 + s;
       const int c1 = c1_0 + w;
-      if (c1 >= n1 || n > nd) continue;
-      const bool need_p = s <= TS && n <= nd - 1;  // F+ at n+1/2
+      if (s >= nw || c1 >= n1 || n > nd) continue;
+      const bool need_p = s <= ts && n <= nd - 1;  // F+ at n+1/2
       const bool need_m = s >= 1;                  // F- at n-1/2
       if (!need_p && !need_m) continue;
-      const int64_t p = origin + c1 * s1 + n * sd;
+      const uint32_t p = origin + (uint32_t)c1 * s1 + (uint32_t)n * sd;
       R q0[5];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) q0[v] = R(Q[v * plane + p]);
-      const Basis<R> B = make_basis(q0, R(mx[p]), R(my[p]), R(mz[p]), gamma);
+      for (int v = 0; v < 5; ++v) q0[v] = R((Q + v * plane)[p]);
+      const Basis<R> B = make_basis(q0, R(mx[p]), R(my[p]), R(mz[p]), G);
       R V[5][5];  // V[t][field] at node n + t - 2
 #pragma unroll
-      for (int t = 0; t < 5; ++t) {
+      for (int tt = 0; tt < 5; ++tt) {
         R qq[5];
-        const int64_t pt = p + (t - 2) * sd;
+        const uint32_t pt = p + (uint32_t)(tt - 2) * sd;
 #pragma unroll
-        for (int v = 0; v < 5; ++v) qq[v] = R(Q[v * plane + pt]);
-        project(B, qq, V[t]);
+        for (int v = 0; v < 5; ++v) qq[v] = R((Q + v * plane)[pt]);
+        project(B, G, qq, V[tt]);
       }
       R vl[5], vr[5];
 #pragma unroll
       for (int f = 0; f < 5; ++f) weno_pair(V[0][f], V[1][f], V[2][f], V[3][f], V[4][f], eps, linear, vl[f], vr[f]);
       if (need_p) {
         R ul[5], F[5];
-        unproject(B, vl, ul);
-        const R hx = R(half_metric([&](int m) { return mx[p + m * sd]; }));
-        const R hy = R(half_metric([&](int m) { return my[p + m * sd]; }));
-        const R hz = R(half_metric([&](int m) { return mz[p + m * sd]; }));
-        sw_flux<+1>(ul, hx, hy, hz, gamma, F);
+        unproject(B, G, vl, ul);
+        const R hx = R(half_metric([&](int m) { return mx[p + (uint32_t)m * sd]; }));
+        const R hy = R(half_metric([&](int m) { return my[p + (uint32_t)m * sd]; }));
+        const R hz = R(half_metric([&](int m) { return mz[p + (uint32_t)m * sd]; }));
+        sw_flux<+1>(ul, hx, hy, hz, G, F);
 #pragma unroll
         for (int v = 0; v < 5; ++v) sFp[L::f(v, w, s, NH)] = F[v];
       }
       if (need_m) {
         R ur[5], F[5];
-        unproject(B, vr, ur);
-        const int64_t pm = p - sd;  // half point n-1/2 = (n-1)+1/2
-        const R hx = R(half_metric([&](int m) { return mx[pm + m * sd]; }));
-        const R hy = R(half_metric([&](int m) { return my[pm + m * sd]; }));
-        const R hz = R(half_metric([&](int m) { return mz[pm + m * sd]; }));
-        sw_flux<-1>(ur, hx, hy, hz, gamma, F);
+        unproject(B, G, vr, ur);
+        const uint32_t pm = p - sd;  // half point n-1/2 = (n-1)+1/2
+        const R hx = R(half_metric([&](int m) { return mx[pm + (uint32_t)m * sd]; }));
+        const R hy = R(half_metric([&](int m) { return my[pm + (uint32_t)m * sd]; }));
+        const R hz = R(half_metric([&](int m) { return mz[pm + (uint32_t)m * sd]; }));
+        sw_flux<-1>(ur, hx, hy, hz, G, F);
 #pragma unroll
         for (int v = 0; v < 5; ++v) sFm[L::f(v, w, s - 1, NH)] = F[v];
       }
@@ -298,15 +370,15 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
   }
 
   // ---- assembly per output node ---------------------------------------------------------
-  const R* vis = static_cast<const R*>(a.vis);
+  const R* vis = static_cast<const R*>(a.vis) + (4 * DIR) * plane;
   const R* rin = static_cast<const R*>(a.rt_in);
-  for (int e = threadIdx.x; e < TW * TS; e += 256) {
+  for (int e = threadIdx.x; e < TW * TS; e += NT) {
     const int s = DIR == 0 ? e % TS : e / TW;
     const int w = DIR == 0 ? e / TS : e % TW;
     const int n = d0 + s;
     const int c1 = c1_0 + w;
-    if (c1 >= n1 || n >= nd) continue;
-    const int64_t p = origin + c1 * s1 + n * sd;
+    if (s >= ts || c1 >= n1 || n >= nd) continue;
+    const uint32_t p = origin + (uint32_t)c1 * s1 + (uint32_t)n * sd;
     R r[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) r[v] = R(0);
@@ -324,52 +396,176 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
     if (a.do_vis) {
 #pragma unroll
       for (int v = 1; v < 5; ++v) {
-        const R* vp = vis + (4 * DIR + v - 1) * plane + p;
-        r[v] += d6<R>([&](int m) { return vp[m * sd]; });
+        const R* vp = vis + (v - 1) * plane;
+        r[v] += d6<R>([&](int m) { return vp[p + (uint32_t)m * sd]; });
       }
     }
     if (a.has_prev) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) r[v] += rin[v * plane + p];
+      for (int v = 0; v < 5; ++v) r[v] += (rin + v * plane)[p];
     }
     if (a.out_kind == kOutPartial) {
       R* ro = static_cast<R*>(a.rt_out);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) ro[v * plane + p] = r[v];
+      for (int v = 0; v < 5; ++v) (ro + v * plane)[p] = r[v];
     } else {
-      const double J = met[9 * plane + p];
+      const double J = (a.met + 9 * plane)[p];
       if (a.out_kind == kOutRhs) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) a.out[v * plane + p] = J * double(r[v]);
+        for (int v = 0; v < 5; ++v) (a.out + v * plane)[p] = J * double(r[v]);
       } else {
         const double dt = a.dt_dev ? *a.dt_dev : a.dt;
         const double cdt = a.cc * dt * J;
 #pragma unroll
         for (int v = 0; v < 5; ++v)
-          a.out[v * plane + p] = a.ca * a.qn[v * plane + p] + a.cb * Q[v * plane + p] + cdt * double(r[v]);
+          (a.out + v * plane)[p] = a.ca * (a.qn + v * plane)[p] + a.cb * (Q + v * plane)[p] + cdt * double(r[v]);
       }
     }
   }
 }
 
-template <typename R>
-hipError_t launch_sweep(int dir, SweepArgs a, hipStream_t s) {
-  constexpr int TW = 16, TS = 14;
-  const int nd = dir == 0 ? a.g.ni : dir == 1 ? a.g.nj : a.g.nk;
-  const int n1 = dir == 0 ? a.g.nj : a.g.ni;
-  const int n2 = dir == 2 ? a.g.nj : a.g.nk;
-  a.tiles_c1 = (n1 + TW - 1) / TW;
-  dim3 grid(a.tiles_c1 * ((nd + TS - 1) / TS), n2);
+// LDS of one workgroup for the largest tile configuration in use.
+template <typename R, int TW, int TS>
+struct SweepShared {
+  R Fp[5 * TW * SweepLds<TW, TS>::NH];
+  R Fm[5 * TW * SweepLds<TW, TS>::NH];
+  R Fn[5 * TW * SweepLds<TW, TS>::NN];
+};
+
+// Single block: one workgroup per tile, ids remapped XCD-contiguously.
+template <int DIR, typename R, int TW, int TS, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep(SweepArgs a) {
+  __shared__ SweepShared<R, TW, TS> sh;
+  sweep_tile<DIR, R, TW, TS, NT>(a, xcd_remap(blockIdx.x, gridDim.x), sh.Fp, sh.Fm, sh.Fn);
+}
+
+// Batched blocks: one launch walks a work list covering the tiles of every block
+// (prefix[b] = first tile of block b).  The list is split into eight contiguous ranges, one
+// per XCD.  PERSIST: a fixed grid of workgroups strides through its XCD's range; otherwise
+// one workgroup per tile (ids remapped XCD-contiguously).
+template <int DIR, typename R, int TW, int TS, int NT, bool PERSIST>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_batch(const SweepArgs* args,
+                                                                                            TileList tl) {
+  __shared__ SweepShared<R, TW, TS> sh;
+  const int total = tl.prefix[tl.nblk];
+  if (!PERSIST) {
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    int blk = 0;
+    while (t >= tl.prefix[blk + 1]) ++blk;
+    sweep_tile<DIR, R, TW, TS, NT>(args[blk], t - tl.prefix[blk], sh.Fp, sh.Fm, sh.Fn);
+    return;
+  }
+  int start, count, lane_wg, nwg_x;
+  xcd_range(total, &start, &count, &lane_wg, &nwg_x);
+  int blk = 0;
+  for (int u = lane_wg; u < count; u += nwg_x) {
+    const int t = start + u;
+    while (t >= tl.prefix[blk + 1]) ++blk;  // t only grows, so the scan resumes
+    sweep_tile<DIR, R, TW, TS, NT>(args[blk], t - tl.prefix[blk], sh.Fp, sh.Fm, sh.Fn);
+    __syncthreads();  // the next tile overwrites the LDS this one read
+  }
+}
+
+// tile configurations (lines across x nodes along the sweep x threads)
+template <int CFG>
+struct TileCfg;
+template <>
+struct TileCfg<0> {
+  static constexpr int TW = 16, TS = 30, NT = 512;
+};
+template <>
+struct TileCfg<1> {
+  static constexpr int TW = 32, TS = 14, NT = 512;
+};
+template <>
+struct TileCfg<2> {
+  static constexpr int TW = 16, TS = 14, NT = 256;
+};
+template <>
+struct TileCfg<3> {
+  static constexpr int TW = 8, TS = 62, NT = 512;
+};
+
+void sweep_tiling(int dir, int cfg, const Geom& g, int* tiles_c1, int* tiles_d, int* tile_len) {
+  static const int tw[kTileCfgs] = {TileCfg<0>::TW, TileCfg<1>::TW, TileCfg<2>::TW, TileCfg<3>::TW};
+  static const int tsz[kTileCfgs] = {TileCfg<0>::TS, TileCfg<1>::TS, TileCfg<2>::TS, TileCfg<3>::TS};
+  const int nd = dir == 0 ? g.ni : dir == 1 ? g.nj : g.nk;
+  const int n1 = dir == 0 ? g.nj : g.ni;
+  *tiles_c1 = (n1 + tw[cfg] - 1) / tw[cfg];
+  *tiles_d = (nd + tsz[cfg] - 1) / tsz[cfg];
+  *tile_len = (nd + *tiles_d - 1) / *tiles_d;  // balanced tiles along the sweep
+}
+
+int sweep_threads(int cfg) {
+  static const int nt[kTileCfgs] = {TileCfg<0>::NT, TileCfg<1>::NT, TileCfg<2>::NT, TileCfg<3>::NT};
+  return nt[cfg];
+}
+
+template <typename R, int CFG>
+hipError_t launch_sweep_cfg(int dir, const SweepArgs& a, int64_t nwg, hipStream_t s) {
+  using C = TileCfg<CFG>;
+  dim3 grid((unsigned)nwg);
   if (dir == 0)
-    hipLaunchKernelGGL((k_sweep<0, R, TW, TS>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_sweep<0, R, C::TW, C::TS, C::NT>), grid, dim3(C::NT), 0, s, a);
   else if (dir == 1)
-    hipLaunchKernelGGL((k_sweep<1, R, TW, TS>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_sweep<1, R, C::TW, C::TS, C::NT>), grid, dim3(C::NT), 0, s, a);
   else
-    hipLaunchKernelGGL((k_sweep<2, R, TW, TS>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_sweep<2, R, C::TW, C::TS, C::NT>), grid, dim3(C::NT), 0, s, a);
   return hipGetLastError();
 }
-template hipError_t launch_sweep<double>(int, SweepArgs, hipStream_t);
-template hipError_t launch_sweep<float>(int, SweepArgs, hipStream_t);
+
+template <typename R>
+hipError_t launch_sweep(int dir, SweepArgs a, hipStream_t s, int cfg) {
+  const int n2 = dir == 2 ? a.g.nj : a.g.nk;
+  sweep_tiling(dir, cfg, a.g, &a.tiles_c1, &a.tiles_d, &a.tile_len);
+  const int64_t nwg = (int64_t)a.tiles_c1 * a.tiles_d * n2;
+  if (nwg > 0x7fffffff) return hipErrorInvalidValue;
+  switch (cfg) {
+    case 0: return launch_sweep_cfg<R, 0>(dir, a, nwg, s);
+    case 1: return launch_sweep_cfg<R, 1>(dir, a, nwg, s);
+    case 2: return launch_sweep_cfg<R, 2>(dir, a, nwg, s);
+    case 3: return launch_sweep_cfg<R, 3>(dir, a, nwg, s);
+  }
+  return hipErrorInvalidValue;
+}
+template hipError_t launch_sweep<double>(int, SweepArgs, hipStream_t, int);
+template hipError_t launch_sweep<float>(int, SweepArgs, hipStream_t, int);
+
+template <typename R, int CFG, bool P>
+hipError_t launch_sweep_batch_cfg(int dir, const SweepArgs* args, const TileList& tl, int nwg, hipStream_t s) {
+  using C = TileCfg<CFG>;
+  if (dir == 0)
+    hipLaunchKernelGGL((k_sweep_batch<0, R, C::TW, C::TS, C::NT, P>), dim3(nwg), dim3(C::NT), 0, s, args, tl);
+  else if (dir == 1)
+    hipLaunchKernelGGL((k_sweep_batch<1, R, C::TW, C::TS, C::NT, P>), dim3(nwg), dim3(C::NT), 0, s, args, tl);
+  else
+    hipLaunchKernelGGL((k_sweep_batch<2, R, C::TW, C::TS, C::NT, P>), dim3(nwg), dim3(C::NT), 0, s, args, tl);
+  return hipGetLastError();
+}
+
+// persist: nwg workgroups stride through the list; otherwise nwg must equal the tile count
+template <typename R>
+hipError_t launch_sweep_batch(int dir, int cfg, bool persist, const SweepArgs* args_dev, const TileList& tl, int nwg,
+                              hipStream_t s) {
+  if (persist) {
+    switch (cfg) {
+      case 0: return launch_sweep_batch_cfg<R, 0, true>(dir, args_dev, tl, nwg, s);
+      case 1: return launch_sweep_batch_cfg<R, 1, true>(dir, args_dev, tl, nwg, s);
+      case 2: return launch_sweep_batch_cfg<R, 2, true>(dir, args_dev, tl, nwg, s);
+      case 3: return launch_sweep_batch_cfg<R, 3, true>(dir, args_dev, tl, nwg, s);
+    }
+  } else {
+    switch (cfg) {
+      case 0: return launch_sweep_batch_cfg<R, 0, false>(dir, args_dev, tl, nwg, s);
+      case 1: return launch_sweep_batch_cfg<R, 1, false>(dir, args_dev, tl, nwg, s);
+      case 2: return launch_sweep_batch_cfg<R, 2, false>(dir, args_dev, tl, nwg, s);
+      case 3: return launch_sweep_batch_cfg<R, 3, false>(dir, args_dev, tl, nwg, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+template hipError_t launch_sweep_batch<double>(int, int, bool, const SweepArgs*, const TileList&, int, hipStream_t);
+template hipError_t launch_sweep_batch<float>(int, int, bool, const SweepArgs*, const TileList&, int, hipStream_t);
 
 // =====================================================================================
 // Halo copies across 1-to-1 faces (ghost layer m of the destination face <- interior

@@ -10,6 +10,12 @@ namespace cfd {
 
 constexpr int kMaxBlocks = 64;
 
+// work list of a batched launch: block b owns logical tiles [prefix[b], prefix[b+1])
+struct TileList {
+  int nblk;
+  int prefix[kMaxBlocks + 1];
+};
+
 // ---- metrics ------------------------------------------------------------------------
 struct MetricArgs {
   Geom g;
@@ -31,6 +37,10 @@ struct ViscArgs {
 };
 template <typename R>
 hipError_t launch_visc(const ViscArgs& a, hipStream_t s);
+// batched viscous prepass over the tiles (64 x 4 points of one k plane) of every block
+template <typename R>
+hipError_t launch_visc_batch(const ViscArgs* args_dev, const TileList& tl, int nwg, hipStream_t s);
+void visc_tiling(const Geom& g, int* tiles);
 
 // ---- direction sweep ----------------------------------------------------------------
 enum OutKind { kOutPartial = 0, kOutRhs = 1, kOutRK = 2 };
@@ -48,10 +58,18 @@ struct SweepArgs {
   double ca, cb, cc;     // Qout = ca Qn + cb Q + cc dt J Rtilde
   Phys ph;
   int do_inv, do_vis, has_prev, out_kind;
-  int tiles_c1;          // filled by the launcher
+  int tiles_c1, tiles_d, tile_len;  // filled by the launcher
 };
+constexpr int kTileCfgs = 4;  // sweep tile configurations (see TileCfg in cfd_kernels.hip)
+// tiles of one block for direction dir under configuration cfg
+void sweep_tiling(int dir, int cfg, const Geom& g, int* tiles_c1, int* tiles_d, int* tile_len);
+int sweep_threads(int cfg);
 template <typename R>
-hipError_t launch_sweep(int dir, SweepArgs a, hipStream_t s);
+hipError_t launch_sweep(int dir, SweepArgs a, hipStream_t s, int cfg = 0);
+
+template <typename R>
+hipError_t launch_sweep_batch(int dir, int cfg, bool persist, const SweepArgs* args_dev, const TileList& tl, int nwg,
+                              hipStream_t s);
 
 // ---- halo copies and boundary fills -------------------------------------------------
 struct CopySeg {

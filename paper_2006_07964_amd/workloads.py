@@ -238,3 +238,176 @@ def taylor_green_wavy(n: int = 256, seed: Optional[int] = 2, noise: float = 1e-4
 
     return periodic_workload(f"taylor_green_{n}", xyz, init, mach=0.1, reynolds=1600.0, steps=steps,
                              description=f"{n}^3 Taylor-Green vortex, Mach 0.1, Re 1600, wavy 2pi cube")
+
+
+# ----------------------------------------------------------------------------------------
+# multi-block workloads
+# ----------------------------------------------------------------------------------------
+def _block_index(a, b, c, na, nb):
+    return a + na * (b + nb * c)
+
+
+def structured_interfaces(na, nb, nc, periodic=(True, True, True)):
+    """1-to-1 interfaces of an na x nb x nc arrangement of blocks (i+ of a block to i- of
+    the next, and so on), with wrap-around seams along the periodic directions."""
+    out = []
+    for c in range(nc):
+        for b in range(nb):
+            for a in range(na):
+                me = _block_index(a, b, c, na, nb)
+                if a + 1 < na or (periodic[0] and na > 0):
+                    out.append(Interface(me, 1, _block_index((a + 1) % na, b, c, na, nb), 0))
+                if b + 1 < nb or periodic[1]:
+                    out.append(Interface(me, 3, _block_index(a, (b + 1) % nb, c, na, nb), 2))
+                if c + 1 < nc or periodic[2]:
+                    out.append(Interface(me, 5, _block_index(a, b, (c + 1) % nc, na, nb), 4))
+    return out
+
+
+def draw_block_sizes(seed: int = 4, lo=(48, 64, 32), hi=(192, 128, 96), counts=(4, 3, 2),
+                     total=(36_000_000, 44_000_000), step: int = 8):
+    """Per-axis block extents (multiples of `step` in [lo, hi]) redrawn until the product of
+    the axis totals lies in `total`."""
+    rng = np.random.default_rng(seed)
+    while True:
+        sizes = [list(rng.integers(lo[d] // step, hi[d] // step + 1, size=counts[d]) * step) for d in range(3)]
+        pts = int(np.prod([sum(s) for s in sizes]))
+        if total[0] <= pts <= total[1]:
+            return [[int(v) for v in s] for s in sizes]
+
+
+def split_block(wl_single: Workload, sizes, periodic=(True, True, True)) -> Workload:
+    """Cut a single-block workload into a structured arrangement of blocks with the given
+    per-axis extents; coordinates and states are sliced from the single block (whose
+    halos already hold the periodic images), so the blocks hold identical data."""
+    b = wl_single.blocks[0]
+    assert sum(sizes[0]) == b.ni and sum(sizes[1]) == b.nj and sum(sizes[2]) == b.nk
+    na, nb, nc = len(sizes[0]), len(sizes[1]), len(sizes[2])
+    off = [np.concatenate([[0], np.cumsum(s)]) for s in sizes]
+    blocks = []
+    for c in range(nc):
+        for bb in range(nb):
+            for a in range(na):
+                i0, j0, k0 = int(off[0][a]), int(off[1][bb]), int(off[2][c])
+                ni, nj, nk = sizes[0][a], sizes[1][bb], sizes[2][c]
+                xyz = np.ascontiguousarray(b.xyz[:, k0:k0 + nk + 12, j0:j0 + nj + 12, i0:i0 + ni + 12])
+                q = np.ascontiguousarray(b.q[:, k0:k0 + nk + 6, j0:j0 + nj + 6, i0:i0 + ni + 6])
+                blocks.append(Block(ni, nj, nk, xyz, q, (BC_INTERFACE,) * 6))
+    out = dataclasses.replace(wl_single, name=wl_single.name + f"_{na}x{nb}x{nc}blocks", blocks=blocks,
+                              interfaces=structured_interfaces(na, nb, nc, periodic))
+    return out
+
+
+def o_grid_vortices(seed: int = 4, sizes=None, n_vortices: int = 8, mach: float = 0.2,
+                    reynolds: float = 1000.0, steps: int = 50) -> Workload:
+    """24 uneven blocks (4 around x 3 radial x 2 spanwise) of an O-grid around a cylinder of
+    diameter 1: theta = -2 pi I/NI + 0.05 sin(2 pi z/Lz), r_j = 0.5 + sum_{m<j} 2e-3 * 1.05^min(m,64)
+    (wall spacing 2e-3, stretching ratio 1.05), z = 2 K/NK (Lz = 2), x = r cos theta,
+    y = r sin theta.  No-slip isothermal wall at the cylinder (j = 0), far field at the
+    outer radius, periodic in theta and z.  Uniform Mach 0.2 stream along x plus seeded
+    isentropic vortices (centres 1.5 <= r <= 6, radius 0.3, peak swirl 0.05, random sign)."""
+    if sizes is None:
+        sizes = draw_block_sizes(seed)
+    NI, NJ, NK = (sum(s) for s in sizes)
+    Lz = 2.0
+    m = np.arange(NJ + 8)
+    dr = 2e-3 * 1.05 ** np.minimum(m, 64)
+    r_nodes = 0.5 + np.concatenate([[0.0], np.cumsum(dr)])[:NJ]
+
+    def radius(gj):
+        gj = np.asarray(gj).astype(np.int64)
+        inside = np.clip(gj, 0, NJ - 1)
+        r = r_nodes[inside]
+        below = gj < 0
+        r = np.where(below, 2 * r_nodes[0] - r_nodes[np.clip(-gj, 0, NJ - 1)], r)   # mirrored at the wall
+        above = gj > NJ - 1
+        r = np.where(above, r_nodes[NJ - 1] + (gj - (NJ - 1)) * (r_nodes[NJ - 1] - r_nodes[NJ - 2]), r)
+        return r
+
+    rng = np.random.default_rng(seed + 100)
+    vr = rng.uniform(1.5, 6.0, n_vortices)
+    vt = rng.uniform(0.0, 2 * np.pi, n_vortices)
+    vs = rng.choice([-1.0, 1.0], n_vortices) * 0.05
+    centres = np.stack([vr * np.cos(vt), vr * np.sin(vt)], axis=1)
+
+    def coords(gi, gj, gk):
+        z = Lz * gk / NK
+        th = -2 * np.pi * np.mod(gi, NI) / NI + 0.05 * np.sin(2 * np.pi * z / Lz)
+        r = radius(gj)
+        return r * np.cos(th), r * np.sin(th), z
+
+    def state(x, y, z):
+        u = np.full_like(x, mach)
+        v = np.zeros_like(x)
+        T = np.ones_like(x)
+        for (cx, cy), sw in zip(centres, vs):
+            dx, dy = x - cx, y - cy
+            r2 = (dx * dx + dy * dy) / 0.09
+            g = np.exp(0.5 * (1.0 - r2))
+            u = u - sw * (dy / 0.3) * g
+            v = v + sw * (dx / 0.3) * g
+            T = T - 0.5 * (GAMMA - 1.0) * sw * sw * g * g
+        rho = T ** (1.0 / (GAMMA - 1.0))
+        p = rho ** GAMMA / GAMMA
+        return conserved(rho, u, v, np.zeros_like(u), p)
+
+    off = [np.concatenate([[0], np.cumsum(s)]) for s in sizes]
+    blocks = []
+    na, nb, nc = (len(s) for s in sizes)
+    for c in range(nc):
+        for b in range(nb):
+            for a in range(na):
+                ni, nj, nk = sizes[0][a], sizes[1][b], sizes[2][c]
+                K, J, I = index_grid(ni, nj, nk, CHALO)
+                x, y, z = coords(I + off[0][a], J + off[1][b], K + off[2][c])
+                xyz = np.ascontiguousarray(np.stack([x, y, z]))
+                d = CHALO - HALO
+                q = np.ascontiguousarray(state(x[d:-d, d:-d, d:-d], y[d:-d, d:-d, d:-d], z[d:-d, d:-d, d:-d]))
+                bc = [BC_INTERFACE] * 6
+                if b == 0:
+                    bc[2] = BC_WALL
+                if b == nb - 1:
+                    bc[3] = BC_FARFIELD
+                blocks.append(Block(ni, nj, nk, xyz, q, tuple(bc)))
+    qinf = tuple(float(v) for v in conserved(np.array(1.0), np.array(mach), np.array(0.0), np.array(0.0),
+                                             np.array(1.0 / GAMMA)).ravel())
+    return Workload(f"o_grid_{len(blocks)}blocks", blocks, structured_interfaces(na, nb, nc, (True, False, True)),
+                    mach=mach, reynolds=reynolds, steps=steps, qinf=qinf,
+                    description=f"O-grid, {len(blocks)} uneven blocks, {NI}x{NJ}x{NK} = {NI*NJ*NK} points")
+
+
+def channel(ni: int = 512, nj: int = 512, nk: int = 384, seed: int = 5, mach: float = 0.3,
+            reynolds: float = 16200.0, beta: float = 2.5, bump: float = 0.02, steps: int = 20) -> Workload:
+    """Channel block: x = 2 pi I/ni (periodic), y = tanh(beta eta)/tanh(beta) with
+    eta = -1 + 2 J/(nj-1) (no-slip isothermal walls at J = 0 and nj-1), z = pi K/nk
+    (periodic), plus the bump y += 0.02 (1 - y^2) sin x cos 2z.  Laminar profile
+    u = Ma (1 - y^2), T = 1, p = 1/gamma, plus seeded N(0, (0.05 Ma)^2) (1 - y^2) on u, v, w."""
+    K, J, I = index_grid(ni, nj, nk, CHALO)
+    x = 2 * np.pi * I / ni
+    z = np.pi * K / nk
+
+    def ymap(jj):
+        eta = -1.0 + 2.0 * jj / (nj - 1)
+        return np.tanh(beta * eta) / np.tanh(beta)
+
+    # walls at J = 0 and nj-1; ghost points are odd mirrors of the interior ones
+    jj = np.where(J < 0, -J, np.where(J > nj - 1, 2 * (nj - 1) - J, J))
+    y0 = ymap(jj)
+    y0 = np.where(J < 0, 2 * ymap(0) - y0, np.where(J > nj - 1, 2 * ymap(nj - 1) - y0, y0))
+    yb = y0 + bump * (1 - np.minimum(y0 * y0, 1.0)) * np.sin(x) * np.cos(2 * z)
+    xyz = np.ascontiguousarray(np.stack([x, yb, z]))
+    d = CHALO - HALO
+    xs, ys = x[d:-d, d:-d, d:-d], yb[d:-d, d:-d, d:-d]
+    prof = np.maximum(1.0 - ys * ys, 0.0)
+    rng = np.random.default_rng(seed)
+    sig = 0.05 * mach
+    u = mach * prof + rng.normal(0.0, sig, size=xs.shape) * prof
+    v = rng.normal(0.0, sig, size=xs.shape) * prof
+    w = rng.normal(0.0, sig, size=xs.shape) * prof
+    one = np.ones_like(xs)
+    q = conserved(one, u, v, w, one / GAMMA)
+    q = wrap_halo(q, axes=(0, 2))
+    bc = (BC_PERIODIC, BC_PERIODIC, BC_WALL, BC_WALL, BC_PERIODIC, BC_PERIODIC)
+    blk = Block(ni, nj, nk, xyz, np.ascontiguousarray(q), bc)
+    return Workload(f"channel_{ni}x{nj}x{nk}", [blk], [], mach=mach, reynolds=reynolds, steps=steps,
+                    description=f"{ni}x{nj}x{nk} channel, tanh stretching {beta}, bump {bump}, Mach {mach}")

@@ -34,19 +34,27 @@ def torch_dev(a: np.ndarray):
 class DevBlock:
     """One block on the GPU: coordinates, metrics and three state buffers."""
 
-    def __init__(self, wl, bi=0, precision=B.CFD_FP64, q=None, **over):
+    def __init__(self, wl, bi=0, precision=B.CFD_FP64, q=None, pitched=False, **over):
+        """pitched: rows padded to 16 doubles (and columns by 3) in the aligned layout."""
         import torch
         b = wl.blocks[bi]
         self.wl, self.blk = wl, b
+        if pitched:
+            over.setdefault("ld_i", B.aligned_pitch(b.ni))
+            over.setdefault("ld_j", b.nj + 9)
         self.desc = B.desc_from_workload(wl, bi, precision, **over)
         self.h = B.cfd_block_create(self.desc, torch.cuda.current_stream())
         self.xyz = torch_dev(b.xyz)
         B.cfd_metrics(self.h, self.xyz, b.ni + 12, b.nj + 12)
-        self.q = torch_dev(b.q if q is None else q)
-        self.qa = self.q.clone()
-        self.qb = self.q.clone()
-        self.r = torch.zeros_like(self.q)
+        q0 = b.q if q is None else q
+        self.q = B.upload_state(self.desc, q0)
+        self.qa = B.upload_state(self.desc, q0)
+        self.qb = B.upload_state(self.desc, q0)
+        self.r = B.state_tensor(self.desc, 5)
         self.x = None
+
+    def host(self, t):
+        return B.download_state(self.desc, t)
 
     @property
     def shape(self):
@@ -55,7 +63,9 @@ class DevBlock:
     def metrics_host(self):
         import torch
         torch.cuda.synchronize()
-        return dev_to_host(B.cfd_metrics_ptr(self.h), (10,) + tuple(self.q.shape[1:]))
+        d = self.desc
+        full = dev_to_host(B.cfd_metrics_ptr(self.h), (10, d.nk + 6, d.ld_j, d.ld_i))
+        return np.ascontiguousarray(full[:, :, :d.nj + 6, :d.ni + 6])
 
     def exchange(self):
         if self.x is None:
@@ -67,7 +77,7 @@ class DevBlock:
 
     def rhs(self, mask=B.CFD_ALL, q=None):
         B.cfd_rhs(self.h, self.q if q is None else q, self.r, mask)
-        return self.r.cpu().numpy()
+        return self.host(self.r)
 
     def step(self, dt):
         B.cfd_rk_stage(self.h, 0, dt, self.q, self.q, self.qa)
@@ -113,3 +123,71 @@ def vector_norm_err(a, b):
     ai = a[:, 3:-3, 3:-3, 3:-3]
     bi = b[:, 3:-3, 3:-3, 3:-3]
     return float(np.max(np.abs(ai - bi)) / np.max(np.abs(bi)))
+
+
+class DevMulti:
+    """All blocks of a multi-block workload on the GPU (pitched, aligned layout)."""
+
+    def __init__(self, wl, precision=B.CFD_FP64, **over):
+        import torch
+        self.wl = wl
+        self.descs, self.h, self.q, self.qa, self.qb = [], [], [], [], []
+        s = torch.cuda.current_stream()
+        for bi, b in enumerate(wl.blocks):
+            d = B.desc_from_workload(wl, bi, precision, ld_i=B.aligned_pitch(b.ni), **over)
+            h = B.cfd_block_create(d, s)
+            xyz = torch_dev(b.xyz)
+            B.cfd_metrics(h, xyz, b.ni + 12, b.nj + 12)
+            del xyz
+            self.descs.append(d)
+            self.h.append(h)
+            self.q.append(B.upload_state(d, b.q))
+            self.qa.append(B.upload_state(d, b.q))
+            self.qb.append(B.upload_state(d, b.q))
+        self.x = B.cfd_exchange_create(self.h, wl.interfaces)
+        self.bt = None
+        self.halo(self.q)  # initial wall reset, copies and ghost fills
+
+    def halo(self, bufs):
+        B.cfd_halo_exchange(self.x, B.CFD_FIELDS_Q, bufs)
+
+    def stage(self, st, dt, cur, out):
+        for h, c in zip(self.h, cur):
+            B.cfd_viscous_fluxes(h, c)
+        B.cfd_halo_exchange(self.x, B.CFD_FIELDS_VISC, None)
+        for h, qn, c, o in zip(self.h, self.q, cur, out):
+            B.cfd_rk_sweeps(h, st, dt, qn, c, o)
+        self.halo(out)
+
+    def step(self, dt):
+        self.stage(0, dt, self.q, self.qa)
+        self.stage(1, dt, self.qa, self.qb)
+        self.stage(2, dt, self.qb, self.q)
+
+    def batch_step(self, dt_dev):
+        if self.bt is None:
+            import torch
+            self.bt = B.cfd_batch_create(self.h, self.x, torch.cuda.current_stream())
+        B.cfd_batch_step(self.bt, dt_dev, self.q, self.qa, self.qb)
+
+    def host(self, bi, t=None):
+        return B.download_state(self.descs[bi], self.q[bi] if t is None else t)
+
+    def close(self):
+        if self.bt is not None:
+            B.cfd_batch_destroy(self.bt)
+        B.cfd_exchange_destroy(self.x)
+        for h in self.h:
+            B.cfd_block_destroy(h)
+
+
+def oracle_multi(wl, linear=False):
+    """Oracle configs, metrics and initial states (halos filled like cfd_halo_exchange)."""
+    import oracle as O
+    cfgs = [O.cfg_from_workload(wl, bi, linear_weights=linear) for bi in range(len(wl.blocks))]
+    mets = [O.metrics(c, b.xyz) for c, b in zip(cfgs, wl.blocks)]
+    qs = [O.wall_reset(c, b.q) for c, b in zip(cfgs, wl.blocks)]
+    qs = [O.periodic_wrap(c, q) for c, q in zip(cfgs, qs)]
+    O.exchange(cfgs, qs, wl.interfaces)
+    qs = [O.bc_fill(c, q) for c, q in zip(cfgs, qs)]
+    return cfgs, mets, qs

@@ -32,8 +32,8 @@ def _cuda():
     yield
 
 
-def _pair(wl, **over):
-    dev = DevBlock(wl, **over)
+def _pair(wl, pitched=False, **over):
+    dev = DevBlock(wl, pitched=pitched, **over)
     c = O.cfg_from_workload(wl, linear_weights=over.get("weights", B.CFD_WENO_JS) == B.CFD_WENO_LINEAR,
                             viscous=over.get("viscous", wl.viscous))
     met = O.metrics(c, wl.blocks[0].xyz)
@@ -124,9 +124,9 @@ def test_periodic_halo_exchange(size):
         q[:, :, -3:] = np.nan
         q[:, :, :, :3] = np.nan
         q[:, :, :, -3:] = np.nan
-        buf = torch.from_numpy(q).cuda()
+        buf = B.upload_state(dev.desc, q)
         dev.halo(buf)
-        got = buf.cpu().numpy()
+        got = dev.host(buf)
         ref = O.periodic_wrap(c, q)
         s = slice(3, -3)
         for face in [(slice(None), s, s, slice(0, 3)), (slice(None), s, s, slice(-3, None)),
@@ -148,7 +148,7 @@ def test_rk_ten_steps_c1():
         for step in range(10):
             dev.step(dt)
             qo = O.rk_step(c, met, dt, qo)
-            got = dev.q.cpu().numpy()
+            got = dev.host(dev.q)
             err = normwise(got, qo)
             print(step, err, per_component(got, qo))
             assert np.all(err < TOL), (step, err)
@@ -156,10 +156,11 @@ def test_rk_ten_steps_c1():
         dev.close()
 
 
-@pytest.mark.parametrize("size", [(23, 17, 11), (7, 7, 7)])
-def test_rk_ragged(size):
+@pytest.mark.parametrize("size,pitched", [((23, 17, 11), False), ((7, 7, 7), False), ((23, 17, 11), True),
+                                          ((40, 33, 9), True)])
+def test_rk_ragged(size, pitched):
     wl = _vortex(*size)
-    dev, c, met = _pair(wl)
+    dev, c, met = _pair(wl, pitched=pitched)
     try:
         q = wl.blocks[0].q
         dt = O.dt_cfl(c, met, q, 0.5)
@@ -167,7 +168,7 @@ def test_rk_ragged(size):
         for step in range(3):
             dev.step(dt)
             qo = O.rk_step(c, met, dt, qo)
-        assert np.all(normwise(dev.q.cpu().numpy(), qo) < TOL)
+        assert np.all(normwise(dev.host(dev.q), qo) < TOL)
     finally:
         dev.close()
 
@@ -232,14 +233,15 @@ def test_argument_and_state_errors():
 
 
 def test_full_size_taylor_green_first_stage():
-    """256^3 Taylor-Green case at its real size: the first RK stage, every point."""
+    """256^3 Taylor-Green case at its real size, in the benchmark's pitched layout: the
+    first RK stage, every point."""
     wl = W.taylor_green_wavy(256)
-    dev, c, met = _pair(wl)
+    dev, c, met = _pair(wl, pitched=True)
     try:
         q = wl.blocks[0].q
         dt = O.dt_cfl(c, met, q, wl.cfl)
         B.cfd_rk_stage(dev.h, 0, dt, dev.q, dev.q, dev.qa)
-        got = dev.qa.cpu().numpy()
+        got = dev.host(dev.qa)
         r = O.rhs(c, met, q)
         ref = q + dt * r
         err = normwise(got, ref)
