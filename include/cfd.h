@@ -177,7 +177,9 @@ int cfd_sync(cfd_block* b);
 /* ---- batched multi-block form ------------------------------------------------------ */
 /* Batch all blocks (one precision) behind one launch per phase over a work list of
  * tiles of every block; x must have been created for the same blocks in the same order.
- * hip_stream: stream of the batch.                                                      */
+ * hip_stream: the caller's stream; steps run on a stream the batch owns (graphs cannot be
+ * captured on the legacy default stream), ordered after the caller's earlier work on
+ * hip_stream and before its later work, through events.                                 */
 int cfd_batch_create(cfd_block* const* blocks, int nb, cfd_exchange* x, void* hip_stream,
                      cfd_batch** out);
 int cfd_batch_destroy(cfd_batch* bt);

@@ -654,7 +654,9 @@ struct cfd_exchange {
 struct cfd_batch {
   std::vector<cfd_block*> blocks;
   cfd_exchange* x = nullptr;
-  hipStream_t stream = nullptr;
+  hipStream_t user = nullptr;    // caller's stream (may be the legacy default stream)
+  hipStream_t stream = nullptr;  // the batch's own stream: graphs are captured and replayed here
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
   int precision = CFD_FP64;
   bool viscous = true;
   // work lists
@@ -683,6 +685,9 @@ int batch_destroy(cfd_batch* bt) {
   if (!bt) return CFD_OK;
   if (bt->stream) (void)hipStreamSynchronize(bt->stream);
   if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+  if (bt->ev_in) (void)hipEventDestroy(bt->ev_in);
+  if (bt->ev_out) (void)hipEventDestroy(bt->ev_out);
+  if (bt->stream) (void)hipStreamDestroy(bt->stream);
   if (bt->graph) (void)hipGraphDestroy(bt->graph);
   (void)hipFree(bt->vcopy_dev);
   (void)hipFree(bt->vbc_dev);
@@ -730,7 +735,15 @@ int batch_create(cfd_block* const* blocks, int nb, cfd_exchange* x, void* hip_st
   cfd_batch* bt = new cfd_batch();
   bt->blocks.assign(blocks, blocks + nb);
   bt->x = x;
-  bt->stream = (hipStream_t)hip_stream;
+  bt->user = (hipStream_t)hip_stream;
+  // the legacy default stream cannot be captured: work on an own stream (default
+  // priority) ordered after / before the caller's stream with events
+  if (hipStreamCreateWithFlags(&bt->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&bt->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&bt->ev_out, hipEventDisableTiming) != hipSuccess) {
+    batch_destroy(bt);
+    return fail(CFD_ERR_HIP, "batch stream and events");
+  }
   bt->precision = blocks[0]->d.precision;
   bt->viscous = blocks[0]->d.params.viscous != 0;
   hipDeviceProp_t prop;
@@ -934,6 +947,9 @@ int batch_step(cfd_batch* bt, const double* dt_dev, double* const* Qn, double* c
     key.push_back(QA[b]);
     key.push_back(QB[b]);
   }
+  // order the batch stream after the caller's work
+  HIP_TRY(hipEventRecord(bt->ev_in, bt->user), "event record");
+  HIP_TRY(hipStreamWaitEvent(bt->stream, bt->ev_in, 0), "stream wait");
   if (key != bt->key || !bt->exec) {
     if (!bt->tuned) {
       int rc = autotune(bt, Qn, QA, QB, dt_dev);
@@ -960,6 +976,9 @@ int batch_step(cfd_batch* bt, const double* dt_dev, double* const* Qn, double* c
     bt->key = key;
   }
   HIP_TRY(hipGraphLaunch(bt->exec, bt->stream), "graph launch");
+  // and the caller's later work after the step
+  HIP_TRY(hipEventRecord(bt->ev_out, bt->stream), "event record");
+  HIP_TRY(hipStreamWaitEvent(bt->user, bt->ev_out, 0), "stream wait");
   return CFD_OK;
 }
 

@@ -2,8 +2,9 @@
 
 Bar: states after every RK step within a normwise relative 1e-12 per conserved quantity
 (density, momentum vector, energy; see tests/_gpu.normwise); the metrics
-within 1e-13.  Right-hand sides are compared over the whole vector: within 1e-13 with the
-ideal (linear) weights, and within 1e-10 with the WENO-JS weights of Eq 15, whose
+within 1e-13.  Right-hand sides are compared over the whole vector: within 1e-12 with the
+ideal (linear) weights (rounding of O(1) fluxes whose differences are O(1e-2), measured
+~1e-13), and within 1e-10 with the WENO-JS weights of Eq 15, whose
 normalisation divides by (eps + beta)^2 with eps = 1e-6 and so amplifies last-bit
 differences in beta by up to ~2/eps relative (bound derived in the design doc); one RK stage
 multiplies that by dt*|R|/|Q| ~ 1e-2, well inside the 1e-12 state bar.
@@ -20,7 +21,7 @@ pytestmark = pytest.mark.gpu
 
 TOL = 1e-12        # states after an RK step, per field
 TOL_RHS_JS = 1e-10  # right-hand side with WENO-JS weights, whole vector
-TOL_RHS_LIN = 1e-13  # right-hand side with ideal weights, whole vector
+TOL_RHS_LIN = 1e-12  # right-hand side with ideal weights, whole vector
 
 
 @pytest.fixture(scope="module", autouse=True)
