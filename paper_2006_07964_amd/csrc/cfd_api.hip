@@ -158,6 +158,14 @@ Phys make_phys(const cfd_params& p) {
   return ph;
 }
 
+bool same_params(const cfd_params& a, const cfd_params& b) {
+  bool same = a.gamma == b.gamma && a.mach == b.mach && a.reynolds == b.reynolds && a.prandtl == b.prandtl &&
+              a.suth == b.suth && a.weno_eps == b.weno_eps && a.viscous == b.viscous && a.weights == b.weights &&
+              a.t_wall == b.t_wall;
+  for (int v = 0; v < 5; ++v) same = same && a.qinf[v] == b.qinf[v];
+  return same;
+}
+
 int npts(const Geom& g, int axis) { return axis == 0 ? g.ni : axis == 1 ? g.nj : g.nk; }
 int64_t stride(const Geom& g, int axis) { return axis == 0 ? 1 : axis == 1 ? g.ld_i : g.ld_i * g.ld_j; }
 int64_t at_h(const Geom& g, int i, int j, int k) {
@@ -173,13 +181,23 @@ void face_geom(const Geom& g, int f, int* axis, int* w, int* out) {
 
 // halo copy of face fa of block A (index ia) from face fb of block B (index ib):
 // ghost layer m (1..3) beyond fa <- interior layer m-1 inside fb.
+// tangential axes of a face on `axis`; the contiguous i axis comes first whenever it is
+// tangential, so that neighbouring threads of the halo kernels touch neighbouring elements
+void tangential(int axis, int* ta, int* tb) {
+  *ta = axis == 0 ? 1 : 0;
+  *tb = axis == 2 ? 1 : 2;
+}
+
 CopySeg make_copy(const Geom& A, int ia, int fa, const Geom& B, int ib, int fb, int plane0, int nplanes) {
   int axis, wa, outa, wb, outb;
   face_geom(A, fa, &axis, &wa, &outa);
   int axis_b;
   face_geom(B, fb, &axis_b, &wb, &outb);
-  const int ta = (axis + 1) % 3, tb = (axis + 2) % 3;
+  int ta, tb;
+  tangential(axis, &ta, &tb);
   CopySeg s;
+  std::memset(&s, 0, sizeof s);
+  s.layer_fast = axis == 0;  // on i faces the three halo layers are the contiguous run
   s.dst = ia;
   s.src = ib;
   s.na = npts(A, ta);
@@ -203,7 +221,8 @@ CopySeg make_copy(const Geom& A, int ia, int fa, const Geom& B, int ib, int fb, 
 BcSeg make_bc(const Geom& G, int blk, int f, int kind) {
   int axis, w, out;
   face_geom(G, f, &axis, &w, &out);
-  const int ta = (axis + 1) % 3, tb = (axis + 2) % 3;
+  int ta, tb;
+  tangential(axis, &ta, &tb);
   BcSeg s;
   s.blk = blk;
   s.kind = kind;
@@ -317,26 +336,26 @@ int run_sweeps(cfd_block* b, const double* Q, unsigned mask, int out_kind, doubl
     if (mask & (1u << d)) dirs[nd++] = d;
   SweepArgs a;
   std::memset(&a, 0, sizeof a);
-  a.g = b->g;
-  a.q = Q;
-  a.met = b->met;
-  a.vis = b->vis;
-  a.ph = make_phys(b->d.params);
-  a.do_inv = inv;
-  a.do_vis = vis;
-  a.qn = qn;
-  a.dt_dev = dt_dev;
-  a.dt = dt;
-  a.ca = ca;
-  a.cb = cb;
-  a.cc = cc;
+  a.b.g = b->g;
+  a.b.q = Q;
+  a.b.met = b->met;
+  a.b.vis = b->vis;
+  a.b.qn = qn;
+  a.c.ph = make_phys(b->d.params);
+  a.c.do_inv = inv;
+  a.c.do_vis = vis;
+  a.c.dt_dev = dt_dev;
+  a.c.dt = dt;
+  a.c.ca = ca;
+  a.c.cb = cb;
+  a.c.cc = cc;
   if (nd == 0 || (!inv && !vis)) {
     // nothing to evaluate: R = 0 or Qout = ca Qn + cb Q, via a zero-term sweep along xi
-    a.do_inv = 0;
-    a.do_vis = 0;
-    a.has_prev = 0;
-    a.out_kind = out_kind;
-    a.out = out;
+    a.c.do_inv = 0;
+    a.c.do_vis = 0;
+    a.c.has_prev = 0;
+    a.c.out_kind = out_kind;
+    a.b.out = out;
     ProfScope ps(&b->prof, kSweepNames[0], b->stream);
     hipError_t e = b->d.precision == CFD_FP64 ? launch_sweep<double>(0, a, b->stream) : launch_sweep<float>(0, a, b->stream);
     ps.done();
@@ -344,11 +363,11 @@ int run_sweeps(cfd_block* b, const double* Q, unsigned mask, int out_kind, doubl
   }
   for (int n = 0; n < nd; ++n) {
     const bool last = n == nd - 1;
-    a.has_prev = n > 0;
-    a.rt_in = b->rt;
-    a.rt_out = b->rt;
-    a.out_kind = last ? out_kind : kOutPartial;
-    a.out = last ? out : nullptr;
+    a.c.has_prev = n > 0;
+    a.b.rt_in = b->rt;
+    a.b.rt_out = b->rt;
+    a.c.out_kind = last ? out_kind : kOutPartial;
+    a.b.out = last ? out : nullptr;
     const char* name = (last && out_kind == kOutRK) ? kSweepRkNames[dirs[n]] : kSweepNames[dirs[n]];
     ProfScope ps(&b->prof, name, b->stream);
     hipError_t e = b->d.precision == CFD_FP64 ? launch_sweep<double>(dirs[n], a, b->stream)
@@ -672,8 +691,9 @@ struct cfd_batch {
   BcSeg* vbc_dev = nullptr;
   int nvbc = 0, maxvbc = 0;
   // argument tables of the captured pointer set: 3 stages x (visc + 3 sweeps)
-  ViscArgs* visc_args_dev = nullptr;    // [3][nb]
-  SweepArgs* sweep_args_dev = nullptr;  // [3][3][nb]
+  ViscArgs* visc_args_dev = nullptr;      // [3][nb]
+  SweepBlock* sweep_args_dev = nullptr;   // [3][3][nb]
+  SweepCommon sweep_common[3][3]{};       // [stage][direction], passed by value
   std::vector<const void*> key;         // pointers the graph was captured for
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -729,8 +749,8 @@ int batch_create(cfd_block* const* blocks, int nb, cfd_exchange* x, void* hip_st
     if (!blocks[b] || blocks[b] != x->blocks[b]) return fail(CFD_ERR_ARG, "exchange plan was made for a different block list");
     if (!blocks[b]->have_metrics) return fail(CFD_ERR_STATE, "cfd_metrics has not been run on every block");
     if (blocks[b]->d.precision != blocks[0]->d.precision) return fail(CFD_ERR_ARG, "blocks of a batch share one precision");
-    if (blocks[b]->d.params.viscous != blocks[0]->d.params.viscous)
-      return fail(CFD_ERR_ARG, "blocks of a batch are all viscous or all inviscid");
+    if (!same_params(blocks[b]->d.params, blocks[0]->d.params))
+      return fail(CFD_ERR_ARG, "blocks of a batch share one set of physical parameters");
   }
   cfd_batch* bt = new cfd_batch();
   bt->blocks.assign(blocks, blocks + nb);
@@ -770,7 +790,7 @@ int batch_create(cfd_block* const* blocks, int nb, cfd_exchange* x, void* hip_st
   bt->nvcopy = (int)vc.size();
   bt->nvbc = (int)vb.size();
   if (hipMalloc((void**)&bt->visc_args_dev, 3 * nb * sizeof(ViscArgs)) != hipSuccess ||
-      hipMalloc((void**)&bt->sweep_args_dev, 9 * nb * sizeof(SweepArgs)) != hipSuccess) {
+      hipMalloc((void**)&bt->sweep_args_dev, 9 * nb * sizeof(SweepBlock)) != hipSuccess) {
     batch_destroy(bt);
     return fail(CFD_ERR_ALLOC, "batch argument tables");
   }
@@ -779,15 +799,30 @@ int batch_create(cfd_block* const* blocks, int nb, cfd_exchange* x, void* hip_st
   return CFD_OK;
 }
 
-// per-block argument tables for stage s reading Qcur[b] and writing Qout[b]
-void build_args(cfd_batch* bt, double* const* Qn, double* const* QA, double* const* QB, std::vector<ViscArgs>& va,
-                std::vector<SweepArgs>& sa) {
+// argument tables for stage s reading Qcur[b] and writing Qout[b]: per-block parts in
+// va / sa, the parts shared by every block in bt->sweep_common
+void build_args(cfd_batch* bt, double* const* Qn, double* const* QA, double* const* QB, const double* dt_dev,
+                std::vector<ViscArgs>& va, std::vector<SweepBlock>& sa) {
   const int nb = (int)bt->blocks.size();
   va.assign(3 * nb, ViscArgs{});
-  sa.assign(9 * nb, SweepArgs{});
+  sa.assign(9 * nb, SweepBlock{});
+  const Phys ph = make_phys(bt->blocks[0]->d.params);
   for (int st = 0; st < 3; ++st) {
     double* const* cur = st == 0 ? Qn : st == 1 ? QA : QB;
     double* const* outp = st == 0 ? QA : st == 1 ? QB : Qn;
+    for (int d = 0; d < 3; ++d) {
+      SweepCommon& c = bt->sweep_common[st][d];
+      std::memset(&c, 0, sizeof c);
+      c.ph = ph;
+      c.do_inv = 1;
+      c.do_vis = bt->viscous;
+      c.has_prev = d > 0;
+      c.out_kind = d == 2 ? kOutRK : kOutPartial;
+      c.dt_dev = dt_dev;
+      c.ca = kRK[st][0];
+      c.cb = kRK[st][1];
+      c.cc = kRK[st][2];
+    }
     for (int b = 0; b < nb; ++b) {
       cfd_block* B = bt->blocks[b];
       ViscArgs& v = va[st * nb + b];
@@ -795,9 +830,9 @@ void build_args(cfd_batch* bt, double* const* Qn, double* const* QA, double* con
       v.q = cur[b];
       v.met = B->met;
       v.vis = B->vis;
-      v.ph = make_phys(B->d.params);
+      v.ph = ph;
       for (int d = 0; d < 3; ++d) {
-        SweepArgs& a = sa[(st * 3 + d) * nb + b];
+        SweepBlock& a = sa[(st * 3 + d) * nb + b];
         std::memset(&a, 0, sizeof a);
         a.g = B->g;
         a.q = cur[b];
@@ -805,30 +840,24 @@ void build_args(cfd_batch* bt, double* const* Qn, double* const* QA, double* con
         a.vis = B->vis;
         a.rt_in = B->rt;
         a.rt_out = B->rt;
-        a.ph = make_phys(B->d.params);
-        a.do_inv = 1;
-        a.do_vis = bt->viscous;
-        a.has_prev = d > 0;
-        a.out_kind = d == 2 ? kOutRK : kOutPartial;
         a.out = d == 2 ? outp[b] : nullptr;
         a.qn = Qn[b];
-        a.ca = kRK[st][0];
-        a.cb = kRK[st][1];
-        a.cc = kRK[st][2];
         sweep_tiling(d, bt->cfg[d], B->g, &a.tiles_c1, &a.tiles_d, &a.tile_len);
       }
     }
   }
 }
 
-hipError_t launch_batch_sweep(cfd_batch* bt, int st, int d, const SweepArgs* args_dev) {
+hipError_t launch_batch_sweep(cfd_batch* bt, int st, int d) {
   const int nb = (int)bt->blocks.size();
   const TileList& tl = bt->sweep_tl[d];
   const int ntiles = tl.prefix[nb];
   const int nwg = bt->persist[d] ? std::min(ntiles, bt->persist_wgs) : ntiles;
-  const SweepArgs* a = args_dev + (st * 3 + d) * nb;
-  return bt->precision == CFD_FP64 ? launch_sweep_batch<double>(d, bt->cfg[d], bt->persist[d] != 0, a, tl, nwg, bt->stream)
-                                   : launch_sweep_batch<float>(d, bt->cfg[d], bt->persist[d] != 0, a, tl, nwg, bt->stream);
+  const SweepBlock* a = bt->sweep_args_dev + (st * 3 + d) * nb;
+  const SweepCommon& c = bt->sweep_common[st][d];
+  return bt->precision == CFD_FP64
+             ? launch_sweep_batch<double>(d, bt->cfg[d], bt->persist[d] != 0, a, c, tl, nwg, bt->stream)
+             : launch_sweep_batch<float>(d, bt->cfg[d], bt->persist[d] != 0, a, c, tl, nwg, bt->stream);
 }
 
 // one RK stage of every block (all launches on bt->stream)
@@ -854,7 +883,7 @@ hipError_t enqueue_stage(cfd_batch* bt, int st, double* const* outp) {
                                   : launch_visc_ghost<float>(bt->vbc_dev, bt->nvbc, bt->maxvbc, t, bt->stream);
     if (e != hipSuccess) return e;
   }
-  for (int d = 0; d < 3 && e == hipSuccess; ++d) e = launch_batch_sweep(bt, st, d, bt->sweep_args_dev);
+  for (int d = 0; d < 3 && e == hipSuccess; ++d) e = launch_batch_sweep(bt, st, d);
   if (e != hipSuccess) return e;
   // Q halos of every block: wall reset, interface / periodic copies, ghost fills
   BcArgs ba;
@@ -876,11 +905,10 @@ hipError_t enqueue_stage(cfd_batch* bt, int st, double* const* outp) {
 
 int upload_args(cfd_batch* bt, double* const* Qn, double* const* QA, double* const* QB, const double* dt_dev) {
   std::vector<ViscArgs> va;
-  std::vector<SweepArgs> sa;
-  build_args(bt, Qn, QA, QB, va, sa);
-  for (auto& a : sa) a.dt_dev = dt_dev;
+  std::vector<SweepBlock> sa;
+  build_args(bt, Qn, QA, QB, dt_dev, va, sa);
   HIP_TRY(hipMemcpy(bt->visc_args_dev, va.data(), va.size() * sizeof(ViscArgs), hipMemcpyHostToDevice), "upload args");
-  HIP_TRY(hipMemcpy(bt->sweep_args_dev, sa.data(), sa.size() * sizeof(SweepArgs), hipMemcpyHostToDevice), "upload args");
+  HIP_TRY(hipMemcpy(bt->sweep_args_dev, sa.data(), sa.size() * sizeof(SweepBlock), hipMemcpyHostToDevice), "upload args");
   return CFD_OK;
 }
 
@@ -912,7 +940,7 @@ int autotune(cfd_batch* bt, double* const* Qn, double* const* QA, double* const*
         float ms = 0.f, total = 0.f;
         for (int rep = 0; rep < 3 && rc == CFD_OK; ++rep) {
           hipError_t e = hipEventRecord(e0, bt->stream);
-          if (e == hipSuccess) e = launch_batch_sweep(bt, 0, d, bt->sweep_args_dev);
+          if (e == hipSuccess) e = launch_batch_sweep(bt, 0, d);
           if (e == hipSuccess) e = hipEventRecord(e1, bt->stream);
           if (e == hipSuccess) e = hipEventSynchronize(e1);
           if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);

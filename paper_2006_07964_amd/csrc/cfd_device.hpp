@@ -25,6 +25,18 @@ __device__ __forceinline__ int64_t at(const Geom& g, int i, int j, int k) {
   return ((int64_t)(k + kHalo) * g.ld_j + (j + kHalo)) * g.ld_i + (i + kHalo);
 }
 
+// A pointer read from device memory (a per-block argument table) is generic to the
+// compiler, which then emits flat memory instructions; flat loads count against both the
+// vector-memory and the LDS counters and serialise waits in LDS-heavy kernels.  Kernels
+// that take their pointers from such a table access memory through pointers typed in the
+// global address space.
+template <typename T>
+using GP = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ GP<T> to_global(T* p) {
+  return (GP<T>)p;
+}
+
 // Physical constants of one block (FP64 on the host side of the kernel arguments).
 struct Phys {
   double gamma;

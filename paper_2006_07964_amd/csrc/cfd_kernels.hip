@@ -123,6 +123,7 @@ __device__ __forceinline__ void visc_point(const ViscArgs& a, int i, int j, int 
   const int64_t p = at(g, i, j, k);
   const R gamma = R(a.ph.gamma), gm1 = gamma - R(1);
   const int64_t st[3] = {1, g.ld_i, g.ld_i * g.ld_j};
+  const GP<const double> Q = to_global(a.q), met = to_global(a.met);
   R gr[4][3];  // d(u, v, w, T)/d(xi, eta, zeta)
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -136,7 +137,7 @@ __device__ __forceinline__ void visc_point(const ViscArgs& a, int i, int j, int 
       const int64_t pp = p + m * st[d];
       R q[5];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) q[v] = R(a.q[v * g.plane + pp]);
+      for (int v = 0; v < 5; ++v) q[v] = R(Q[v * g.plane + pp]);
       const R rinv = rcp(q[0]);
       const R u = q[1] * rinv, v = q[2] * rinv, w = q[3] * rinv;
       const R T = gamma * gm1 * (q[4] * rinv - R(0.5) * (u * u + v * v + w * w));
@@ -151,8 +152,8 @@ __device__ __forceinline__ void visc_point(const ViscArgs& a, int i, int j, int 
 #pragma unroll
   for (int d = 0; d < 3; ++d)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) mh[d][c] = R(a.met[(3 * d + c) * g.plane + p]);
-  const R J = R(a.met[9 * g.plane + p]);
+    for (int c = 0; c < 3; ++c) mh[d][c] = R(met[(3 * d + c) * g.plane + p]);
+  const R J = R(met[9 * g.plane + p]);
   R dx[4][3];  // d(u, v, w, T)/d(x, y, z), Eq 21
 #pragma unroll
   for (int n = 0; n < 4; ++n)
@@ -160,7 +161,7 @@ __device__ __forceinline__ void visc_point(const ViscArgs& a, int i, int j, int 
     for (int c = 0; c < 3; ++c) dx[n][c] = J * (mh[0][c] * gr[n][0] + mh[1][c] * gr[n][1] + mh[2][c] * gr[n][2]);
   R q0[5];
 #pragma unroll
-  for (int v = 0; v < 5; ++v) q0[v] = R(a.q[v * g.plane + p]);
+  for (int v = 0; v < 5; ++v) q0[v] = R(Q[v * g.plane + p]);
   const R rinv = rcp(q0[0]);
   const R u = q0[1] * rinv, v = q0[2] * rinv, w = q0[3] * rinv;
   const R T = gamma * gm1 * (q0[4] * rinv - R(0.5) * (u * u + v * v + w * w));
@@ -177,7 +178,7 @@ __device__ __forceinline__ void visc_point(const ViscArgs& a, int i, int j, int 
   R bet[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) bet[c] = u * tau[0][c] + v * tau[1][c] + w * tau[2][c] + hs * dx[3][c];
-  R* out = static_cast<R*>(a.vis);
+  const GP<R> out = to_global(static_cast<R*>(a.vis));
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
 #pragma unroll
@@ -188,7 +189,7 @@ __device__ __forceinline__ void visc_point(const ViscArgs& a, int i, int j, int 
 }
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_visc(ViscArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_visc(ViscArgs a) {
   const int i = blockIdx.x * 64 + (threadIdx.x & 63);
   const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (i >= a.g.ni || j >= a.g.nj) return;
@@ -199,7 +200,8 @@ __global__ __launch_bounds__(256) void k_visc(ViscArgs a) {
 void visc_tiling(const Geom& g, int* tiles) { *tiles = ((g.ni + 63) / 64) * ((g.nj + 3) / 4) * g.nk; }
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_visc_batch(const ViscArgs* args, TileList tl) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_visc_batch(const ViscArgs* args,
+                                                                                             TileList tl) {
   const int total = tl.prefix[tl.nblk];
   int start, count, lane_wg, nwg_x;
   xcd_range(total, &start, &count, &lane_wg, &nwg_x);
@@ -265,13 +267,14 @@ struct SweepLds {
 // One tile of a direction sweep: t is the logical tile index inside the block (sweep-
 // direction tile fastest, then the cross tile c1, then the cross index c2).
 template <int DIR, typename R, int TW, int TS, int NT>
-__device__ __forceinline__ void sweep_tile(const SweepArgs& a, int t, R* sFp, R* sFm, R* sFn) {
+__device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBlock& b, int t, R* sFp, R* sFm,
+                                           R* sFn) {
   constexpr int NH = SweepLds<TW, TS>::NH;
   constexpr int NN = SweepLds<TW, TS>::NN;
   constexpr int NW = SweepLds<TW, TS>::NW;
   using L = LdsIdx<DIR, TW>;
 
-  const Geom& g = a.g;
+  const Geom& g = b.g;
   const int nd = DIR == 0 ? g.ni : DIR == 1 ? g.nj : g.nk;
   const int n1 = DIR == 0 ? g.nj : g.ni;
   // element offsets inside one plane fit in 32 bits (checked on the host); every array
@@ -279,27 +282,28 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, int t, R* sFp, R*
   const uint32_t sd = DIR == 0 ? 1u : DIR == 1 ? (uint32_t)g.ld_i : (uint32_t)(g.ld_i * g.ld_j);
   const uint32_t s1 = DIR == 0 ? (uint32_t)g.ld_i : 1u;
   const uint32_t s2 = DIR == 2 ? (uint32_t)g.ld_i : (uint32_t)(g.ld_i * g.ld_j);
-  const int ts = a.tile_len;  // output nodes per tile along the sweep (<= TS)
+  const int ts = b.tile_len;  // output nodes per tile along the sweep (<= TS)
   const int nw = ts + 2;      // WENO nodes
   const int nn = ts + 6;      // nodal-flux nodes
-  const int tiled = t % a.tiles_d;
-  const int rest = t / a.tiles_d;
-  const int tile1 = rest % a.tiles_c1;
-  const int c2 = rest / a.tiles_c1;
+  const int tiled = t % b.tiles_d;
+  const int rest = t / b.tiles_d;
+  const int tile1 = rest % b.tiles_c1;
+  const int c2 = rest / b.tiles_c1;
   const int c1_0 = tile1 * TW;
   const int d0 = tiled * ts;
   // offset of (c1 = 0, c2, n = 0)
   const uint32_t origin = (uint32_t)at(g, 0, 0, 0) + (uint32_t)c2 * s2;
   const int64_t plane = g.plane;
-  const double* Q = a.q;
-  const Gas<R> G(a.ph);
-  const R eps = R(a.ph.eps);
-  const bool linear = a.ph.linear != 0;
-  const double* mx = a.met + (3 * DIR + 0) * plane;
-  const double* my = a.met + (3 * DIR + 1) * plane;
-  const double* mz = a.met + (3 * DIR + 2) * plane;
+  const GP<const double> Q = to_global(b.q);
+  const GP<const double> met = to_global(b.met);
+  const Gas<R> G(c.ph);
+  const R eps = R(c.ph.eps);
+  const bool linear = c.ph.linear != 0;
+  const GP<const double> mx = met + (3 * DIR + 0) * plane;
+  const GP<const double> my = met + (3 * DIR + 1) * plane;
+  const GP<const double> mz = met + (3 * DIR + 2) * plane;
 
-  if (a.do_inv) {
+  if (c.do_inv) {
     // ---- nodal fluxes, Eq 4 -----------------------------------------------------------
     // items are laid out with the compile-time extents NN / NW / TS so that the index
     // split needs no runtime division; slots beyond the tile's actual length idle
@@ -370,8 +374,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, int t, R* sFp, R*
   }
 
   // ---- assembly per output node ---------------------------------------------------------
-  const R* vis = static_cast<const R*>(a.vis) + (4 * DIR) * plane;
-  const R* rin = static_cast<const R*>(a.rt_in);
+  const GP<const R> vis = to_global(static_cast<const R*>(b.vis)) + (4 * DIR) * plane;
+  const GP<const R> rin = to_global(static_cast<const R*>(b.rt_in));
   for (int e = threadIdx.x; e < TW * TS; e += NT) {
     const int s = DIR == 0 ? e % TS : e / TW;
     const int w = DIR == 0 ? e / TS : e % TW;
@@ -382,7 +386,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, int t, R* sFp, R*
     R r[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) r[v] = R(0);
-    if (a.do_inv) {
+    if (c.do_inv) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         const R fp = sFp[L::f(v, w, s + 1, NH)] + sFm[L::f(v, w, s + 1, NH)];
@@ -393,32 +397,34 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, int t, R* sFp, R*
         r[v] = -D;
       }
     }
-    if (a.do_vis) {
+    if (c.do_vis) {
 #pragma unroll
       for (int v = 1; v < 5; ++v) {
-        const R* vp = vis + (v - 1) * plane;
+        const GP<const R> vp = vis + (v - 1) * plane;
         r[v] += d6<R>([&](int m) { return vp[p + (uint32_t)m * sd]; });
       }
     }
-    if (a.has_prev) {
+    if (c.has_prev) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) r[v] += (rin + v * plane)[p];
     }
-    if (a.out_kind == kOutPartial) {
-      R* ro = static_cast<R*>(a.rt_out);
+    if (c.out_kind == kOutPartial) {
+      const GP<R> ro = to_global(static_cast<R*>(b.rt_out));
 #pragma unroll
       for (int v = 0; v < 5; ++v) (ro + v * plane)[p] = r[v];
     } else {
-      const double J = (a.met + 9 * plane)[p];
-      if (a.out_kind == kOutRhs) {
+      const double J = (met + 9 * plane)[p];
+      const GP<double> out = to_global(b.out);
+      if (c.out_kind == kOutRhs) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) (a.out + v * plane)[p] = J * double(r[v]);
+        for (int v = 0; v < 5; ++v) (out + v * plane)[p] = J * double(r[v]);
       } else {
-        const double dt = a.dt_dev ? *a.dt_dev : a.dt;
-        const double cdt = a.cc * dt * J;
+        const double dt = c.dt_dev ? *c.dt_dev : c.dt;
+        const double cdt = c.cc * dt * J;
+        const GP<const double> qn = to_global(b.qn);
 #pragma unroll
         for (int v = 0; v < 5; ++v)
-          (a.out + v * plane)[p] = a.ca * (a.qn + v * plane)[p] + a.cb * (Q + v * plane)[p] + cdt * double(r[v]);
+          (out + v * plane)[p] = c.ca * (qn + v * plane)[p] + c.cb * (Q + v * plane)[p] + cdt * double(r[v]);
       }
     }
   }
@@ -436,7 +442,7 @@ struct SweepShared {
 template <int DIR, typename R, int TW, int TS, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep(SweepArgs a) {
   __shared__ SweepShared<R, TW, TS> sh;
-  sweep_tile<DIR, R, TW, TS, NT>(a, xcd_remap(blockIdx.x, gridDim.x), sh.Fp, sh.Fm, sh.Fn);
+  sweep_tile<DIR, R, TW, TS, NT>(a.c, a.b, xcd_remap(blockIdx.x, gridDim.x), sh.Fp, sh.Fm, sh.Fn);
 }
 
 // Batched blocks: one launch walks a work list covering the tiles of every block
@@ -444,15 +450,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 // per XCD.  PERSIST: a fixed grid of workgroups strides through its XCD's range; otherwise
 // one workgroup per tile (ids remapped XCD-contiguously).
 template <int DIR, typename R, int TW, int TS, int NT, bool PERSIST>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_batch(const SweepArgs* args,
-                                                                                            TileList tl) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_batch(
+    const SweepBlock* __restrict__ blocks, SweepCommon c, TileList tl) {
   __shared__ SweepShared<R, TW, TS> sh;
   const int total = tl.prefix[tl.nblk];
   if (!PERSIST) {
     const int t = xcd_remap(blockIdx.x, gridDim.x);
     int blk = 0;
     while (t >= tl.prefix[blk + 1]) ++blk;
-    sweep_tile<DIR, R, TW, TS, NT>(args[blk], t - tl.prefix[blk], sh.Fp, sh.Fm, sh.Fn);
+    sweep_tile<DIR, R, TW, TS, NT>(c, blocks[blk], t - tl.prefix[blk], sh.Fp, sh.Fm, sh.Fn);
     return;
   }
   int start, count, lane_wg, nwg_x;
@@ -461,7 +467,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   for (int u = lane_wg; u < count; u += nwg_x) {
     const int t = start + u;
     while (t >= tl.prefix[blk + 1]) ++blk;  // t only grows, so the scan resumes
-    sweep_tile<DIR, R, TW, TS, NT>(args[blk], t - tl.prefix[blk], sh.Fp, sh.Fm, sh.Fn);
+    sweep_tile<DIR, R, TW, TS, NT>(c, blocks[blk], t - tl.prefix[blk], sh.Fp, sh.Fm, sh.Fn);
     __syncthreads();  // the next tile overwrites the LDS this one read
   }
 }
@@ -516,9 +522,9 @@ hipError_t launch_sweep_cfg(int dir, const SweepArgs& a, int64_t nwg, hipStream_
 
 template <typename R>
 hipError_t launch_sweep(int dir, SweepArgs a, hipStream_t s, int cfg) {
-  const int n2 = dir == 2 ? a.g.nj : a.g.nk;
-  sweep_tiling(dir, cfg, a.g, &a.tiles_c1, &a.tiles_d, &a.tile_len);
-  const int64_t nwg = (int64_t)a.tiles_c1 * a.tiles_d * n2;
+  const int n2 = dir == 2 ? a.b.g.nj : a.b.g.nk;
+  sweep_tiling(dir, cfg, a.b.g, &a.b.tiles_c1, &a.b.tiles_d, &a.b.tile_len);
+  const int64_t nwg = (int64_t)a.b.tiles_c1 * a.b.tiles_d * n2;
   if (nwg > 0x7fffffff) return hipErrorInvalidValue;
   switch (cfg) {
     case 0: return launch_sweep_cfg<R, 0>(dir, a, nwg, s);
@@ -532,40 +538,43 @@ template hipError_t launch_sweep<double>(int, SweepArgs, hipStream_t, int);
 template hipError_t launch_sweep<float>(int, SweepArgs, hipStream_t, int);
 
 template <typename R, int CFG, bool P>
-hipError_t launch_sweep_batch_cfg(int dir, const SweepArgs* args, const TileList& tl, int nwg, hipStream_t s) {
+hipError_t launch_sweep_batch_cfg(int dir, const SweepBlock* blocks, const SweepCommon& c, const TileList& tl, int nwg,
+                                  hipStream_t s) {
   using C = TileCfg<CFG>;
   if (dir == 0)
-    hipLaunchKernelGGL((k_sweep_batch<0, R, C::TW, C::TS, C::NT, P>), dim3(nwg), dim3(C::NT), 0, s, args, tl);
+    hipLaunchKernelGGL((k_sweep_batch<0, R, C::TW, C::TS, C::NT, P>), dim3(nwg), dim3(C::NT), 0, s, blocks, c, tl);
   else if (dir == 1)
-    hipLaunchKernelGGL((k_sweep_batch<1, R, C::TW, C::TS, C::NT, P>), dim3(nwg), dim3(C::NT), 0, s, args, tl);
+    hipLaunchKernelGGL((k_sweep_batch<1, R, C::TW, C::TS, C::NT, P>), dim3(nwg), dim3(C::NT), 0, s, blocks, c, tl);
   else
-    hipLaunchKernelGGL((k_sweep_batch<2, R, C::TW, C::TS, C::NT, P>), dim3(nwg), dim3(C::NT), 0, s, args, tl);
+    hipLaunchKernelGGL((k_sweep_batch<2, R, C::TW, C::TS, C::NT, P>), dim3(nwg), dim3(C::NT), 0, s, blocks, c, tl);
   return hipGetLastError();
 }
 
 // persist: nwg workgroups stride through the list; otherwise nwg must equal the tile count
 template <typename R>
-hipError_t launch_sweep_batch(int dir, int cfg, bool persist, const SweepArgs* args_dev, const TileList& tl, int nwg,
-                              hipStream_t s) {
+hipError_t launch_sweep_batch(int dir, int cfg, bool persist, const SweepBlock* blocks, const SweepCommon& c,
+                              const TileList& tl, int nwg, hipStream_t s) {
   if (persist) {
     switch (cfg) {
-      case 0: return launch_sweep_batch_cfg<R, 0, true>(dir, args_dev, tl, nwg, s);
-      case 1: return launch_sweep_batch_cfg<R, 1, true>(dir, args_dev, tl, nwg, s);
-      case 2: return launch_sweep_batch_cfg<R, 2, true>(dir, args_dev, tl, nwg, s);
-      case 3: return launch_sweep_batch_cfg<R, 3, true>(dir, args_dev, tl, nwg, s);
+      case 0: return launch_sweep_batch_cfg<R, 0, true>(dir, blocks, c, tl, nwg, s);
+      case 1: return launch_sweep_batch_cfg<R, 1, true>(dir, blocks, c, tl, nwg, s);
+      case 2: return launch_sweep_batch_cfg<R, 2, true>(dir, blocks, c, tl, nwg, s);
+      case 3: return launch_sweep_batch_cfg<R, 3, true>(dir, blocks, c, tl, nwg, s);
     }
   } else {
     switch (cfg) {
-      case 0: return launch_sweep_batch_cfg<R, 0, false>(dir, args_dev, tl, nwg, s);
-      case 1: return launch_sweep_batch_cfg<R, 1, false>(dir, args_dev, tl, nwg, s);
-      case 2: return launch_sweep_batch_cfg<R, 2, false>(dir, args_dev, tl, nwg, s);
-      case 3: return launch_sweep_batch_cfg<R, 3, false>(dir, args_dev, tl, nwg, s);
+      case 0: return launch_sweep_batch_cfg<R, 0, false>(dir, blocks, c, tl, nwg, s);
+      case 1: return launch_sweep_batch_cfg<R, 1, false>(dir, blocks, c, tl, nwg, s);
+      case 2: return launch_sweep_batch_cfg<R, 2, false>(dir, blocks, c, tl, nwg, s);
+      case 3: return launch_sweep_batch_cfg<R, 3, false>(dir, blocks, c, tl, nwg, s);
     }
   }
   return hipErrorInvalidValue;
 }
-template hipError_t launch_sweep_batch<double>(int, int, bool, const SweepArgs*, const TileList&, int, hipStream_t);
-template hipError_t launch_sweep_batch<float>(int, int, bool, const SweepArgs*, const TileList&, int, hipStream_t);
+template hipError_t launch_sweep_batch<double>(int, int, bool, const SweepBlock*, const SweepCommon&, const TileList&, int,
+                                               hipStream_t);
+template hipError_t launch_sweep_batch<float>(int, int, bool, const SweepBlock*, const SweepCommon&, const TileList&, int,
+                                              hipStream_t);
 
 // =====================================================================================
 // Halo copies across 1-to-1 faces (ghost layer m of the destination face <- interior
@@ -574,18 +583,27 @@ template hipError_t launch_sweep_batch<float>(int, int, bool, const SweepArgs*, 
 template <typename T>
 __global__ __launch_bounds__(256) void k_copy(const CopySeg* segs, PtrTable t) {
   const CopySeg S = segs[blockIdx.y];
-  const int64_t per_plane = (int64_t)S.na * S.nb * kHalo;
-  const int64_t total = per_plane * S.nplanes;
+  const int per_plane = S.na * S.nb * kHalo;
+  const int total = per_plane * S.nplanes;
   T* dst = static_cast<T*>(t.p[S.dst]);
   const T* src = static_cast<const T*>(t.p[S.src]);
   const int64_t pd = t.plane[S.dst], ps = t.plane[S.src];
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
-    const int v = S.plane0 + (int)(e / per_plane);
-    int64_t r = e % per_plane;
-    const int a = (int)(r % S.na);
-    r /= S.na;
-    const int l = (int)(r % kHalo);
-    const int b = (int)(r / kHalo);
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < total; e += gridDim.x * 256) {
+    const int v = S.plane0 + e / per_plane;
+    int r = e % per_plane;
+    int a, l;
+    if (S.layer_fast) {
+      l = r % kHalo;
+      r /= kHalo;
+      a = r % S.na;
+      r /= S.na;
+    } else {
+      a = r % S.na;
+      r /= S.na;
+      l = r % kHalo;
+      r /= kHalo;
+    }
+    const int b = r;
     dst[v * pd + S.dst_off + a * S.dst_sa + b * S.dst_sb + l * S.dst_sl] =
         src[v * ps + S.src_off + a * S.src_sa + b * S.src_sb + l * S.src_sl];
   }

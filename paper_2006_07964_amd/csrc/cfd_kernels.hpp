@@ -44,21 +44,29 @@ void visc_tiling(const Geom& g, int* tiles);
 
 // ---- direction sweep ----------------------------------------------------------------
 enum OutKind { kOutPartial = 0, kOutRhs = 1, kOutRK = 2 };
-struct SweepArgs {
+// per-block part of a sweep launch
+struct SweepBlock {
   Geom g;
-  const double* q;       // state whose RHS is evaluated (Qcur)
-  const double* met;     // 10 metric planes
-  const void* vis;       // 12 viscous-flux planes (compute type)
-  const void* rt_in;     // partial sums of earlier directions (compute type) or null
-  void* rt_out;          // partial sums out (kOutPartial)
-  double* out;           // R (kOutRhs) or Qout (kOutRK)
-  const double* qn;      // RK base state (kOutRK)
+  const double* q;    // state whose RHS is evaluated (Qcur)
+  const double* met;  // 10 metric planes
+  const void* vis;    // 12 viscous-flux planes (compute type)
+  const void* rt_in;  // partial sums of earlier directions (compute type) or null
+  void* rt_out;       // partial sums out (kOutPartial)
+  double* out;        // R (kOutRhs) or Qout (kOutRK)
+  const double* qn;   // RK base state (kOutRK)
+  int tiles_c1, tiles_d, tile_len;  // filled by the launcher
+};
+// part shared by every block of a launch
+struct SweepCommon {
   const double* dt_dev;  // device time step or null (then dt)
   double dt;
   double ca, cb, cc;     // Qout = ca Qn + cb Q + cc dt J Rtilde
   Phys ph;
   int do_inv, do_vis, has_prev, out_kind;
-  int tiles_c1, tiles_d, tile_len;  // filled by the launcher
+};
+struct SweepArgs {
+  SweepCommon c;
+  SweepBlock b;
 };
 constexpr int kTileCfgs = 4;  // sweep tile configurations (see TileCfg in cfd_kernels.hip)
 // tiles of one block for direction dir under configuration cfg
@@ -68,14 +76,15 @@ template <typename R>
 hipError_t launch_sweep(int dir, SweepArgs a, hipStream_t s, int cfg = 0);
 
 template <typename R>
-hipError_t launch_sweep_batch(int dir, int cfg, bool persist, const SweepArgs* args_dev, const TileList& tl, int nwg,
-                              hipStream_t s);
+hipError_t launch_sweep_batch(int dir, int cfg, bool persist, const SweepBlock* blocks_dev, const SweepCommon& c,
+                              const TileList& tl, int nwg, hipStream_t s);
 
 // ---- halo copies and boundary fills -------------------------------------------------
 struct CopySeg {
   int32_t dst, src;          // block indices
   int32_t na, nb;            // tangential extents
   int32_t plane0, nplanes;   // planes copied
+  int32_t layer_fast, pad;   // 1: halo layer is the fastest thread index, else a
   int64_t dst_off, src_off;  // element offsets of (a=0, b=0, layer 0)
   int64_t dst_sa, dst_sb, dst_sl;
   int64_t src_sa, src_sb, src_sl;
