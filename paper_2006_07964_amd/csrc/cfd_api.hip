@@ -295,6 +295,7 @@ PtrTable single_table(void* p, int64_t plane) {
 // viscous fluxes of one block with block-local halos (periodic wraps, physical ghosts)
 int run_visc(cfd_block* b, const double* Q) {
   ViscArgs va;
+  std::memset(&va, 0, sizeof va);
   va.g = b->g;
   va.q = Q;
   va.met = b->met;
@@ -722,8 +723,8 @@ void fill_tiles(cfd_batch* bt) {
   bt->visc_tl.nblk = nb;
   bt->visc_tl.prefix[0] = 0;
   for (int b = 0; b < nb; ++b) {
-    int t;
-    visc_tiling(bt->blocks[b]->g, &t);
+    int kc, t;
+    visc_tiling(bt->blocks[b]->g, &kc, &t);
     bt->visc_tl.prefix[b + 1] = bt->visc_tl.prefix[b] + t;
   }
   for (int d = 0; d < 3; ++d) {
@@ -831,6 +832,8 @@ void build_args(cfd_batch* bt, double* const* Qn, double* const* QA, double* con
       v.met = B->met;
       v.vis = B->vis;
       v.ph = ph;
+      int tiles;
+      visc_tiling(B->g, &v.kc, &tiles);
       for (int d = 0; d < 3; ++d) {
         SweepBlock& a = sa[(st * 3 + d) * nb + b];
         std::memset(&a, 0, sizeof a);
@@ -866,9 +869,8 @@ hipError_t enqueue_stage(cfd_batch* bt, int st, double* const* outp) {
   hipError_t e = hipSuccess;
   if (bt->viscous) {
     const ViscArgs* va = bt->visc_args_dev + st * nb;
-    const int nv = bt->visc_tl.prefix[nb];
-    e = bt->precision == CFD_FP64 ? launch_visc_batch<double>(va, bt->visc_tl, nv, bt->stream)
-                                  : launch_visc_batch<float>(va, bt->visc_tl, nv, bt->stream);
+    e = bt->precision == CFD_FP64 ? launch_visc_batch<double>(va, bt->visc_tl, bt->stream)
+                                  : launch_visc_batch<float>(va, bt->visc_tl, bt->stream);
     if (e != hipSuccess) return e;
     PtrTable t;
     std::memset(&t, 0, sizeof t);
@@ -924,8 +926,8 @@ int autotune(cfd_batch* bt, double* const* Qn, double* const* QA, double* const*
     if ((rc = upload_args(bt, Qn, QA, QB, dt_dev)) != CFD_OK) return rc;
     const int nb = (int)bt->blocks.size();
     hipError_t e = bt->precision == CFD_FP64
-                       ? launch_visc_batch<double>(bt->visc_args_dev, bt->visc_tl, bt->visc_tl.prefix[nb], bt->stream)
-                       : launch_visc_batch<float>(bt->visc_args_dev, bt->visc_tl, bt->visc_tl.prefix[nb], bt->stream);
+                       ? launch_visc_batch<double>(bt->visc_args_dev, bt->visc_tl, bt->stream)
+                       : launch_visc_batch<float>(bt->visc_args_dev, bt->visc_tl, bt->stream);
     if (e != hipSuccess) rc = hip_fail(e, "tuning prepass");
   }
   for (int d = 0; d < 3 && rc == CFD_OK; ++d) {

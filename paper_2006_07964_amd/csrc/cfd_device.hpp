@@ -37,6 +37,27 @@ __device__ __forceinline__ GP<T> to_global(T* p) {
   return (GP<T>)p;
 }
 
+// Element e of the array at a wave-uniform base, with e < 2^32 / sizeof(T): the byte offset
+// is formed in 32 bits so that the access takes the scalar-base + 32-bit vector-offset
+// form, and accesses to several planes at one node share the offset register.
+// The base of each plane is made opaque (a wave-uniform value read from lane 0) so that the
+// compiler keeps it in scalar registers instead of re-associating it with the offsets.
+template <typename T>
+__device__ __forceinline__ GP<T> plane_ptr(GP<T> base, int64_t plane_off) {
+  const uint64_t u = (uint64_t)(base + plane_off);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+  return (GP<T>)(((uint64_t)hi << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ T ldg(GP<const T> base, uint32_t e) {
+  return *(GP<const T>)((GP<const char>)base + e * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void stg(GP<T> base, uint32_t e, T v) {
+  *(GP<T>)((GP<char>)base + e * (uint32_t)sizeof(T)) = v;
+}
+
 // Physical constants of one block (FP64 on the host side of the kernel arguments).
 struct Phys {
   double gamma;

@@ -116,125 +116,189 @@ hipError_t launch_metrics(const MetricArgs& a, hipStream_t s) {
 // =====================================================================================
 // Viscous prepass (Eqs 5, 6, 21): nodal viscous fluxes of all three directions.
 // Plane 4*d + (n-1) holds component n = 1..4 of the direction-d flux, divided by J.
+//
+// A workgroup owns a VI x VJ tile of (i, j) columns and marches along k through a chunk
+// of kc planes.  Each thread keeps the primitives (u, v, w, T) of its own column at
+// k-3..k+3 in registers for the zeta derivative; the primitives of plane k, with three
+// halo columns / rows, go through LDS for the xi and eta derivatives.  Every primitive is
+// formed about twice per chunk instead of at each of its eighteen stencil uses, and Q is
+// read once per column.
 // =====================================================================================
+constexpr int VI = 64, VJ = 8, VNT = VI * VJ;
+constexpr int kViscChunk = 16;  // planes per workgroup (fewer when nk is smaller)
+
 template <typename R>
-__device__ __forceinline__ void visc_point(const ViscArgs& a, int i, int j, int k) {
+struct ViscShared {
+  R p[4][VJ + 6][VI + 6];  // (u, v, w, T) of plane k at (j - j0 + 3, i - i0 + 3)
+};
+
+template <typename R>
+__device__ __forceinline__ void primitives(GP<const double> Q, int64_t plane, uint32_t p, R gg, R out[4]) {
+  R q[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) q[v] = R(ldg(plane_ptr(Q, v * plane), p));
+  const R rinv = rcp(q[0]);
+  out[0] = q[1] * rinv;
+  out[1] = q[2] * rinv;
+  out[2] = q[3] * rinv;
+  out[3] = gg * (q[4] * rinv - R(0.5) * (out[0] * out[0] + out[1] * out[1] + out[2] * out[2]));
+}
+
+// d/dn of a field on a 7-point line, g(m) = value at offset m (sixth-order central)
+template <typename R, typename F>
+__device__ __forceinline__ R grad6(F g) {
+  R s = R(0);
+#pragma unroll
+  for (int m = -3; m <= 3; ++m) {
+    if (m == 0) continue;
+    const R wgt = (m == 1 || m == -1) ? R(0.75) : (m == 2 || m == -2) ? R(-0.15) : R(1.0 / 60.0);
+    s += (m > 0 ? wgt : -wgt) * g(m);
+  }
+  return s;
+}
+
+template <typename R>
+__device__ __forceinline__ void visc_tile(const ViscArgs& a, int t, ViscShared<R>& sh) {
   const Geom& g = a.g;
-  const int64_t p = at(g, i, j, k);
-  const R gamma = R(a.ph.gamma), gm1 = gamma - R(1);
-  const int64_t st[3] = {1, g.ld_i, g.ld_i * g.ld_j};
+  const int nti = (g.ni + VI - 1) / VI, ntj = (g.nj + VJ - 1) / VJ;
+  const int i0 = (t % nti) * VI, j0 = ((t / nti) % ntj) * VJ;
+  const int k0 = (t / (nti * ntj)) * a.kc;
+  const int k1 = min(k0 + a.kc, g.nk);
+  const int ti = threadIdx.x % VI, tj = threadIdx.x / VI;
+  const int i = i0 + ti, j = j0 + tj;
+  const bool own = i < g.ni + kHalo && j < g.nj + kHalo;  // column inside the stored array
+  const bool act = i < g.ni && j < g.nj;                  // column with outputs
+  const uint32_t sk = (uint32_t)(g.ld_i * g.ld_j);
+  const uint32_t pc = (uint32_t)at(g, own ? i : 0, own ? j : 0, 0);  // (i, j, k = 0); plane < 2^29
+  // halo node of this thread in plane k: eta rows below / above the tile, xi columns
+  // left / right of it (the stencil is a cross, corners are not needed)
+  int hi = 0, hj = 0;
+  const int h = threadIdx.x;
+  if (h < 2 * 3 * VI) {
+    hi = i0 + h % VI;
+    hj = h < 3 * VI ? j0 - 3 + h / VI : j0 + VJ + (h - 3 * VI) / VI;
+  } else if (h < 2 * 3 * VI + 2 * 3 * VJ) {
+    const int e = h - 2 * 3 * VI;
+    hj = j0 + (e % (3 * VJ)) / 3;
+    hi = e < 3 * VJ ? i0 - 3 + e % 3 : i0 + VI + e % 3;
+  } else {
+    hi = g.ni + kHalo;  // no halo node
+  }
+  const bool hval = hi < g.ni + kHalo && hj < g.nj + kHalo;
+  const uint32_t ph = (uint32_t)at(g, hval ? hi : 0, hval ? hj : 0, 0);
+
+  const R gg = R(a.ph.gamma) * (R(a.ph.gamma) - R(1));
   const GP<const double> Q = to_global(a.q), met = to_global(a.met);
-  R gr[4][3];  // d(u, v, w, T)/d(xi, eta, zeta)
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-#pragma unroll
-    for (int n = 0; n < 4; ++n) gr[n][d] = R(0);
-#pragma unroll
-    for (int m = -3; m <= 3; ++m) {
-      if (m == 0) continue;
-      const R wgt = (m == 1 || m == -1) ? R(0.75) : (m == 2 || m == -2) ? R(-0.15) : R(1.0 / 60.0);
-      const R sgn = m > 0 ? R(1) : R(-1);
-      const int64_t pp = p + m * st[d];
-      R q[5];
-#pragma unroll
-      for (int v = 0; v < 5; ++v) q[v] = R(Q[v * g.plane + pp]);
-      const R rinv = rcp(q[0]);
-      const R u = q[1] * rinv, v = q[2] * rinv, w = q[3] * rinv;
-      const R T = gamma * gm1 * (q[4] * rinv - R(0.5) * (u * u + v * v + w * w));
-      const R f = sgn * wgt;
-      gr[0][d] += f * u;
-      gr[1][d] += f * v;
-      gr[2][d] += f * w;
-      gr[3][d] += f * T;
-    }
-  }
-  R mh[3][3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) mh[d][c] = R(met[(3 * d + c) * g.plane + p]);
-  const R J = R(met[9 * g.plane + p]);
-  R dx[4][3];  // d(u, v, w, T)/d(x, y, z), Eq 21
-#pragma unroll
-  for (int n = 0; n < 4; ++n)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) dx[n][c] = J * (mh[0][c] * gr[n][0] + mh[1][c] * gr[n][1] + mh[2][c] * gr[n][2]);
-  R q0[5];
-#pragma unroll
-  for (int v = 0; v < 5; ++v) q0[v] = R(Q[v * g.plane + p]);
-  const R rinv = rcp(q0[0]);
-  const R u = q0[1] * rinv, v = q0[2] * rinv, w = q0[3] * rinv;
-  const R T = gamma * gm1 * (q0[4] * rinv - R(0.5) * (u * u + v * v + w * w));
-  const R mu = viscosity(T, R(a.ph.suth));
-  const R vs = R(a.ph.visc_scale) * mu;
-  const R lam = R(-2.0 / 3.0) * vs;
-  const R div = dx[0][0] + dx[1][1] + dx[2][2];
-  R tau[3][3];
-#pragma unroll
-  for (int r = 0; r < 3; ++r)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) tau[r][c] = vs * (dx[r][c] + dx[c][r]) + (r == c ? lam * div : R(0));
-  const R hs = R(a.ph.heat_scale) * mu;
-  R bet[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) bet[c] = u * tau[0][c] + v * tau[1][c] + w * tau[2][c] + hs * dx[3][c];
   const GP<R> out = to_global(static_cast<R*>(a.vis));
+  const int64_t plane = g.plane;
+  R P[7][4];  // own column, planes k-3 .. k+3
+  if (own) {
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
+    for (int m = 0; m < 6; ++m) primitives<R>(Q, plane, pc + (uint32_t)(k0 - 3 + m) * sk, gg, P[m]);
+  }
+  for (int k = k0; k < k1; ++k) {
+    if (own) primitives<R>(Q, plane, pc + (uint32_t)(k + 3) * sk, gg, P[6]);
+    if (own) {
 #pragma unroll
-    for (int n = 0; n < 3; ++n)
-      out[(4 * d + n) * g.plane + p] = mh[d][0] * tau[n][0] + mh[d][1] * tau[n][1] + mh[d][2] * tau[n][2];
-    out[(4 * d + 3) * g.plane + p] = mh[d][0] * bet[0] + mh[d][1] * bet[1] + mh[d][2] * bet[2];
+      for (int n = 0; n < 4; ++n) sh.p[n][tj + 3][ti + 3] = P[3][n];
+    }
+    if (hval) {
+      R ph4[4];
+      primitives<R>(Q, plane, ph + (uint32_t)k * sk, gg, ph4);
+#pragma unroll
+      for (int n = 0; n < 4; ++n) sh.p[n][hj - j0 + 3][hi - i0 + 3] = ph4[n];
+    }
+    __syncthreads();
+    if (act) {
+      R gr[4][3];  // d(u, v, w, T)/d(xi, eta, zeta)
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        gr[n][0] = grad6<R>([&](int m) { return sh.p[n][tj + 3][ti + 3 + m]; });
+        gr[n][1] = grad6<R>([&](int m) { return sh.p[n][tj + 3 + m][ti + 3]; });
+        gr[n][2] = grad6<R>([&](int m) { return P[3 + m][n]; });
+      }
+      const uint32_t p = pc + (uint32_t)k * sk;
+      R mh[3][3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) mh[d][c] = R(ldg(plane_ptr(met, (3 * d + c) * plane), p));
+      const R J = R(ldg(plane_ptr(met, 9 * plane), p));
+      R dx[4][3];  // d(u, v, w, T)/d(x, y, z), Eq 21
+#pragma unroll
+      for (int n = 0; n < 4; ++n)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dx[n][c] = J * (mh[0][c] * gr[n][0] + mh[1][c] * gr[n][1] + mh[2][c] * gr[n][2]);
+      const R u = P[3][0], v = P[3][1], w = P[3][2];
+      const R mu = viscosity(P[3][3], R(a.ph.suth));
+      const R vs = R(a.ph.visc_scale) * mu;
+      const R lam = R(-2.0 / 3.0) * vs;
+      const R div = dx[0][0] + dx[1][1] + dx[2][2];
+      R tau[3][3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) tau[r][c] = vs * (dx[r][c] + dx[c][r]) + (r == c ? lam * div : R(0));
+      const R hs = R(a.ph.heat_scale) * mu;
+      R bet[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) bet[c] = u * tau[0][c] + v * tau[1][c] + w * tau[2][c] + hs * dx[3][c];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+#pragma unroll
+        for (int n = 0; n < 3; ++n)
+          stg(plane_ptr(out, (4 * d + n) * plane), p, mh[d][0] * tau[n][0] + mh[d][1] * tau[n][1] + mh[d][2] * tau[n][2]);
+        stg(plane_ptr(out, (4 * d + 3) * plane), p, mh[d][0] * bet[0] + mh[d][1] * bet[1] + mh[d][2] * bet[2]);
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < 6; ++m)
+#pragma unroll
+      for (int n = 0; n < 4; ++n) P[m][n] = P[m + 1][n];
+    __syncthreads();  // plane k of the LDS tile is consumed
   }
 }
 
 template <typename R>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_visc(ViscArgs a) {
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (i >= a.g.ni || j >= a.g.nj) return;
-  visc_point<R>(a, i, j, blockIdx.z);
+__global__ __launch_bounds__(VNT) __attribute__((amdgpu_waves_per_eu(4))) void k_visc(ViscArgs a) {
+  __shared__ ViscShared<R> sh;
+  visc_tile<R>(a, xcd_remap(blockIdx.x, gridDim.x), sh);
 }
 
-// tiles of 64 x 4 points of one k plane, i-tile fastest, then j-tile, then k
-void visc_tiling(const Geom& g, int* tiles) { *tiles = ((g.ni + 63) / 64) * ((g.nj + 3) / 4) * g.nk; }
+// chunk length and tile count of one block: i-tile fastest, then j-tile, then k-chunk
+void visc_tiling(const Geom& g, int* kc, int* tiles) {
+  *kc = g.nk < kViscChunk ? g.nk : kViscChunk;
+  *tiles = ((g.ni + VI - 1) / VI) * ((g.nj + VJ - 1) / VJ) * ((g.nk + *kc - 1) / *kc);
+}
 
+// one workgroup per tile of the concatenated list (ids remapped XCD-contiguously)
 template <typename R>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_visc_batch(const ViscArgs* args,
-                                                                                             TileList tl) {
-  const int total = tl.prefix[tl.nblk];
-  int start, count, lane_wg, nwg_x;
-  xcd_range(total, &start, &count, &lane_wg, &nwg_x);
+__global__ __launch_bounds__(VNT) __attribute__((amdgpu_waves_per_eu(4))) void k_visc_batch(const ViscArgs* __restrict__ args, TileList tl) {
+  __shared__ ViscShared<R> sh;
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
   int blk = 0;
-  for (int u = lane_wg; u < count; u += nwg_x) {
-    const int t = start + u;
-    while (t >= tl.prefix[blk + 1]) ++blk;
-    const ViscArgs& a = args[blk];
-    const int lt = t - tl.prefix[blk];
-    const int ti = (a.g.ni + 63) / 64, tj = (a.g.nj + 3) / 4;
-    const int i = (lt % ti) * 64 + (threadIdx.x & 63);
-    const int j = ((lt / ti) % tj) * 4 + (threadIdx.x >> 6);
-    const int k = lt / (ti * tj);
-    if (i < a.g.ni && j < a.g.nj) visc_point<R>(a, i, j, k);
-  }
+  while (t >= tl.prefix[blk + 1]) ++blk;
+  visc_tile<R>(args[blk], t - tl.prefix[blk], sh);
 }
 
 template <typename R>
-hipError_t launch_visc(const ViscArgs& a, hipStream_t s) {
-  dim3 grid((a.g.ni + 63) / 64, (a.g.nj + 3) / 4, a.g.nk);
-  hipLaunchKernelGGL(k_visc<R>, grid, dim3(256), 0, s, a);
+hipError_t launch_visc(ViscArgs a, hipStream_t s) {
+  int tiles;
+  visc_tiling(a.g, &a.kc, &tiles);
+  hipLaunchKernelGGL(k_visc<R>, dim3(tiles), dim3(VNT), 0, s, a);
   return hipGetLastError();
 }
-template hipError_t launch_visc<double>(const ViscArgs&, hipStream_t);
-template hipError_t launch_visc<float>(const ViscArgs&, hipStream_t);
+template hipError_t launch_visc<double>(ViscArgs, hipStream_t);
+template hipError_t launch_visc<float>(ViscArgs, hipStream_t);
 
+// args_dev[b].kc must be the chunk length visc_tiling gives for block b
 template <typename R>
-hipError_t launch_visc_batch(const ViscArgs* args_dev, const TileList& tl, int nwg, hipStream_t s) {
-  hipLaunchKernelGGL(k_visc_batch<R>, dim3(nwg), dim3(256), 0, s, args_dev, tl);
+hipError_t launch_visc_batch(const ViscArgs* args_dev, const TileList& tl, hipStream_t s) {
+  hipLaunchKernelGGL(k_visc_batch<R>, dim3(tl.prefix[tl.nblk]), dim3(VNT), 0, s, args_dev, tl);
   return hipGetLastError();
 }
-template hipError_t launch_visc_batch<double>(const ViscArgs*, const TileList&, int, hipStream_t);
-template hipError_t launch_visc_batch<float>(const ViscArgs*, const TileList&, int, hipStream_t);
+template hipError_t launch_visc_batch<double>(const ViscArgs*, const TileList&, hipStream_t);
+template hipError_t launch_visc_batch<float>(const ViscArgs*, const TileList&, hipStream_t);
 
 // =====================================================================================
 // Direction sweep: modified AFWENO inviscid derivative (Sec. 4.5.1, Figs 10-11, Eq 19),
@@ -299,9 +363,9 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
   const Gas<R> G(c.ph);
   const R eps = R(c.ph.eps);
   const bool linear = c.ph.linear != 0;
-  const GP<const double> mx = met + (3 * DIR + 0) * plane;
-  const GP<const double> my = met + (3 * DIR + 1) * plane;
-  const GP<const double> mz = met + (3 * DIR + 2) * plane;
+  const GP<const double> mx = plane_ptr(met, (3 * DIR + 0) * plane);
+  const GP<const double> my = plane_ptr(met, (3 * DIR + 1) * plane);
+  const GP<const double> mz = plane_ptr(met, (3 * DIR + 2) * plane);
 
   if (c.do_inv) {
     // ---- nodal fluxes, Eq 4 -----------------------------------------------------------
@@ -316,8 +380,8 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
       const uint32_t p = origin + (uint32_t)c1 * s1 + (uint32_t)n * sd;
       R q[5], F[5];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) q[v] = R((Q + v * plane)[p]);
-      phys_flux(q, R(mx[p]), R(my[p]), R(mz[p]), G, F);
+      for (int v = 0; v < 5; ++v) q[v] = R(ldg(plane_ptr(Q, v * plane), p));
+      phys_flux(q, R(ldg(mx, p)), R(ldg(my, p)), R(ldg(mz, p)), G, F);
 #pragma unroll
       for (int v = 0; v < 5; ++v) sFn[L::f(v, w, s, NN)] = F[v];
     }
@@ -334,15 +398,15 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
       const uint32_t p = origin + (uint32_t)c1 * s1 + (uint32_t)n * sd;
       R q0[5];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) q0[v] = R((Q + v * plane)[p]);
-      const Basis<R> B = make_basis(q0, R(mx[p]), R(my[p]), R(mz[p]), G);
+      for (int v = 0; v < 5; ++v) q0[v] = R(ldg(plane_ptr(Q, v * plane), p));
+      const Basis<R> B = make_basis(q0, R(ldg(mx, p)), R(ldg(my, p)), R(ldg(mz, p)), G);
       R V[5][5];  // V[t][field] at node n + t - 2
 #pragma unroll
       for (int tt = 0; tt < 5; ++tt) {
         R qq[5];
         const uint32_t pt = p + (uint32_t)(tt - 2) * sd;
 #pragma unroll
-        for (int v = 0; v < 5; ++v) qq[v] = R((Q + v * plane)[pt]);
+        for (int v = 0; v < 5; ++v) qq[v] = R(ldg(plane_ptr(Q, v * plane), pt));
         project(B, G, qq, V[tt]);
       }
       R vl[5], vr[5];
@@ -351,9 +415,9 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
       if (need_p) {
         R ul[5], F[5];
         unproject(B, G, vl, ul);
-        const R hx = R(half_metric([&](int m) { return mx[p + (uint32_t)m * sd]; }));
-        const R hy = R(half_metric([&](int m) { return my[p + (uint32_t)m * sd]; }));
-        const R hz = R(half_metric([&](int m) { return mz[p + (uint32_t)m * sd]; }));
+        const R hx = R(half_metric([&](int m) { return ldg(mx, p + (uint32_t)m * sd); }));
+        const R hy = R(half_metric([&](int m) { return ldg(my, p + (uint32_t)m * sd); }));
+        const R hz = R(half_metric([&](int m) { return ldg(mz, p + (uint32_t)m * sd); }));
         sw_flux<+1>(ul, hx, hy, hz, G, F);
 #pragma unroll
         for (int v = 0; v < 5; ++v) sFp[L::f(v, w, s, NH)] = F[v];
@@ -362,9 +426,9 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
         R ur[5], F[5];
         unproject(B, G, vr, ur);
         const uint32_t pm = p - sd;  // half point n-1/2 = (n-1)+1/2
-        const R hx = R(half_metric([&](int m) { return mx[pm + (uint32_t)m * sd]; }));
-        const R hy = R(half_metric([&](int m) { return my[pm + (uint32_t)m * sd]; }));
-        const R hz = R(half_metric([&](int m) { return mz[pm + (uint32_t)m * sd]; }));
+        const R hx = R(half_metric([&](int m) { return ldg(mx, pm + (uint32_t)m * sd); }));
+        const R hy = R(half_metric([&](int m) { return ldg(my, pm + (uint32_t)m * sd); }));
+        const R hz = R(half_metric([&](int m) { return ldg(mz, pm + (uint32_t)m * sd); }));
         sw_flux<-1>(ur, hx, hy, hz, G, F);
 #pragma unroll
         for (int v = 0; v < 5; ++v) sFm[L::f(v, w, s - 1, NH)] = F[v];
@@ -400,31 +464,31 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
     if (c.do_vis) {
 #pragma unroll
       for (int v = 1; v < 5; ++v) {
-        const GP<const R> vp = vis + (v - 1) * plane;
-        r[v] += d6<R>([&](int m) { return vp[p + (uint32_t)m * sd]; });
+        const GP<const R> vp = plane_ptr(vis, (v - 1) * plane);
+        r[v] += d6<R>([&](int m) { return ldg(vp, p + (uint32_t)m * sd); });
       }
     }
     if (c.has_prev) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) r[v] += (rin + v * plane)[p];
+      for (int v = 0; v < 5; ++v) r[v] += ldg(plane_ptr(rin, v * plane), p);
     }
     if (c.out_kind == kOutPartial) {
       const GP<R> ro = to_global(static_cast<R*>(b.rt_out));
 #pragma unroll
-      for (int v = 0; v < 5; ++v) (ro + v * plane)[p] = r[v];
+      for (int v = 0; v < 5; ++v) stg(plane_ptr(ro, v * plane), p, r[v]);
     } else {
-      const double J = (met + 9 * plane)[p];
+      const double J = ldg(plane_ptr(met, 9 * plane), p);
       const GP<double> out = to_global(b.out);
       if (c.out_kind == kOutRhs) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) (out + v * plane)[p] = J * double(r[v]);
+        for (int v = 0; v < 5; ++v) stg(plane_ptr(out, v * plane), p, J * double(r[v]));
       } else {
         const double dt = c.dt_dev ? *c.dt_dev : c.dt;
         const double cdt = c.cc * dt * J;
         const GP<const double> qn = to_global(b.qn);
 #pragma unroll
         for (int v = 0; v < 5; ++v)
-          (out + v * plane)[p] = c.ca * (qn + v * plane)[p] + c.cb * (Q + v * plane)[p] + cdt * double(r[v]);
+          stg(plane_ptr(out, v * plane), p, c.ca * ldg(plane_ptr(qn, v * plane), p) + c.cb * ldg(plane_ptr(Q, v * plane), p) + cdt * double(r[v]));
       }
     }
   }

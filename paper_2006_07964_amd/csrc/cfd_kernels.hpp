@@ -34,13 +34,14 @@ struct ViscArgs {
   const double* met;
   void* vis;  // 12 planes of the compute type
   Phys ph;
+  int kc;     // planes per tile (set by visc_tiling)
 };
 template <typename R>
-hipError_t launch_visc(const ViscArgs& a, hipStream_t s);
-// batched viscous prepass over the tiles (64 x 4 points of one k plane) of every block
+hipError_t launch_visc(ViscArgs a, hipStream_t s);
+// batched viscous prepass over the tiles (64 x 8 columns, a chunk of k planes) of every block
 template <typename R>
-hipError_t launch_visc_batch(const ViscArgs* args_dev, const TileList& tl, int nwg, hipStream_t s);
-void visc_tiling(const Geom& g, int* tiles);
+hipError_t launch_visc_batch(const ViscArgs* args_dev, const TileList& tl, hipStream_t s);
+void visc_tiling(const Geom& g, int* kc, int* tiles);
 
 // ---- direction sweep ----------------------------------------------------------------
 enum OutKind { kOutPartial = 0, kOutRhs = 1, kOutRK = 2 };
