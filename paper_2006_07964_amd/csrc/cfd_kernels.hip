@@ -332,7 +332,7 @@ struct SweepLds {
 // direction tile fastest, then the cross tile c1, then the cross index c2).
 template <int DIR, typename R, int TW, int TS, int NT>
 __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBlock& b, int t, R* sFp, R* sFm,
-                                           R* sFn) {
+                                           R* sFn, double* sM) {
   constexpr int NH = SweepLds<TW, TS>::NH;
   constexpr int NN = SweepLds<TW, TS>::NN;
   constexpr int NW = SweepLds<TW, TS>::NW;
@@ -368,9 +368,10 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
   const GP<const double> mz = plane_ptr(met, (3 * DIR + 2) * plane);
 
   if (c.do_inv) {
-    // ---- nodal fluxes, Eq 4 -----------------------------------------------------------
-    // items are laid out with the compile-time extents NN / NW / TS so that the index
-    // split needs no runtime division; slots beyond the tile's actual length idle
+    // ---- stage Q (compute type) and the sweep direction's node metrics (FP64) of nodes
+    // d0-3 .. d0+ts+2 of the tile's lines in LDS; sFn holds Q until the nodal fluxes
+    // replace it.  Items are laid out with the compile-time extents NN / NW / TS so that
+    // the index split needs no runtime division; slots beyond the tile's length idle.
     for (int e = threadIdx.x; e < TW * NN; e += NT) {
       const int s = DIR == 0 ? e % NN : e / TW;
       const int w = DIR == 0 ? e / NN : e % TW;
@@ -378,14 +379,15 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
       const int c1 = c1_0 + w;
       if (s >= nn || c1 >= n1 || n > nd + 2) continue;
       const uint32_t p = origin + (uint32_t)c1 * s1 + (uint32_t)n * sd;
-      R q[5], F[5];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) q[v] = R(ldg(plane_ptr(Q, v * plane), p));
-      phys_flux(q, R(ldg(mx, p)), R(ldg(my, p)), R(ldg(mz, p)), G, F);
-#pragma unroll
-      for (int v = 0; v < 5; ++v) sFn[L::f(v, w, s, NN)] = F[v];
+      for (int v = 0; v < 5; ++v) sFn[L::f(v, w, s, NN)] = R(ldg(plane_ptr(Q, v * plane), p));
+      sM[L::f(0, w, s, NN)] = ldg(mx, p);
+      sM[L::f(1, w, s, NN)] = ldg(my, p);
+      sM[L::f(2, w, s, NN)] = ldg(mz, p);
     }
-    // ---- characteristic WENO pair and split fluxes ------------------------------------
+    __syncthreads();
+    // ---- characteristic WENO pair and split fluxes; node n = d0-1+s sits at staged
+    // index s+2 ------------------------------------------------------------------------
     for (int e = threadIdx.x; e < TW * NW; e += NT) {
       const int s = DIR == 0 ? e % NW : e / TW;
       const int w = DIR == 0 ? e / NW : e % TW;
@@ -395,18 +397,18 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
       const bool need_p = s <= ts && n <= nd - 1;  // F+ at n+1/2
       const bool need_m = s >= 1;                  // F- at n-1/2
       if (!need_p && !need_m) continue;
-      const uint32_t p = origin + (uint32_t)c1 * s1 + (uint32_t)n * sd;
+      const int sc = s + 2;
       R q0[5];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) q0[v] = R(ldg(plane_ptr(Q, v * plane), p));
-      const Basis<R> B = make_basis(q0, R(ldg(mx, p)), R(ldg(my, p)), R(ldg(mz, p)), G);
+      for (int v = 0; v < 5; ++v) q0[v] = sFn[L::f(v, w, sc, NN)];
+      const Basis<R> B =
+          make_basis(q0, R(sM[L::f(0, w, sc, NN)]), R(sM[L::f(1, w, sc, NN)]), R(sM[L::f(2, w, sc, NN)]), G);
       R V[5][5];  // V[t][field] at node n + t - 2
 #pragma unroll
       for (int tt = 0; tt < 5; ++tt) {
         R qq[5];
-        const uint32_t pt = p + (uint32_t)(tt - 2) * sd;
 #pragma unroll
-        for (int v = 0; v < 5; ++v) qq[v] = R(ldg(plane_ptr(Q, v * plane), pt));
+        for (int v = 0; v < 5; ++v) qq[v] = sFn[L::f(v, w, s + tt, NN)];
         project(B, G, qq, V[tt]);
       }
       R vl[5], vr[5];
@@ -415,9 +417,9 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
       if (need_p) {
         R ul[5], F[5];
         unproject(B, G, vl, ul);
-        const R hx = R(half_metric([&](int m) { return ldg(mx, p + (uint32_t)m * sd); }));
-        const R hy = R(half_metric([&](int m) { return ldg(my, p + (uint32_t)m * sd); }));
-        const R hz = R(half_metric([&](int m) { return ldg(mz, p + (uint32_t)m * sd); }));
+        const R hx = R(half_metric([&](int m) { return sM[L::f(0, w, sc + m, NN)]; }));
+        const R hy = R(half_metric([&](int m) { return sM[L::f(1, w, sc + m, NN)]; }));
+        const R hz = R(half_metric([&](int m) { return sM[L::f(2, w, sc + m, NN)]; }));
         sw_flux<+1>(ul, hx, hy, hz, G, F);
 #pragma unroll
         for (int v = 0; v < 5; ++v) sFp[L::f(v, w, s, NH)] = F[v];
@@ -425,14 +427,29 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
       if (need_m) {
         R ur[5], F[5];
         unproject(B, G, vr, ur);
-        const uint32_t pm = p - sd;  // half point n-1/2 = (n-1)+1/2
-        const R hx = R(half_metric([&](int m) { return ldg(mx, pm + (uint32_t)m * sd); }));
-        const R hy = R(half_metric([&](int m) { return ldg(my, pm + (uint32_t)m * sd); }));
-        const R hz = R(half_metric([&](int m) { return ldg(mz, pm + (uint32_t)m * sd); }));
+        // half point n-1/2 = (n-1)+1/2, centred on staged index sc-1
+        const R hx = R(half_metric([&](int m) { return sM[L::f(0, w, sc - 1 + m, NN)]; }));
+        const R hy = R(half_metric([&](int m) { return sM[L::f(1, w, sc - 1 + m, NN)]; }));
+        const R hz = R(half_metric([&](int m) { return sM[L::f(2, w, sc - 1 + m, NN)]; }));
         sw_flux<-1>(ur, hx, hy, hz, G, F);
 #pragma unroll
         for (int v = 0; v < 5; ++v) sFm[L::f(v, w, s - 1, NH)] = F[v];
       }
+    }
+    __syncthreads();
+    // ---- nodal fluxes, Eq 4, in place of the staged Q ------------------------------------
+    for (int e = threadIdx.x; e < TW * NN; e += NT) {
+      const int s = DIR == 0 ? e % NN : e / TW;
+      const int w = DIR == 0 ? e / NN : e % TW;
+      const int n = d0 - 3 + s;
+      const int c1 = c1_0 + w;
+      if (s >= nn || c1 >= n1 || n > nd + 2) continue;
+      R q[5], F[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) q[v] = sFn[L::f(v, w, s, NN)];
+      phys_flux(q, R(sM[L::f(0, w, s, NN)]), R(sM[L::f(1, w, s, NN)]), R(sM[L::f(2, w, s, NN)]), G, F);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sFn[L::f(v, w, s, NN)] = F[v];
     }
     __syncthreads();
   }
@@ -500,13 +517,14 @@ struct SweepShared {
   R Fp[5 * TW * SweepLds<TW, TS>::NH];
   R Fm[5 * TW * SweepLds<TW, TS>::NH];
   R Fn[5 * TW * SweepLds<TW, TS>::NN];
+  double M[3 * TW * SweepLds<TW, TS>::NN];  // node metrics of the sweep direction
 };
 
 // Single block: one workgroup per tile, ids remapped XCD-contiguously.
 template <int DIR, typename R, int TW, int TS, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep(SweepArgs a) {
   __shared__ SweepShared<R, TW, TS> sh;
-  sweep_tile<DIR, R, TW, TS, NT>(a.c, a.b, xcd_remap(blockIdx.x, gridDim.x), sh.Fp, sh.Fm, sh.Fn);
+  sweep_tile<DIR, R, TW, TS, NT>(a.c, a.b, xcd_remap(blockIdx.x, gridDim.x), sh.Fp, sh.Fm, sh.Fn, sh.M);
 }
 
 // Batched blocks: one launch walks a work list covering the tiles of every block
@@ -522,7 +540,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const int t = xcd_remap(blockIdx.x, gridDim.x);
     int blk = 0;
     while (t >= tl.prefix[blk + 1]) ++blk;
-    sweep_tile<DIR, R, TW, TS, NT>(c, blocks[blk], t - tl.prefix[blk], sh.Fp, sh.Fm, sh.Fn);
+    sweep_tile<DIR, R, TW, TS, NT>(c, blocks[blk], t - tl.prefix[blk], sh.Fp, sh.Fm, sh.Fn, sh.M);
     return;
   }
   int start, count, lane_wg, nwg_x;
@@ -531,7 +549,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   for (int u = lane_wg; u < count; u += nwg_x) {
     const int t = start + u;
     while (t >= tl.prefix[blk + 1]) ++blk;  // t only grows, so the scan resumes
-    sweep_tile<DIR, R, TW, TS, NT>(c, blocks[blk], t - tl.prefix[blk], sh.Fp, sh.Fm, sh.Fn);
+    sweep_tile<DIR, R, TW, TS, NT>(c, blocks[blk], t - tl.prefix[blk], sh.Fp, sh.Fm, sh.Fn, sh.M);
     __syncthreads();  // the next tile overwrites the LDS this one read
   }
 }
