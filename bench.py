@@ -140,6 +140,8 @@ def main():
     ap.add_argument("--form", default=None, choices=["single", "perblock", "batched"],
                     help="single-block calls, per-block launches, or the batched graph form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--tiles", default=None,
+                    help="sweep tile shapes xi,eta,zeta of the single / per-block forms (library default if unset)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -165,6 +167,8 @@ def main():
         # rows padded to 16 doubles and offset so that interior rows start 128-byte lines
         desc = B.desc_from_workload(wl, bi, prec, ld_i=B.aligned_pitch(blk.ni))
         h = B.cfd_block_create(desc, stream)
+        if args.tiles:
+            B.cfd_block_set_tiles(h, [int(v) for v in args.tiles.split(",")])
         xyz = torch.from_numpy(blk.xyz).cuda()
         B.cfd_metrics(h, xyz, blk.ni + 12, blk.nj + 12)
         del xyz
@@ -269,7 +273,11 @@ def main():
         cfg["grid"] = [blk.ni, blk.nj, blk.nk]
     if bt is not None:
         tc, tp = B.cfd_batch_tuning(bt)
-        cfg["tuned_tiles"] = {"cfg": tc, "persistent": tp}
+        times = B.cfd_batch_tuning_times(bt)
+        cfg["tuned_tiles"] = {"cfg": tc, "persistent": tp,
+                              "candidates_ms": {f"{d}/{c}/{p}": round(v, 4) for (d, c, p), v in times.items()}}
+    else:
+        cfg["tiles"] = B.cfd_block_tiles(hs[0])
     out = {
         "metric": "grid-point RK3 stage updates/s",
         "value": value,

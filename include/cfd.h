@@ -195,6 +195,23 @@ int cfd_batch_step(cfd_batch* bt, const double* dt_dev, double* const* Qn, doubl
 int cfd_batch_tuning(const cfd_batch* bt, int* cfg, int* persist);
 /* Override the tiling (skips the autotuner; the next step re-captures its graph).       */
 int cfd_batch_set_tuning(cfd_batch* bt, const int* cfg, const int* persist);
+/* Milliseconds per launch that the autotuner measured for each candidate, at
+ * ms[(d * cfd_tile_config_count() + cfg) * 2 + persist] for sweep direction d; -1 where
+ * nothing was measured (the tuner runs on the first step unless cfd_batch_set_tuning
+ * came first).  cap is the length of ms, at least 6 * cfd_tile_config_count().          */
+int cfd_batch_tuning_times(const cfd_batch* bt, float* ms, int cap);
+
+/* ---- sweep tile shapes ----------------------------------------------------------------
+ * A sweep workgroup owns `lines` grid lines across the sweep direction and up to `nodes`
+ * output nodes along it, with `threads` threads.  cfd_tile_config_count() returns the
+ * number of shapes; cfd_tile_config gives shape cfg (CFD_ERR_ARG if out of range).       */
+int cfd_tile_config_count(void);
+int cfd_tile_config(int cfg, int* lines, int* nodes, int* threads);
+/* Tile shape per direction (cfg[0..2] for xi, eta, zeta) of a block's own launches
+ * (cfd_rhs, cfd_rk_stage, cfd_rhs_sweeps, cfd_rk_sweeps).  Every shape gives the same
+ * bits; the default is the library's choice for large blocks.                           */
+int cfd_block_set_tiles(cfd_block* b, const int* cfg);
+int cfd_block_tiles(const cfd_block* b, int* cfg);
 
 /* ---- profiling --------------------------------------------------------------------- */
 /* Enable (1) or disable (0) per-launch HIP event timing of the block's kernels.         */

@@ -89,6 +89,11 @@ def lib():
         "cfd_batch_step": ([_VP, _VP, C.POINTER(_VP), C.POINTER(_VP), C.POINTER(_VP)], C.c_int),
         "cfd_batch_tuning": ([_VP, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
         "cfd_batch_set_tuning": ([_VP, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
+        "cfd_batch_tuning_times": ([_VP, C.POINTER(C.c_float), C.c_int], C.c_int),
+        "cfd_tile_config_count": ([], C.c_int),
+        "cfd_tile_config": ([C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
+        "cfd_block_set_tiles": ([_VP, C.POINTER(C.c_int)], C.c_int),
+        "cfd_block_tiles": ([_VP, C.POINTER(C.c_int)], C.c_int),
         "cfd_profile_enable": ([_VP, C.c_int], C.c_int),
         "cfd_profile_read": ([_VP, C.POINTER(C.c_char_p), C.POINTER(C.c_int64), _DP, C.c_int, C.POINTER(C.c_int)], C.c_int),
         "cfd_profile_reset": ([_VP], C.c_int),
@@ -252,6 +257,36 @@ def cfd_batch_set_tuning(bt: int, cfg, persist) -> None:
     c = (C.c_int * 3)(*cfg)
     p = (C.c_int * 3)(*persist)
     _check(lib().cfd_batch_set_tuning(bt, c, p))
+
+
+def cfd_batch_tuning_times(bt: int):
+    """Autotuner timings as {(direction, cfg, persistent): ms per launch}, measured ones only."""
+    n = cfd_tile_config_count()
+    ms = (C.c_float * (6 * n))()
+    _check(lib().cfd_batch_tuning_times(bt, ms, 6 * n))
+    return {(d, c, p): ms[(d * n + c) * 2 + p] for d in range(3) for c in range(n) for p in range(2)
+            if ms[(d * n + c) * 2 + p] >= 0}
+
+
+def cfd_tile_config_count() -> int:
+    return lib().cfd_tile_config_count()
+
+
+def cfd_tile_config(cfg: int):
+    """(lines across, nodes along the sweep, threads) of tile shape cfg."""
+    a, b, c = C.c_int(), C.c_int(), C.c_int()
+    _check(lib().cfd_tile_config(cfg, C.byref(a), C.byref(b), C.byref(c)))
+    return a.value, b.value, c.value
+
+
+def cfd_block_set_tiles(b: int, cfg) -> None:
+    _check(lib().cfd_block_set_tiles(b, (C.c_int * 3)(*cfg)))
+
+
+def cfd_block_tiles(b: int):
+    cfg = (C.c_int * 3)()
+    _check(lib().cfd_block_tiles(b, cfg))
+    return list(cfg)
 
 
 def cfd_profile_enable(b: int, on: bool = True) -> None:

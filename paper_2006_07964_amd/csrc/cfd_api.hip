@@ -116,6 +116,11 @@ struct ProfScope {
 // =====================================================================================
 // block
 // =====================================================================================
+// tile shapes of a block's own sweeps until cfd_block_set_tiles (the batched autotuner's
+// usual choice on large blocks): 4 lines x 58 nodes along xi, 16 lines x 14 nodes along
+// eta and zeta, 256 threads each
+constexpr int kDefaultTiles[3] = {5, 2, 2};
+
 struct cfd_block {
   cfd_block_desc d;
   Geom g;
@@ -136,6 +141,7 @@ struct cfd_block {
   BcSeg* local_bc_dev = nullptr;
   int n_local_bc = 0, max_local_bc = 0;
   bool has_interface = false;
+  int cfg[3] = {kDefaultTiles[0], kDefaultTiles[1], kDefaultTiles[2]};  // sweep tile shape per direction
   // small device scratch for reductions
   unsigned long long* red_dev = nullptr;
   int* flag_dev = nullptr;
@@ -358,7 +364,8 @@ int run_sweeps(cfd_block* b, const double* Q, unsigned mask, int out_kind, doubl
     a.c.out_kind = out_kind;
     a.b.out = out;
     ProfScope ps(&b->prof, kSweepNames[0], b->stream);
-    hipError_t e = b->d.precision == CFD_FP64 ? launch_sweep<double>(0, a, b->stream) : launch_sweep<float>(0, a, b->stream);
+    hipError_t e = b->d.precision == CFD_FP64 ? launch_sweep<double>(0, a, b->stream, b->cfg[0])
+                                              : launch_sweep<float>(0, a, b->stream, b->cfg[0]);
     ps.done();
     return e == hipSuccess ? CFD_OK : hip_fail(e, "sweep launch");
   }
@@ -371,8 +378,8 @@ int run_sweeps(cfd_block* b, const double* Q, unsigned mask, int out_kind, doubl
     a.b.out = last ? out : nullptr;
     const char* name = (last && out_kind == kOutRK) ? kSweepRkNames[dirs[n]] : kSweepNames[dirs[n]];
     ProfScope ps(&b->prof, name, b->stream);
-    hipError_t e = b->d.precision == CFD_FP64 ? launch_sweep<double>(dirs[n], a, b->stream)
-                                              : launch_sweep<float>(dirs[n], a, b->stream);
+    hipError_t e = b->d.precision == CFD_FP64 ? launch_sweep<double>(dirs[n], a, b->stream, b->cfg[dirs[n]])
+                                              : launch_sweep<float>(dirs[n], a, b->stream, b->cfg[dirs[n]]);
     ps.done();
     if (e != hipSuccess) return hip_fail(e, "sweep launch");
   }
@@ -685,6 +692,7 @@ struct cfd_batch {
   int cfg[3] = {0, 0, 0};       // tile configuration per direction
   int persist[3] = {0, 0, 0};   // persistent schedule per direction
   bool tuned = false;
+  float tune_ms[3][kTileCfgs][2];  // autotuner timings (ms per launch, -1: not measured)
   int persist_wgs = 2048;       // workgroups of a persistent launch
   // combined viscous halo work of all blocks: self-periodic + interface copies, ghosts
   CopySeg* vcopy_dev = nullptr;
@@ -767,6 +775,10 @@ int batch_create(cfd_block* const* blocks, int nb, cfd_exchange* x, void* hip_st
   }
   bt->precision = blocks[0]->d.precision;
   bt->viscous = blocks[0]->d.params.viscous != 0;
+  for (int d = 0; d < 3; ++d) {
+    bt->cfg[d] = kDefaultTiles[d];
+    for (int c = 0; c < kTileCfgs; ++c) bt->tune_ms[d][c][0] = bt->tune_ms[d][c][1] = -1.f;
+  }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, blocks[0]->device) == hipSuccess) bt->persist_wgs = prop.multiProcessorCount * 8;
   // viscous halo work of the whole batch
@@ -949,6 +961,7 @@ int autotune(cfd_batch* bt, double* const* Qn, double* const* QA, double* const*
           if (e != hipSuccess) rc = hip_fail(e, "tuning launch");
           if (rep > 0) total += ms;  // first launch warms caches and code
         }
+        if (rc == CFD_OK) bt->tune_ms[d][c][p] = total / 2;
         if (rc == CFD_OK && total < best) {
           best = total;
           best_cfg = c;
@@ -1018,6 +1031,15 @@ int batch_tuning(const cfd_batch* bt, int* cfg, int* persist) {
     cfg[d] = bt->cfg[d];
     persist[d] = bt->persist[d];
   }
+  return CFD_OK;
+}
+
+int batch_tuning_times(const cfd_batch* bt, float* ms, int cap) {
+  if (!bt || !ms) return fail(CFD_ERR_ARG, "null argument");
+  if (cap < 6 * kTileCfgs) return fail(CFD_ERR_ARG, "timing array too short");
+  for (int d = 0; d < 3; ++d)
+    for (int c = 0; c < kTileCfgs; ++c)
+      for (int p = 0; p < 2; ++p) ms[(d * kTileCfgs + c) * 2 + p] = bt->tune_ms[d][c][p];
   return CFD_OK;
 }
 
@@ -1163,5 +1185,29 @@ int cfd_batch_step(cfd_batch* bt, const double* dt_dev, double* const* Qn, doubl
 }
 int cfd_batch_tuning(const cfd_batch* bt, int* cfg, int* persist) { return batch_tuning(bt, cfg, persist); }
 int cfd_batch_set_tuning(cfd_batch* bt, const int* cfg, const int* persist) { return batch_set_tuning(bt, cfg, persist); }
+int cfd_batch_tuning_times(const cfd_batch* bt, float* ms, int cap) { return batch_tuning_times(bt, ms, cap); }
+
+int cfd_tile_config_count(void) { return kTileCfgs; }
+
+int cfd_tile_config(int cfg, int* lines, int* nodes, int* threads) {
+  if (cfg < 0 || cfg >= kTileCfgs) return fail(CFD_ERR_ARG, "tile configuration out of range");
+  if (!lines || !nodes || !threads) return fail(CFD_ERR_ARG, "null argument");
+  tile_shape(cfg, lines, nodes, threads);
+  return CFD_OK;
+}
+
+int cfd_block_set_tiles(cfd_block* b, const int* cfg) {
+  if (!b || !cfg) return fail(CFD_ERR_ARG, "null argument");
+  for (int d = 0; d < 3; ++d)
+    if (cfg[d] < 0 || cfg[d] >= kTileCfgs) return fail(CFD_ERR_ARG, "tile configuration out of range");
+  for (int d = 0; d < 3; ++d) b->cfg[d] = cfg[d];
+  return CFD_OK;
+}
+
+int cfd_block_tiles(const cfd_block* b, int* cfg) {
+  if (!b || !cfg) return fail(CFD_ERR_ARG, "null argument");
+  for (int d = 0; d < 3; ++d) cfg[d] = b->cfg[d];
+  return CFD_OK;
+}
 
 }  // extern "C"

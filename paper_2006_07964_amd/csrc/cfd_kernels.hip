@@ -573,10 +573,20 @@ template <>
 struct TileCfg<3> {
   static constexpr int TW = 8, TS = 62, NT = 512;
 };
+template <>
+struct TileCfg<4> {
+  static constexpr int TW = 8, TS = 26, NT = 256;
+};
+template <>
+struct TileCfg<5> {
+  static constexpr int TW = 4, TS = 58, NT = 256;
+};
 
 void sweep_tiling(int dir, int cfg, const Geom& g, int* tiles_c1, int* tiles_d, int* tile_len) {
-  static const int tw[kTileCfgs] = {TileCfg<0>::TW, TileCfg<1>::TW, TileCfg<2>::TW, TileCfg<3>::TW};
-  static const int tsz[kTileCfgs] = {TileCfg<0>::TS, TileCfg<1>::TS, TileCfg<2>::TS, TileCfg<3>::TS};
+  static const int tw[kTileCfgs] = {TileCfg<0>::TW, TileCfg<1>::TW, TileCfg<2>::TW,
+                                    TileCfg<3>::TW, TileCfg<4>::TW, TileCfg<5>::TW};
+  static const int tsz[kTileCfgs] = {TileCfg<0>::TS, TileCfg<1>::TS, TileCfg<2>::TS,
+                                     TileCfg<3>::TS, TileCfg<4>::TS, TileCfg<5>::TS};
   const int nd = dir == 0 ? g.ni : dir == 1 ? g.nj : g.nk;
   const int n1 = dir == 0 ? g.nj : g.ni;
   *tiles_c1 = (n1 + tw[cfg] - 1) / tw[cfg];
@@ -584,8 +594,19 @@ void sweep_tiling(int dir, int cfg, const Geom& g, int* tiles_c1, int* tiles_d, 
   *tile_len = (nd + *tiles_d - 1) / *tiles_d;  // balanced tiles along the sweep
 }
 
+void tile_shape(int cfg, int* tw, int* ts, int* nt) {
+  static const int w[kTileCfgs] = {TileCfg<0>::TW, TileCfg<1>::TW, TileCfg<2>::TW,
+                                   TileCfg<3>::TW, TileCfg<4>::TW, TileCfg<5>::TW};
+  static const int l[kTileCfgs] = {TileCfg<0>::TS, TileCfg<1>::TS, TileCfg<2>::TS,
+                                   TileCfg<3>::TS, TileCfg<4>::TS, TileCfg<5>::TS};
+  *tw = w[cfg];
+  *ts = l[cfg];
+  *nt = sweep_threads(cfg);
+}
+
 int sweep_threads(int cfg) {
-  static const int nt[kTileCfgs] = {TileCfg<0>::NT, TileCfg<1>::NT, TileCfg<2>::NT, TileCfg<3>::NT};
+  static const int nt[kTileCfgs] = {TileCfg<0>::NT, TileCfg<1>::NT, TileCfg<2>::NT,
+                                    TileCfg<3>::NT, TileCfg<4>::NT, TileCfg<5>::NT};
   return nt[cfg];
 }
 
@@ -613,6 +634,8 @@ hipError_t launch_sweep(int dir, SweepArgs a, hipStream_t s, int cfg) {
     case 1: return launch_sweep_cfg<R, 1>(dir, a, nwg, s);
     case 2: return launch_sweep_cfg<R, 2>(dir, a, nwg, s);
     case 3: return launch_sweep_cfg<R, 3>(dir, a, nwg, s);
+    case 4: return launch_sweep_cfg<R, 4>(dir, a, nwg, s);
+    case 5: return launch_sweep_cfg<R, 5>(dir, a, nwg, s);
   }
   return hipErrorInvalidValue;
 }
@@ -642,6 +665,8 @@ hipError_t launch_sweep_batch(int dir, int cfg, bool persist, const SweepBlock* 
       case 1: return launch_sweep_batch_cfg<R, 1, true>(dir, blocks, c, tl, nwg, s);
       case 2: return launch_sweep_batch_cfg<R, 2, true>(dir, blocks, c, tl, nwg, s);
       case 3: return launch_sweep_batch_cfg<R, 3, true>(dir, blocks, c, tl, nwg, s);
+      case 4: return launch_sweep_batch_cfg<R, 4, true>(dir, blocks, c, tl, nwg, s);
+      case 5: return launch_sweep_batch_cfg<R, 5, true>(dir, blocks, c, tl, nwg, s);
     }
   } else {
     switch (cfg) {
@@ -649,6 +674,8 @@ hipError_t launch_sweep_batch(int dir, int cfg, bool persist, const SweepBlock* 
       case 1: return launch_sweep_batch_cfg<R, 1, false>(dir, blocks, c, tl, nwg, s);
       case 2: return launch_sweep_batch_cfg<R, 2, false>(dir, blocks, c, tl, nwg, s);
       case 3: return launch_sweep_batch_cfg<R, 3, false>(dir, blocks, c, tl, nwg, s);
+      case 4: return launch_sweep_batch_cfg<R, 4, false>(dir, blocks, c, tl, nwg, s);
+      case 5: return launch_sweep_batch_cfg<R, 5, false>(dir, blocks, c, tl, nwg, s);
     }
   }
   return hipErrorInvalidValue;

@@ -69,7 +69,9 @@ struct SweepArgs {
   SweepCommon c;
   SweepBlock b;
 };
-constexpr int kTileCfgs = 4;  // sweep tile configurations (see TileCfg in cfd_kernels.hip)
+constexpr int kTileCfgs = 6;
+// shape of tile configuration cfg (lines across, nodes along the sweep, threads)
+void tile_shape(int cfg, int* tw, int* ts, int* nt);  // sweep tile configurations (see TileCfg in cfd_kernels.hip)
 // tiles of one block for direction dir under configuration cfg
 void sweep_tiling(int dir, int cfg, const Geom& g, int* tiles_c1, int* tiles_d, int* tile_len);
 int sweep_threads(int cfg);

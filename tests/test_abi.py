@@ -90,3 +90,16 @@ def test_oracle_exports():
     for n in ("oracle_metrics", "oracle_rhs", "oracle_rk_stage", "oracle_rk_step", "oracle_dt_cfl",
               "oracle_exchange", "oracle_rhs_multi", "oracle_rk_step_multi", "oracle_wall_reset", "oracle_bc_fill"):
         assert hasattr(L, n), n
+
+
+def test_tile_configurations(lib):
+    n = B.cfd_tile_config_count()
+    assert n >= 4
+    for cfg in range(n):
+        lines, nodes, threads = B.cfd_tile_config(cfg)
+        assert lines >= 1 and nodes >= 6 and threads % 64 == 0
+        # the items of one tile fill the workgroup at most a few times over
+        assert lines * (nodes + 6) <= 4 * threads
+    for bad in (-1, n):
+        with pytest.raises(B.CfdError):
+            B.cfd_tile_config(bad)

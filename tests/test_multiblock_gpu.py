@@ -103,6 +103,11 @@ def test_o_grid_batched_graph_matches_oracle_and_per_block():
     wl = W.o_grid_vortices(sizes=SMALL_OGRID)
     dev, _ = _run_compare(wl, 3, batch=True)
     ref = DevMulti(wl)
+    # the per-block launches use the tile shapes the autotuner chose (the same shape gives
+    # the same bits; different shapes agree to round-off)
+    cfg, _ = B.cfd_batch_tuning(dev.bt)
+    for h in ref.h:
+        B.cfd_block_set_tiles(h, cfg)
     try:
         cfgs, mets, qs = oracle_multi(wl)
         dt = min(O.dt_cfl(c, m, q, wl.cfl) for c, m, q in zip(cfgs, mets, qs))
@@ -111,7 +116,7 @@ def test_o_grid_batched_graph_matches_oracle_and_per_block():
         for bi in range(len(wl.blocks)):
             np.testing.assert_array_equal(ref.host(bi), dev.host(bi))
         cfg, per = B.cfd_batch_tuning(dev.bt)
-        print("tuned tiles", cfg, per)
+        print("tuned tiles", cfg, per, B.cfd_batch_tuning_times(dev.bt))
         # more replays, each checked against the eager per-block path
         dt_dev = torch.tensor([dt], dtype=torch.float64, device="cuda")
         for _ in range(3):
@@ -126,12 +131,16 @@ def test_o_grid_batched_graph_matches_oracle_and_per_block():
         dev.close()
 
 
-@pytest.mark.parametrize("cfg,persist", [((1, 2, 3), (0, 1, 0)), ((3, 0, 1), (1, 0, 1))])
+@pytest.mark.parametrize("cfg,persist", [((1, 2, 3), (0, 1, 0)), ((3, 0, 1), (1, 0, 1)), ((4, 5, 4), (0, 1, 1)),
+                                         ((5, 4, 5), (1, 0, 0))])
 def test_batched_tilings_agree(cfg, persist):
-    """Every tile configuration and schedule gives the same bits."""
+    """The batched launches with a given tile shape per direction, under both schedules,
+    give the same bits as the per-block launches with those shapes."""
     import torch
     wl = W.o_grid_vortices(sizes=SMALL_OGRID)
     a, b = DevMulti(wl), DevMulti(wl)
+    for h in a.h:
+        B.cfd_block_set_tiles(h, cfg)
     try:
         cfgs, mets, qs = oracle_multi(wl)
         dt = min(O.dt_cfl(c, m, q, wl.cfl) for c, m, q in zip(cfgs, mets, qs))

@@ -199,6 +199,41 @@ def test_deterministic():
         dev.close()
 
 
+def test_every_tile_shape_agrees():
+    """A ragged block (tiles cut unevenly along every direction): RHS and one RK step with
+    each sweep tile shape against the default shape.  The arithmetic per node does not
+    depend on the tile, but each shape is a separately compiled kernel whose multiply-add
+    contraction may differ, so the comparison allows round-off (normwise 1e-13)."""
+    wl = _vortex(37, 29, 23)
+    dev = DevBlock(wl, pitched=True)
+    try:
+        ref = dev.rhs().copy()
+        dt = 1e-3
+        q0 = dev.q.clone()
+        dev.step(dt)
+        ref_q = dev.host(dev.q).copy()
+        for cfg in range(B.cfd_tile_config_count()):
+            B.cfd_block_set_tiles(dev.h, [cfg, cfg, cfg])
+            assert B.cfd_block_tiles(dev.h) == [cfg, cfg, cfg]
+            dev.q.copy_(q0)
+            got = dev.rhs()
+            diff = got != ref
+            print(f"tile shape {cfg} {B.cfd_tile_config(cfg)}: {int(diff.sum())} RHS values differ, "
+                  f"vector error {vector_norm_err(got, ref):.2e}")
+            if diff.any():
+                idx = np.argwhere(diff)
+                for ax, name in ((3, "i"), (2, "j"), (1, "k")):
+                    vals, cnt = np.unique(idx[:, ax] - 3, return_counts=True)
+                    print(f"   along {name}: {dict(zip(vals.tolist(), cnt.tolist()))}")
+            assert vector_norm_err(got, ref) < 1e-13
+            dev.step(dt)
+            err = normwise(dev.host(dev.q), ref_q)
+            print(f"   one RK step: normwise {err}")
+            assert np.all(err < 1e-13)
+    finally:
+        dev.close()
+
+
 def test_argument_and_state_errors():
     import torch
     wl = _vortex(16, 16, 16)
