@@ -367,6 +367,52 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
   const GP<const double> my = plane_ptr(met, (3 * DIR + 1) * plane);
   const GP<const double> mz = plane_ptr(met, (3 * DIR + 2) * plane);
 
+  // ---- the output node of this thread (at most one per thread) and its global operands,
+  // requested before the last barrier so that their latency overlaps the nodal-flux phase
+  static_assert(TW * TS <= NT, "one output node per thread");
+  const GP<const R> vis = to_global(static_cast<const R*>(b.vis)) + (4 * DIR) * plane;
+  const GP<const R> rin = to_global(static_cast<const R*>(b.rt_in));
+  const int eo = threadIdx.x;
+  const int so = DIR == 0 ? eo % TS : eo / TW;
+  const int wo = DIR == 0 ? eo / TS : eo % TW;
+  const bool out_here = eo < TW * TS && so < ts && c1_0 + wo < n1 && d0 + so < nd;
+  const uint32_t po = origin + (uint32_t)(c1_0 + wo) * s1 + (uint32_t)(d0 + so) * sd;
+  R vm[4][6];  // viscous fluxes of the direction at offsets -3, -2, -1, 1, 2, 3
+  R rp[5];     // partial sums of the earlier directions
+  double Jo = 0.0, qno[5], qco[5];
+  auto fetch = [&]() {
+    if (!out_here) return;
+    if (c.do_vis) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const GP<const R> vp = plane_ptr(vis, v * plane);
+#pragma unroll
+        for (int m = 0; m < 6; ++m) vm[v][m] = ldg(vp, po + (uint32_t)(m < 3 ? m - 3 : m - 2) * sd);
+      }
+    }
+    if (c.has_prev) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) rp[v] = ldg(plane_ptr(rin, v * plane), po);
+    }
+    if (c.out_kind != kOutPartial) Jo = ldg(plane_ptr(met, 9 * plane), po);
+    if (c.out_kind == kOutRK) {
+      // Q at the output node (an FP64 inviscid sweep took it from the staged tile already)
+      if (!(sizeof(R) == 8 && c.do_inv)) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) qco[v] = ldg(plane_ptr(Q, v * plane), po);
+      }
+      // stage 0 has Qn = Q
+      if (b.qn == b.q) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) qno[v] = qco[v];
+      } else {
+        const GP<const double> qn = to_global(b.qn);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) qno[v] = ldg(plane_ptr(qn, v * plane), po);
+      }
+    }
+  };
+
   if (c.do_inv) {
     // ---- stage Q (compute type) and the sweep direction's node metrics (FP64) of nodes
     // d0-3 .. d0+ts+2 of the tile's lines in LDS; sFn holds Q until the nodal fluxes
@@ -436,7 +482,14 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
         for (int v = 0; v < 5; ++v) sFm[L::f(v, w, s - 1, NH)] = F[v];
       }
     }
+    // in FP64 the staged Q is exact: the output node's copy for the RK combination is read
+    // here, before the barrier after which the nodal fluxes overwrite it
+    if (sizeof(R) == 8 && c.out_kind == kOutRK && out_here) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) qco[v] = double(sFn[L::f(v, wo, so + 3, NN)]);
+    }
     __syncthreads();
+    fetch();
     // ---- nodal fluxes, Eq 4, in place of the staged Q ------------------------------------
     for (int e = threadIdx.x; e < TW * NN; e += NT) {
       const int s = DIR == 0 ? e % NN : e / TW;
@@ -454,59 +507,46 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
     __syncthreads();
   }
 
-  // ---- assembly per output node ---------------------------------------------------------
-  const GP<const R> vis = to_global(static_cast<const R*>(b.vis)) + (4 * DIR) * plane;
-  const GP<const R> rin = to_global(static_cast<const R*>(b.rt_in));
-  for (int e = threadIdx.x; e < TW * TS; e += NT) {
-    const int s = DIR == 0 ? e % TS : e / TW;
-    const int w = DIR == 0 ? e / TS : e % TW;
-    const int n = d0 + s;
-    const int c1 = c1_0 + w;
-    if (s >= ts || c1 >= n1 || n >= nd) continue;
-    const uint32_t p = origin + (uint32_t)c1 * s1 + (uint32_t)n * sd;
-    R r[5];
+  // ---- assembly at the output node ------------------------------------------------------
+  if (!c.do_inv) fetch();
+  if (!out_here) return;
+  const int s = so, w = wo;
+  R r[5];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) r[v] = R(0);
-    if (c.do_inv) {
+  for (int v = 0; v < 5; ++v) r[v] = R(0);
+  if (c.do_inv) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        const R fp = sFp[L::f(v, w, s + 1, NH)] + sFm[L::f(v, w, s + 1, NH)];
-        const R fm = sFp[L::f(v, w, s, NH)] + sFm[L::f(v, w, s, NH)];
-        const R D = fp - fm + R(17.0 / 256.0) * (sFn[L::f(v, w, s + 4, NN)] - sFn[L::f(v, w, s + 2, NN)]) -
-                    R(13.0 / 320.0) * (sFn[L::f(v, w, s + 5, NN)] - sFn[L::f(v, w, s + 1, NN)]) +
-                    R(19.0 / 3840.0) * (sFn[L::f(v, w, s + 6, NN)] - sFn[L::f(v, w, s, NN)]);
-        r[v] = -D;
-      }
+    for (int v = 0; v < 5; ++v) {
+      const R fp = sFp[L::f(v, w, s + 1, NH)] + sFm[L::f(v, w, s + 1, NH)];
+      const R fm = sFp[L::f(v, w, s, NH)] + sFm[L::f(v, w, s, NH)];
+      const R D = fp - fm + R(17.0 / 256.0) * (sFn[L::f(v, w, s + 4, NN)] - sFn[L::f(v, w, s + 2, NN)]) -
+                  R(13.0 / 320.0) * (sFn[L::f(v, w, s + 5, NN)] - sFn[L::f(v, w, s + 1, NN)]) +
+                  R(19.0 / 3840.0) * (sFn[L::f(v, w, s + 6, NN)] - sFn[L::f(v, w, s, NN)]);
+      r[v] = -D;
     }
-    if (c.do_vis) {
+  }
+  if (c.do_vis) {
 #pragma unroll
-      for (int v = 1; v < 5; ++v) {
-        const GP<const R> vp = plane_ptr(vis, (v - 1) * plane);
-        r[v] += d6<R>([&](int m) { return ldg(vp, p + (uint32_t)m * sd); });
-      }
-    }
-    if (c.has_prev) {
+    for (int v = 1; v < 5; ++v) r[v] += d6<R>([&](int m) { return vm[v - 1][m < 0 ? m + 3 : m + 2]; });
+  }
+  if (c.has_prev) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) r[v] += ldg(plane_ptr(rin, v * plane), p);
-    }
-    if (c.out_kind == kOutPartial) {
-      const GP<R> ro = to_global(static_cast<R*>(b.rt_out));
+    for (int v = 0; v < 5; ++v) r[v] += rp[v];
+  }
+  if (c.out_kind == kOutPartial) {
+    const GP<R> ro = to_global(static_cast<R*>(b.rt_out));
 #pragma unroll
-      for (int v = 0; v < 5; ++v) stg(plane_ptr(ro, v * plane), p, r[v]);
+    for (int v = 0; v < 5; ++v) stg(plane_ptr(ro, v * plane), po, r[v]);
+  } else {
+    const GP<double> out = to_global(b.out);
+    if (c.out_kind == kOutRhs) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) stg(plane_ptr(out, v * plane), po, Jo * double(r[v]));
     } else {
-      const double J = ldg(plane_ptr(met, 9 * plane), p);
-      const GP<double> out = to_global(b.out);
-      if (c.out_kind == kOutRhs) {
+      const double dt = c.dt_dev ? *c.dt_dev : c.dt;
+      const double cdt = c.cc * dt * Jo;
 #pragma unroll
-        for (int v = 0; v < 5; ++v) stg(plane_ptr(out, v * plane), p, J * double(r[v]));
-      } else {
-        const double dt = c.dt_dev ? *c.dt_dev : c.dt;
-        const double cdt = c.cc * dt * J;
-        const GP<const double> qn = to_global(b.qn);
-#pragma unroll
-        for (int v = 0; v < 5; ++v)
-          stg(plane_ptr(out, v * plane), p, c.ca * ldg(plane_ptr(qn, v * plane), p) + c.cb * ldg(plane_ptr(Q, v * plane), p) + cdt * double(r[v]));
-      }
+      for (int v = 0; v < 5; ++v) stg(plane_ptr(out, v * plane), po, c.ca * qno[v] + c.cb * qco[v] + cdt * double(r[v]));
     }
   }
 }
