@@ -129,7 +129,9 @@ struct cfd_block {
   double* met = nullptr;  // 10 planes FP64
   void* vis = nullptr;    // 12 planes (compute type)
   void* rt = nullptr;     // 5 planes (compute type)
-  void* met_raw = nullptr;  // allocations behind met, vis, rt (see aligned_planes)
+  void* met_r = nullptr;  // metrics in the compute type: met itself (FP64) or a rounded copy (mixed)
+  void* met_raw = nullptr;  // allocations behind met, met_r, vis, rt (see aligned_planes)
+  void* met_r_raw = nullptr;
   void* vis_raw = nullptr;
   void* rt_raw = nullptr;
   size_t esize = 8;       // bytes of the compute type
@@ -305,6 +307,7 @@ int run_visc(cfd_block* b, const double* Q) {
   va.g = b->g;
   va.q = Q;
   va.met = b->met;
+  va.met_r = b->met_r;
   va.vis = b->vis;
   va.ph = make_phys(b->d.params);
   ProfScope ps(&b->prof, "visc_prepass", b->stream);
@@ -429,12 +432,15 @@ int cfd_block_create(const cfd_block_desc* d, void* hip_stream, cfd_block** out)
   void* mbase = nullptr;
   if (aligned_planes(plane, 10, sizeof(double), &b->met_raw, &mbase)) return cleanup(CFD_ERR_ALLOC, "metrics allocation");
   b->met = static_cast<double*>(mbase);
+  b->met_r = b->met;
+  if (b->esize != sizeof(double) && aligned_planes(plane, 10, b->esize, &b->met_r_raw, &b->met_r))
+    return cleanup(CFD_ERR_ALLOC, "metrics allocation");
   if (aligned_planes(plane, 12, b->esize, &b->vis_raw, &b->vis)) return cleanup(CFD_ERR_ALLOC, "viscous scratch allocation");
   if (aligned_planes(plane, 5, b->esize, &b->rt_raw, &b->rt)) return cleanup(CFD_ERR_ALLOC, "partial-sum allocation");
   if (hipMalloc((void**)&b->red_dev, sizeof(unsigned long long)) != hipSuccess ||
       hipMalloc((void**)&b->flag_dev, sizeof(int)) != hipSuccess)
     return cleanup(CFD_ERR_ALLOC, "reduction scratch");
-  b->bytes = (int64_t)plane * (10 * 8 + 17 * (int64_t)b->esize);
+  b->bytes = (int64_t)plane * (10 * 8 + (b->esize == sizeof(double) ? 17 : 27) * (int64_t)b->esize);
   // block-local viscous halo work
   std::vector<CopySeg> cs;
   std::vector<BcSeg> bs;
@@ -463,6 +469,7 @@ int cfd_block_destroy(cfd_block* b) {
   else (void)hipDeviceSynchronize();
   b->prof.drain();
   (void)hipFree(b->met_raw);
+  (void)hipFree(b->met_r_raw);
   (void)hipFree(b->vis_raw);
   (void)hipFree(b->rt_raw);
   (void)hipFree(b->red_dev);
@@ -501,6 +508,9 @@ int cfd_metrics(cfd_block* b, const double* xyz, int64_t cld_i, int64_t cld_j) {
   int rc = CFD_OK;
   hipError_t e = hipMemsetAsync(b->flag_dev, 0, sizeof(int), b->stream);
   if (e == hipSuccess) e = launch_metrics(a, b->stream);
+  // the FP32 consumers of a mixed block read the metrics rounded once here
+  if (e == hipSuccess && b->met_r != b->met)
+    e = launch_round(b->met, static_cast<float*>(b->met_r), (int64_t)10 * b->g.plane, b->stream);
   int bad = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&bad, b->flag_dev, sizeof(int), hipMemcpyDeviceToHost, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
@@ -732,7 +742,7 @@ void fill_tiles(cfd_batch* bt) {
   bt->visc_tl.prefix[0] = 0;
   for (int b = 0; b < nb; ++b) {
     int kc, t;
-    visc_tiling(bt->blocks[b]->g, &kc, &t);
+    visc_tiling(bt->blocks[b]->g, 0, &kc, &t);
     bt->visc_tl.prefix[b + 1] = bt->visc_tl.prefix[b] + t;
   }
   for (int d = 0; d < 3; ++d) {
@@ -842,10 +852,11 @@ void build_args(cfd_batch* bt, double* const* Qn, double* const* QA, double* con
       v.g = B->g;
       v.q = cur[b];
       v.met = B->met;
+      v.met_r = B->met_r;
       v.vis = B->vis;
       v.ph = ph;
       int tiles;
-      visc_tiling(B->g, &v.kc, &tiles);
+      visc_tiling(B->g, 0, &v.kc, &tiles);  // the batch list is long enough
       for (int d = 0; d < 3; ++d) {
         SweepBlock& a = sa[(st * 3 + d) * nb + b];
         std::memset(&a, 0, sizeof a);

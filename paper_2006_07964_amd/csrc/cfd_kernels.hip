@@ -125,7 +125,8 @@ hipError_t launch_metrics(const MetricArgs& a, hipStream_t s) {
 // read once per column.
 // =====================================================================================
 constexpr int VI = 64, VJ = 8, VNT = VI * VJ;
-constexpr int kViscChunk = 16;  // planes per workgroup (fewer when nk is smaller)
+constexpr int kViscChunk = 32;      // planes per workgroup (fewer when nk is smaller)
+constexpr int kViscMinTiles = 1024;  // workgroups a single-block launch aims for
 
 template <typename R>
 struct ViscShared {
@@ -188,7 +189,8 @@ __device__ __forceinline__ void visc_tile(const ViscArgs& a, int t, ViscShared<R
   const uint32_t ph = (uint32_t)at(g, hval ? hi : 0, hval ? hj : 0, 0);
 
   const R gg = R(a.ph.gamma) * (R(a.ph.gamma) - R(1));
-  const GP<const double> Q = to_global(a.q), met = to_global(a.met);
+  const GP<const double> Q = to_global(a.q);
+  const GP<const R> met = to_global(static_cast<const R*>(a.met_r));
   const GP<R> out = to_global(static_cast<R*>(a.vis));
   const int64_t plane = g.plane;
   R P[7][4];  // own column, planes k-3 .. k+3
@@ -222,8 +224,8 @@ __device__ __forceinline__ void visc_tile(const ViscArgs& a, int t, ViscShared<R
 #pragma unroll
       for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) mh[d][c] = R(ldg(plane_ptr(met, (3 * d + c) * plane), p));
-      const R J = R(ldg(plane_ptr(met, 9 * plane), p));
+        for (int c = 0; c < 3; ++c) mh[d][c] = ldg(plane_ptr(met, (3 * d + c) * plane), p);
+      const R J = ldg(plane_ptr(met, 9 * plane), p);
       R dx[4][3];  // d(u, v, w, T)/d(x, y, z), Eq 21
 #pragma unroll
       for (int n = 0; n < 4; ++n)
@@ -265,10 +267,26 @@ __global__ __launch_bounds__(VNT) __attribute__((amdgpu_waves_per_eu(4))) void k
   visc_tile<R>(a, xcd_remap(blockIdx.x, gridDim.x), sh);
 }
 
-// chunk length and tile count of one block: i-tile fastest, then j-tile, then k-chunk
-void visc_tiling(const Geom& g, int* kc, int* tiles) {
-  *kc = g.nk < kViscChunk ? g.nk : kViscChunk;
-  *tiles = ((g.ni + VI - 1) / VI) * ((g.nj + VJ - 1) / VJ) * ((g.nk + *kc - 1) / *kc);
+__global__ __launch_bounds__(256) void k_round(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) dst[e] = float(src[e]);
+}
+
+hipError_t launch_round(const double* src, float* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nwg = (n + 255) / 256;
+  hipLaunchKernelGGL(k_round, dim3((unsigned)(nwg < 65536 ? nwg : 65536)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+// chunk length and tile count of one block (i-tile fastest, then j-tile, then k-chunk):
+// kViscChunk planes per tile, halved (down to 8) while the block would give fewer than
+// min_tiles workgroups; a longer chunk re-reads fewer priming planes, more tiles fill the chip
+void visc_tiling(const Geom& g, int min_tiles, int* kc, int* tiles) {
+  const int cols = ((g.ni + VI - 1) / VI) * ((g.nj + VJ - 1) / VJ);
+  int c = kViscChunk;
+  while (c > 8 && cols * ((g.nk + c - 1) / c) < min_tiles) c /= 2;
+  *kc = g.nk < c ? g.nk : c;
+  *tiles = cols * ((g.nk + *kc - 1) / *kc);
 }
 
 // one workgroup per tile of the concatenated list (ids remapped XCD-contiguously)
@@ -284,7 +302,7 @@ __global__ __launch_bounds__(VNT) __attribute__((amdgpu_waves_per_eu(4))) void k
 template <typename R>
 hipError_t launch_visc(ViscArgs a, hipStream_t s) {
   int tiles;
-  visc_tiling(a.g, &a.kc, &tiles);
+  visc_tiling(a.g, kViscMinTiles, &a.kc, &tiles);
   hipLaunchKernelGGL(k_visc<R>, dim3(tiles), dim3(VNT), 0, s, a);
   return hipGetLastError();
 }
@@ -331,8 +349,8 @@ struct SweepLds {
 // One tile of a direction sweep: t is the logical tile index inside the block (sweep-
 // direction tile fastest, then the cross tile c1, then the cross index c2).
 template <int DIR, typename R, int TW, int TS, int NT>
-__device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBlock& b, int t, R* sFp, R* sFm,
-                                           R* sFn, double* sM) {
+__device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBlock& b, int t, R* sF, R* sFn,
+                                           double* sM) {
   constexpr int NH = SweepLds<TW, TS>::NH;
   constexpr int NN = SweepLds<TW, TS>::NN;
   constexpr int NW = SweepLds<TW, TS>::NW;
@@ -432,17 +450,19 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
       sM[L::f(2, w, s, NN)] = ldg(mz, p);
     }
     __syncthreads();
-    // ---- characteristic WENO pair and split fluxes; node n = d0-1+s sits at staged
-    // index s+2 ------------------------------------------------------------------------
-    for (int e = threadIdx.x; e < TW * NW; e += NT) {
-      const int s = DIR == 0 ? e % NW : e / TW;
-      const int w = DIR == 0 ? e / NW : e % TW;
-      const int n = d0 - 1 + s;
-      const int c1 = c1_0 + w;
-      if (s >= nw || c1 >= n1 || n > nd) continue;
-      const bool need_p = s <= ts && n <= nd - 1;  // F+ at n+1/2
-      const bool need_m = s >= 1;                  // F- at n-1/2
-      if (!need_p && !need_m) continue;
+    // ---- characteristic WENO pair and split fluxes (one node per thread); node n = d0-1+s
+    // sits at staged index s+2.  F+ at n+1/2 goes to LDS now; F- at n-1/2 is added to the
+    // same interface after the barrier, so sF holds f(n+1/2) = F+(n) + F-(n+1). ----------
+    static_assert(TW * NW <= NT, "one WENO node per thread");
+    R Fkeep[5];
+    const int ew = threadIdx.x;
+    const int sw_ = DIR == 0 ? ew % NW : ew / TW;
+    const int ww = DIR == 0 ? ew / NW : ew % TW;
+    const bool wvalid = ew < TW * NW && sw_ < nw && c1_0 + ww < n1 && d0 - 1 + sw_ <= nd;
+    const bool need_p = wvalid && sw_ <= ts && d0 - 1 + sw_ <= nd - 1;  // F+ at n+1/2
+    const bool need_m = wvalid && sw_ >= 1;                             // F- at n-1/2
+    if (need_p || need_m) {
+      const int s = sw_, w = ww;
       const int sc = s + 2;
       R q0[5];
 #pragma unroll
@@ -468,18 +488,16 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
         const R hz = R(half_metric([&](int m) { return sM[L::f(2, w, sc + m, NN)]; }));
         sw_flux<+1>(ul, hx, hy, hz, G, F);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) sFp[L::f(v, w, s, NH)] = F[v];
+        for (int v = 0; v < 5; ++v) sF[L::f(v, w, s, NH)] = F[v];
       }
       if (need_m) {
-        R ur[5], F[5];
+        R ur[5];
         unproject(B, G, vr, ur);
         // half point n-1/2 = (n-1)+1/2, centred on staged index sc-1
         const R hx = R(half_metric([&](int m) { return sM[L::f(0, w, sc - 1 + m, NN)]; }));
         const R hy = R(half_metric([&](int m) { return sM[L::f(1, w, sc - 1 + m, NN)]; }));
         const R hz = R(half_metric([&](int m) { return sM[L::f(2, w, sc - 1 + m, NN)]; }));
-        sw_flux<-1>(ur, hx, hy, hz, G, F);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) sFm[L::f(v, w, s - 1, NH)] = F[v];
+        sw_flux<-1>(ur, hx, hy, hz, G, Fkeep);
       }
     }
     // in FP64 the staged Q is exact: the output node's copy for the RK combination is read
@@ -489,6 +507,10 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
       for (int v = 0; v < 5; ++v) qco[v] = double(sFn[L::f(v, wo, so + 3, NN)]);
     }
     __syncthreads();
+    if (need_m) {  // each interface receives exactly one F-
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sF[L::f(v, ww, sw_ - 1, NH)] += Fkeep[v];
+    }
     fetch();
     // ---- nodal fluxes, Eq 4, in place of the staged Q ------------------------------------
     for (int e = threadIdx.x; e < TW * NN; e += NT) {
@@ -517,8 +539,8 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
   if (c.do_inv) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      const R fp = sFp[L::f(v, w, s + 1, NH)] + sFm[L::f(v, w, s + 1, NH)];
-      const R fm = sFp[L::f(v, w, s, NH)] + sFm[L::f(v, w, s, NH)];
+      const R fp = sF[L::f(v, w, s + 1, NH)];
+      const R fm = sF[L::f(v, w, s, NH)];
       const R D = fp - fm + R(17.0 / 256.0) * (sFn[L::f(v, w, s + 4, NN)] - sFn[L::f(v, w, s + 2, NN)]) -
                   R(13.0 / 320.0) * (sFn[L::f(v, w, s + 5, NN)] - sFn[L::f(v, w, s + 1, NN)]) +
                   R(19.0 / 3840.0) * (sFn[L::f(v, w, s + 6, NN)] - sFn[L::f(v, w, s, NN)]);
@@ -554,8 +576,7 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
 // LDS of one workgroup for the largest tile configuration in use.
 template <typename R, int TW, int TS>
 struct SweepShared {
-  R Fp[5 * TW * SweepLds<TW, TS>::NH];
-  R Fm[5 * TW * SweepLds<TW, TS>::NH];
+  R F[5 * TW * SweepLds<TW, TS>::NH];  // interface fluxes f(n+1/2)
   R Fn[5 * TW * SweepLds<TW, TS>::NN];
   double M[3 * TW * SweepLds<TW, TS>::NN];  // node metrics of the sweep direction
 };
@@ -564,7 +585,7 @@ struct SweepShared {
 template <int DIR, typename R, int TW, int TS, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep(SweepArgs a) {
   __shared__ SweepShared<R, TW, TS> sh;
-  sweep_tile<DIR, R, TW, TS, NT>(a.c, a.b, xcd_remap(blockIdx.x, gridDim.x), sh.Fp, sh.Fm, sh.Fn, sh.M);
+  sweep_tile<DIR, R, TW, TS, NT>(a.c, a.b, xcd_remap(blockIdx.x, gridDim.x), sh.F, sh.Fn, sh.M);
 }
 
 // Batched blocks: one launch walks a work list covering the tiles of every block
@@ -580,7 +601,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const int t = xcd_remap(blockIdx.x, gridDim.x);
     int blk = 0;
     while (t >= tl.prefix[blk + 1]) ++blk;
-    sweep_tile<DIR, R, TW, TS, NT>(c, blocks[blk], t - tl.prefix[blk], sh.Fp, sh.Fm, sh.Fn, sh.M);
+    sweep_tile<DIR, R, TW, TS, NT>(c, blocks[blk], t - tl.prefix[blk], sh.F, sh.Fn, sh.M);
     return;
   }
   int start, count, lane_wg, nwg_x;
@@ -589,7 +610,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   for (int u = lane_wg; u < count; u += nwg_x) {
     const int t = start + u;
     while (t >= tl.prefix[blk + 1]) ++blk;  // t only grows, so the scan resumes
-    sweep_tile<DIR, R, TW, TS, NT>(c, blocks[blk], t - tl.prefix[blk], sh.Fp, sh.Fm, sh.Fn, sh.M);
+    sweep_tile<DIR, R, TW, TS, NT>(c, blocks[blk], t - tl.prefix[blk], sh.F, sh.Fn, sh.M);
     __syncthreads();  // the next tile overwrites the LDS this one read
   }
 }

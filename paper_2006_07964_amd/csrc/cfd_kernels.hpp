@@ -32,16 +32,19 @@ struct ViscArgs {
   Geom g;
   const double* q;
   const double* met;
+  const void* met_r;  // the 10 metric planes in the compute type
   void* vis;  // 12 planes of the compute type
   Phys ph;
   int kc;     // planes per tile (set by visc_tiling)
 };
 template <typename R>
 hipError_t launch_visc(ViscArgs a, hipStream_t s);
+// dst[e] = float(src[e]) for e < n
+hipError_t launch_round(const double* src, float* dst, int64_t n, hipStream_t s);
 // batched viscous prepass over the tiles (64 x 8 columns, a chunk of k planes) of every block
 template <typename R>
 hipError_t launch_visc_batch(const ViscArgs* args_dev, const TileList& tl, hipStream_t s);
-void visc_tiling(const Geom& g, int* kc, int* tiles);
+void visc_tiling(const Geom& g, int min_tiles, int* kc, int* tiles);
 
 // ---- direction sweep ----------------------------------------------------------------
 enum OutKind { kOutPartial = 0, kOutRhs = 1, kOutRK = 2 };
