@@ -2,6 +2,7 @@
 // sweeps with the fused RK3 update, halo copies, boundary fills and reductions.
 //
 // Method: Ye et al., arXiv 2006.07964, Sec. 2 (Eqs 1-21) and Sec. 4.5 (modified AFWENO).
+#include <type_traits>
 #include <hip/hip_runtime.h>
 
 #include "../../include/cfd.h"
@@ -339,6 +340,12 @@ struct LdsIdx {
 
 
 
+// Type of the staged Q / nodal-flux tile: FP64 in FP64 sweeps and in zeta sweeps (the last
+// direction of an RK stage, whose FP64 combination then takes Q from the tile instead of
+// reading it again), the compute type otherwise.
+template <typename R, int DIR>
+using StageT = typename std::conditional<sizeof(R) == 8 || DIR == 2, double, R>::type;
+
 template <int TW, int TS>
 struct SweepLds {
   static constexpr int NH = TS + 1;  // half points
@@ -349,12 +356,13 @@ struct SweepLds {
 // One tile of a direction sweep: t is the logical tile index inside the block (sweep-
 // direction tile fastest, then the cross tile c1, then the cross index c2).
 template <int DIR, typename R, int TW, int TS, int NT>
-__device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBlock& b, int t, R* sF, R* sFn,
+__device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBlock& b, int t, R* sF, StageT<R, DIR>* sFn,
                                            double* sM) {
   constexpr int NH = SweepLds<TW, TS>::NH;
   constexpr int NN = SweepLds<TW, TS>::NN;
   constexpr int NW = SweepLds<TW, TS>::NW;
   using L = LdsIdx<DIR, TW>;
+  using S = StageT<R, DIR>;
 
   const Geom& g = b.g;
   const int nd = DIR == 0 ? g.ni : DIR == 1 ? g.nj : g.nk;
@@ -414,8 +422,8 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
     }
     if (c.out_kind != kOutPartial) Jo = ldg(plane_ptr(met, 9 * plane), po);
     if (c.out_kind == kOutRK) {
-      // Q at the output node (an FP64 inviscid sweep took it from the staged tile already)
-      if (!(sizeof(R) == 8 && c.do_inv)) {
+      // Q at the output node (an inviscid sweep with an FP64 tile took it from there already)
+      if (!(sizeof(S) == 8 && c.do_inv)) {
 #pragma unroll
         for (int v = 0; v < 5; ++v) qco[v] = ldg(plane_ptr(Q, v * plane), po);
       }
@@ -444,7 +452,7 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
       if (s >= nn || c1 >= n1 || n > nd + 2) continue;
       const uint32_t p = origin + (uint32_t)c1 * s1 + (uint32_t)n * sd;
 #pragma unroll
-      for (int v = 0; v < 5; ++v) sFn[L::f(v, w, s, NN)] = R(ldg(plane_ptr(Q, v * plane), p));
+      for (int v = 0; v < 5; ++v) sFn[L::f(v, w, s, NN)] = S(R(ldg(plane_ptr(Q, v * plane), p)));
       sM[L::f(0, w, s, NN)] = ldg(mx, p);
       sM[L::f(1, w, s, NN)] = ldg(my, p);
       sM[L::f(2, w, s, NN)] = ldg(mz, p);
@@ -466,7 +474,7 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
       const int sc = s + 2;
       R q0[5];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) q0[v] = sFn[L::f(v, w, sc, NN)];
+      for (int v = 0; v < 5; ++v) q0[v] = R(sFn[L::f(v, w, sc, NN)]);
       const Basis<R> B =
           make_basis(q0, R(sM[L::f(0, w, sc, NN)]), R(sM[L::f(1, w, sc, NN)]), R(sM[L::f(2, w, sc, NN)]), G);
       R V[5][5];  // V[t][field] at node n + t - 2
@@ -474,7 +482,7 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
       for (int tt = 0; tt < 5; ++tt) {
         R qq[5];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) qq[v] = sFn[L::f(v, w, s + tt, NN)];
+        for (int v = 0; v < 5; ++v) qq[v] = R(sFn[L::f(v, w, s + tt, NN)]);
         project(B, G, qq, V[tt]);
       }
       R vl[5], vr[5];
@@ -500,9 +508,9 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
         sw_flux<-1>(ur, hx, hy, hz, G, Fkeep);
       }
     }
-    // in FP64 the staged Q is exact: the output node's copy for the RK combination is read
+    // a staged Q in FP64 is exact: the output node's copy for the RK combination is read
     // here, before the barrier after which the nodal fluxes overwrite it
-    if (sizeof(R) == 8 && c.out_kind == kOutRK && out_here) {
+    if (sizeof(S) == 8 && c.out_kind == kOutRK && out_here) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) qco[v] = double(sFn[L::f(v, wo, so + 3, NN)]);
     }
@@ -521,10 +529,10 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
       if (s >= nn || c1 >= n1 || n > nd + 2) continue;
       R q[5], F[5];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) q[v] = sFn[L::f(v, w, s, NN)];
+      for (int v = 0; v < 5; ++v) q[v] = R(sFn[L::f(v, w, s, NN)]);
       phys_flux(q, R(sM[L::f(0, w, s, NN)]), R(sM[L::f(1, w, s, NN)]), R(sM[L::f(2, w, s, NN)]), G, F);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) sFn[L::f(v, w, s, NN)] = F[v];
+      for (int v = 0; v < 5; ++v) sFn[L::f(v, w, s, NN)] = S(F[v]);
     }
     __syncthreads();
   }
@@ -541,9 +549,9 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
     for (int v = 0; v < 5; ++v) {
       const R fp = sF[L::f(v, w, s + 1, NH)];
       const R fm = sF[L::f(v, w, s, NH)];
-      const R D = fp - fm + R(17.0 / 256.0) * (sFn[L::f(v, w, s + 4, NN)] - sFn[L::f(v, w, s + 2, NN)]) -
-                  R(13.0 / 320.0) * (sFn[L::f(v, w, s + 5, NN)] - sFn[L::f(v, w, s + 1, NN)]) +
-                  R(19.0 / 3840.0) * (sFn[L::f(v, w, s + 6, NN)] - sFn[L::f(v, w, s, NN)]);
+      auto fn = [&](int m) { return R(sFn[L::f(v, w, s + m, NN)]); };
+      const R D = fp - fm + R(17.0 / 256.0) * (fn(4) - fn(2)) - R(13.0 / 320.0) * (fn(5) - fn(1)) +
+                  R(19.0 / 3840.0) * (fn(6) - fn(0));
       r[v] = -D;
     }
   }
@@ -574,17 +582,17 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
 }
 
 // LDS of one workgroup for the largest tile configuration in use.
-template <typename R, int TW, int TS>
+template <typename R, typename S, int TW, int TS>
 struct SweepShared {
-  R F[5 * TW * SweepLds<TW, TS>::NH];  // interface fluxes f(n+1/2)
-  R Fn[5 * TW * SweepLds<TW, TS>::NN];
+  R F[5 * TW * SweepLds<TW, TS>::NH];   // interface fluxes f(n+1/2)
+  S Fn[5 * TW * SweepLds<TW, TS>::NN];  // staged Q, then nodal fluxes
   double M[3 * TW * SweepLds<TW, TS>::NN];  // node metrics of the sweep direction
 };
 
 // Single block: one workgroup per tile, ids remapped XCD-contiguously.
 template <int DIR, typename R, int TW, int TS, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep(SweepArgs a) {
-  __shared__ SweepShared<R, TW, TS> sh;
+  __shared__ SweepShared<R, StageT<R, DIR>, TW, TS> sh;
   sweep_tile<DIR, R, TW, TS, NT>(a.c, a.b, xcd_remap(blockIdx.x, gridDim.x), sh.F, sh.Fn, sh.M);
 }
 
@@ -595,7 +603,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 template <int DIR, typename R, int TW, int TS, int NT, bool PERSIST>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_batch(
     const SweepBlock* __restrict__ blocks, SweepCommon c, TileList tl) {
-  __shared__ SweepShared<R, TW, TS> sh;
+  __shared__ SweepShared<R, StageT<R, DIR>, TW, TS> sh;
   const int total = tl.prefix[tl.nblk];
   if (!PERSIST) {
     const int t = xcd_remap(blockIdx.x, gridDim.x);
