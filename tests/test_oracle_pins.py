@@ -638,3 +638,94 @@ def test_multiblock_o_grid_steps_are_finite_and_conservative_in_theta():
     for bi, (b, r) in enumerate(zip(wl.blocks, rs)):
         if b.bc[2] == O.BC_INTERFACE and b.bc[3] == O.BC_INTERFACE:
             assert np.max(np.abs(r[:, 3:-3, 3:-3, 3:-3])) < 1e-10, bi
+
+
+# ---- P15: nonlinear weights at shocks (quasi-one-dimensional shock tube) ----------------
+def _sod_exact_density(xi, g=1.4, rl=1.0, pl=1.0, rr=0.125, pr=0.1):
+    """Density of the exact Riemann solution (left state at rest, right state at rest,
+    left rarefaction + contact + right shock) at similarity coordinates xi = x/t; the star
+    pressure from Newton's method on f_L(p) + f_R(p) = 0 (Toro, Riemann Solvers, ch. 4)."""
+    cl, cr = np.sqrt(g * pl / rl), np.sqrt(g * pr / rr)
+
+    def f(p, rk, pk, ck):
+        if p > pk:  # shock
+            a, b = 2.0 / ((g + 1) * rk), (g - 1) / (g + 1) * pk
+            return (p - pk) * np.sqrt(a / (p + b)), np.sqrt(a / (b + p)) * (1 - 0.5 * (p - pk) / (b + p))
+        r = (p / pk) ** ((g - 1) / (2 * g))  # rarefaction
+        return 2 * ck / (g - 1) * (r - 1), 1.0 / (rk * ck) * (p / pk) ** (-(g + 1) / (2 * g))
+
+    p = 0.5 * (pl + pr)
+    for _ in range(50):
+        fl, dl = f(p, rl, pl, cl)
+        fr, dr = f(p, rr, pr, cr)
+        dp = (fl + fr) / (dl + dr)
+        p = max(p - dp, 1e-12)
+        if abs(dp) < 1e-15 * p:
+            break
+    fl, _ = f(p, rl, pl, cl)
+    fr, _ = f(p, rr, pr, cr)
+    u = 0.5 * (fr - fl)
+    assert p < pl and p > pr  # rarefaction to the left, shock to the right
+    rho_l = rl * (p / pl) ** (1 / g)
+    cls = cl * (p / pl) ** ((g - 1) / (2 * g))
+    rho_r = rr * (p / pr + (g - 1) / (g + 1)) / ((g - 1) / (g + 1) * p / pr + 1)
+    s = cr * np.sqrt((g + 1) / (2 * g) * p / pr + (g - 1) / (2 * g))
+    xi = np.asarray(xi, dtype=float)
+    fan = rl * (2 / (g + 1) + (g - 1) / ((g + 1) * cl) * (-xi)) ** (2 / (g - 1))
+    return np.select([xi < -cl, xi < u - cls, xi < u, xi < s], [rl, fan, rho_l, rho_r], rr), (p, u, rho_l, rho_r, s)
+
+
+def test_sod_exact_solver_textbook_values():
+    _, (p, u, rl, rr, s) = _sod_exact_density(0.0)
+    assert abs(p - 0.30313) < 1e-5 and abs(u - 0.92745) < 1e-5
+    assert abs(rl - 0.42632) < 1e-5 and abs(rr - 0.26557) < 1e-5 and abs(s - 1.75216) < 1e-5
+
+
+def _double_shock_tube(n, t_end=0.15):
+    """Periodic unit interval (7 x 7 points across), high state (rho 1, p 1) between
+    0.25 and 0.75, low state (0.125, 0.1) outside: two mirror-image shock tubes that do not
+    interact before t ~ 0.2.  Euler, WENO-JS, fixed dt = 0.3 dx."""
+    c = O.make_cfg(n, 7, 7, viscous=False)
+    xyz = W.cartesian_grid(n, 7, 7, 1.0, 7.0 / n, 7.0 / n)
+    met = O.metrics(c, xyz)
+    dx = 1.0 / n
+    x = np.arange(-3, n + 3) * dx
+    high = (x >= 0.25 - dx / 2) & (x < 0.75 - dx / 2)
+    rho = np.where(high, 1.0, 0.125)
+    p = np.where(high, 1.0, 0.1)
+    shape = (7 + 6, 7 + 6, n + 6)
+    q = W.conserved(np.broadcast_to(rho, shape), np.zeros(shape), np.zeros(shape), np.zeros(shape),
+                    np.broadcast_to(p, shape))
+    q = O.periodic_wrap(c, np.ascontiguousarray(q))
+    dt = 0.3 * dx
+    steps = int(round(t_end / dt))
+    for _ in range(steps):
+        q = O.rk_step(c, met, dt, q)
+    t = steps * dt
+    xi_ = np.arange(n) * dx
+    # exact: a tube centred on 0.75 - dx/2, and its mirror image centred on 0.25 - dx/2
+    right = xi_ >= 0.5 - dx / 2
+    xr = (xi_ - (0.75 - dx / 2)) / t
+    xl = ((0.25 - dx / 2) - xi_) / t
+    exact = np.where(right, _sod_exact_density(xr)[0], _sod_exact_density(xl)[0])
+    return q[0, 3:-3, 3:-3, 3:-3], exact
+
+
+def test_shock_tube_weno_js_bounded_and_converging():
+    """P15: WENO-JS with the characteristic projection and Steger-Warming splitting on two
+    mirror-image shock tubes: the solution is uniform across the tube, mirror symmetric,
+    free of overshoots beyond 1% of the density jump, and its L1 density error against the
+    exact Riemann solution falls with the resolution."""
+    errs = []
+    for n in (64, 128, 256):
+        rho, exact = _double_shock_tube(n)
+        assert np.max(np.abs(rho - rho[:1, :1, :])) < 1e-12  # no variation across the tube
+        line = rho[0, 0]
+        # mirror symmetry about x = 0.5 - dx/2: node i <-> node n - 1 - i
+        assert np.max(np.abs(line - line[::-1])) < 1e-12
+        jump = 1.0 - 0.125
+        assert line.max() <= 1.0 + 0.01 * jump and line.min() >= 0.125 - 0.01 * jump
+        errs.append(np.mean(np.abs(line - exact)))
+    print("L1 density errors", errs)
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 0.01

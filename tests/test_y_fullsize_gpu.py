@@ -1,5 +1,9 @@
-"""Parity at the benchmark workloads' real sizes, every interior point of the first RK
-stage, in the pitched layout and launch configuration the benchmark uses."""
+"""Parity at the benchmark workloads' real sizes, in the pitched layout and launch
+configuration the benchmark uses: every interior point of the first RK stage, and the
+256^3 case after 1, 10 and 100 steps at sampled nodes."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -64,5 +68,71 @@ def test_channel_512x512x384_first_stage():
         err = normwise(got, q0 + dt * r)
         print("channel first stage normwise error", err)
         assert np.all(err < TOL)
+    finally:
+        dev.close()
+
+
+GOLD_TGV256 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "tgv256_samples.json")
+
+
+def _tgv256_samples():
+    if not os.path.exists(GOLD_TGV256):
+        pytest.skip("tests/golden/tgv256_samples.json not generated")
+    gold = json.load(open(GOLD_TGV256))
+    ix = np.array(gold["index"]) + 3
+    ref = {int(s): np.array(v) for s, v in gold["values"].items()}
+    return gold["dt"], ix, ref
+
+
+def _sample(a, ix):
+    return a[:, ix][:, :, ix][:, :, :, ix]
+
+
+def _sample_normwise(got, ref):
+    """normwise error (rho, momentum vector, e) over the sample nodes"""
+    def rel(sl):
+        return np.max(np.abs(got[sl] - ref[sl])) / np.max(np.abs(ref[sl]))
+    return np.array([rel(slice(0, 1)), rel(slice(1, 4)), rel(slice(4, 5))])
+
+
+def test_taylor_green_256_fp64_steps_1_10_100():
+    """The 256^3 benchmark case run 100 RK3 steps in FP64 with the benchmark's single-block
+    calls and tiles, against the oracle's states after 1, 10 and 100 steps (stored at a
+    12^3 lattice of nodes by tests/golden/make_tgv256_samples.py).  Independent runs: the
+    per-step round-off (~1e-15 per step, up to ~1e-13 where WENO-JS weights amplify it)
+    accumulates, so step s is held to 1e-12 for s <= 10 and 1e-12 * s / 10 beyond."""
+    dt, ix, ref = _tgv256_samples()
+    wl = W.taylor_green_wavy(256)
+    dev = DevBlock(wl, pitched=True)
+    try:
+        for s in range(1, max(ref) + 1):
+            dev.step(dt)
+            if s in ref:
+                got = _sample(dev.host(dev.q), ix)
+                err = _sample_normwise(got, ref[s])
+                print(f"step {s}: normwise (rho, momentum, e) {err}", flush=True)
+                assert np.all(err < 1e-12 * max(1.0, s / 10.0))
+    finally:
+        dev.close()
+
+
+def test_taylor_green_256_mixed_100_steps_vs_oracle():
+    """The same case in mixed precision: per-field L2 and Linf over the sample nodes against
+    the FP64 oracle after 1, 10 and 100 steps (reported), normwise error bounded by 2e-5
+    as at 64^3."""
+    dt, ix, ref = _tgv256_samples()
+    wl = W.taylor_green_wavy(256)
+    dev = DevBlock(wl, precision=B.CFD_MIXED, pitched=True)
+    try:
+        for s in range(1, max(ref) + 1):
+            dev.step(dt)
+            if s in ref:
+                got = _sample(dev.host(dev.q), ix)
+                for f, name in enumerate(("rho", "rho u", "rho v", "rho w", "E")):
+                    d = got[f] - ref[s][f]
+                    print(f"step {s} {name}: L2 {np.sqrt(np.mean(d * d)):.3e} Linf {np.max(np.abs(d)):.3e}")
+                err = _sample_normwise(got, ref[s])
+                print(f"step {s}: normwise (rho, momentum, e) {err}", flush=True)
+                assert np.all(err < 2e-5)
     finally:
         dev.close()
