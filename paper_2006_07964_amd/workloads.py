@@ -218,6 +218,26 @@ def vortex_wavy(n: int = 32, seed: Optional[int] = 1, noise: float = 1e-3, visco
                              description=f"{n}^3 periodic wavy grid, isentropic vortex Mach {mach}")
 
 
+def double_shock_tube(n: int = 128, across: int = 7) -> Workload:
+    """Two mirror-image shock tubes on the periodic unit interval (a Cartesian n x across x
+    across grid, spacing 1/n): high state (rho 1, p 1) for x in [0.25 - dx/2, 0.75 - dx/2),
+    low state (rho 0.125, p 0.1) elsewhere, at rest; Euler.  The discontinuities sit
+    midway between nodes and the two tubes do not interact before t ~ 0.2."""
+    dx = 1.0 / n
+    xyz = cartesian_grid(n, across, across, 1.0, across * dx, across * dx)
+
+    def state(c):
+        x = c[0]
+        high = (x >= 0.25 - dx / 2) & (x < 0.75 - dx / 2)
+        rho = np.where(high, 1.0, 0.125)
+        p = np.where(high, 1.0, 0.1)
+        zero = np.zeros_like(x)
+        return conserved(rho, zero, zero, zero, p)
+
+    return periodic_workload(f"double_shock_tube_{n}", xyz, state, viscous=False, cfl=0.3,
+                             description=f"two shock tubes, {n} x {across} x {across}, Euler")
+
+
 def taylor_green_wavy(n: int = 256, seed: Optional[int] = 2, noise: float = 1e-4, steps: int = 100,
                       amp: float = 0.05) -> Workload:
     """Single periodic block on the 2 pi cube with a sinusoidal grid perturbation.

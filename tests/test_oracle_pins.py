@@ -682,21 +682,13 @@ def test_sod_exact_solver_textbook_values():
 
 
 def _double_shock_tube(n, t_end=0.15):
-    """Periodic unit interval (7 x 7 points across), high state (rho 1, p 1) between
-    0.25 and 0.75, low state (0.125, 0.1) outside: two mirror-image shock tubes that do not
-    interact before t ~ 0.2.  Euler, WENO-JS, fixed dt = 0.3 dx."""
-    c = O.make_cfg(n, 7, 7, viscous=False)
-    xyz = W.cartesian_grid(n, 7, 7, 1.0, 7.0 / n, 7.0 / n)
-    met = O.metrics(c, xyz)
+    """The two mirror-image shock tubes of workloads.double_shock_tube, advanced to t_end
+    with the oracle (Euler, WENO-JS, fixed dt = 0.3 dx)."""
+    wl = W.double_shock_tube(n)
+    c = O.cfg_from_workload(wl)
+    met = O.metrics(c, wl.blocks[0].xyz)
+    q = wl.blocks[0].q.copy()
     dx = 1.0 / n
-    x = np.arange(-3, n + 3) * dx
-    high = (x >= 0.25 - dx / 2) & (x < 0.75 - dx / 2)
-    rho = np.where(high, 1.0, 0.125)
-    p = np.where(high, 1.0, 0.1)
-    shape = (7 + 6, 7 + 6, n + 6)
-    q = W.conserved(np.broadcast_to(rho, shape), np.zeros(shape), np.zeros(shape), np.zeros(shape),
-                    np.broadcast_to(p, shape))
-    q = O.periodic_wrap(c, np.ascontiguousarray(q))
     dt = 0.3 * dx
     steps = int(round(t_end / dt))
     for _ in range(steps):

@@ -234,6 +234,27 @@ def test_every_tile_shape_agrees():
         dev.close()
 
 
+def test_shock_tube_rk_steps():
+    """Two mirror-image shock tubes (discontinuous data: WENO-JS weights far from the ideal
+    ones, Steger-Warming split near sonic points), Euler, 30 RK3 steps against the oracle,
+    normwise after every step."""
+    wl = W.double_shock_tube(64)
+    c = O.cfg_from_workload(wl)
+    met = O.metrics(c, wl.blocks[0].xyz)
+    dev = DevBlock(wl, pitched=True)
+    try:
+        dt = 0.3 / 64
+        q = wl.blocks[0].q.copy()
+        for s in range(30):
+            dev.step(dt)
+            q = O.rk_step(c, met, dt, q)
+            err = normwise(dev.host(dev.q), q)
+            print(s, err)
+            assert np.all(err < TOL), (s, err)
+    finally:
+        dev.close()
+
+
 def test_argument_and_state_errors():
     import torch
     wl = _vortex(16, 16, 16)
