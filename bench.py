@@ -27,20 +27,32 @@ sys.path.insert(0, ROOT)
 
 # algorithmic HBM bytes per interior point of each kernel (compulsory reads and writes)
 # FP64 path: Q 40 B, a metric component or J 8 B, a viscous-flux component 8 B
+# compulsory HBM bytes per interior point of each kernel, by the role of a sweep in the
+# direction order (first: no partial sum in; last: the RK combination)
 ALG_BYTES_FP64 = {
-    "visc_prepass": 40 + 80 + 96,                 # Q, 9 metrics + J, 12 flux planes
-    "sweep_xi": 40 + 24 + 32 + 40,                # Q, 3 metrics, 4 flux planes, partial sum out
-    "sweep_eta": 40 + 24 + 32 + 40 + 40,          # + partial sum in
-    "sweep_zeta": 40 + 24 + 32 + 40 + 40,
-    "sweep_zeta_rk": 40 + 24 + 32 + 40 + 8 + 40 + 40,  # Q, metrics, fluxes, partial in, J, Qn, Qout
+    "visc_prepass": 40 + 80 + 96,          # Q, 9 metrics + J, 12 flux planes
+    "first": 40 + 24 + 32 + 40,            # Q, 3 metrics, 4 flux planes, partial sum out
+    "middle": 40 + 24 + 32 + 40 + 40,      # + partial sum in
+    "last_rk": 40 + 24 + 32 + 40 + 8 + 40 + 40,  # Q, metrics, fluxes, partial in, J, Qn, Qout
 }
 ALG_BYTES_MIXED = {
-    "visc_prepass": 40 + 80 + 48,
-    "sweep_xi": 40 + 24 + 16 + 20,
-    "sweep_eta": 40 + 24 + 16 + 20 + 20,
-    "sweep_zeta": 40 + 24 + 16 + 20 + 20,
-    "sweep_zeta_rk": 40 + 24 + 16 + 20 + 8 + 40 + 40,
+    "visc_prepass": 40 + 40 + 48,          # Q, the FP32 copy of the metrics, FP32 flux planes
+    "first": 40 + 24 + 16 + 20,
+    "middle": 40 + 24 + 16 + 20 + 20,
+    "last_rk": 40 + 24 + 16 + 20 + 8 + 40 + 40,
 }
+DIR_NAMES = ("xi", "eta", "zeta")
+
+
+def kernel_bytes(table, order):
+    """Algorithmic bytes per point keyed by the library's profiler names."""
+    out = {"visc_prepass": table["visc_prepass"]}
+    out[f"sweep_{DIR_NAMES[order[0]]}"] = table["first"]
+    out[f"sweep_{DIR_NAMES[order[1]]}"] = table["middle"]
+    out[f"sweep_{DIR_NAMES[order[2]]}_rk"] = table["last_rk"]
+    return out
+
+
 HBM_PEAK_GBS = 8000.0
 
 
@@ -237,8 +249,8 @@ def main():
     updates = points * 3 * args.steps
     value = updates / el
 
-    alg = ALG_BYTES_FP64 if prec == B.CFD_FP64 else ALG_BYTES_MIXED
-    stage_bytes = sum(alg[n] for n in ("visc_prepass", "sweep_xi", "sweep_eta", "sweep_zeta_rk")) * points
+    alg = kernel_bytes(ALG_BYTES_FP64 if prec == B.CFD_FP64 else ALG_BYTES_MIXED, B.cfd_sweep_order())
+    stage_bytes = sum(alg.values()) * points
     kernels = {}
     for name, (launches, ms) in prof.items():
         avg_ms = ms / max(launches, 1)

@@ -203,6 +203,10 @@ int cfd_batch_set_tuning(cfd_batch* bt, const int* cfg, const int* persist);
  * came first).  cap is the length of ms, at least 6 * cfd_tile_config_count().          */
 int cfd_batch_tuning_times(const cfd_batch* bt, float* ms, int cap);
 
+/* Order of the three direction sweeps of an RHS evaluation (dirs[0..2], 0 = xi, 1 = eta,
+ * 2 = zeta); the last one writes R or the RK stage, the others partial sums.            */
+int cfd_sweep_order(int* dirs);
+
 /* ---- sweep tile shapes ----------------------------------------------------------------
  * A sweep workgroup owns `lines` grid lines across the sweep direction and up to `nodes`
  * output nodes along it, with `threads` threads.  cfd_tile_config_count() returns the

@@ -91,6 +91,7 @@ def lib():
         "cfd_batch_set_tuning": ([_VP, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
         "cfd_batch_tuning_times": ([_VP, C.POINTER(C.c_float), C.c_int], C.c_int),
         "cfd_tile_config_count": ([], C.c_int),
+        "cfd_sweep_order": ([C.POINTER(C.c_int)], C.c_int),
         "cfd_tile_config": ([C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
         "cfd_block_set_tiles": ([_VP, C.POINTER(C.c_int)], C.c_int),
         "cfd_block_tiles": ([_VP, C.POINTER(C.c_int)], C.c_int),
@@ -266,6 +267,14 @@ def cfd_batch_tuning_times(bt: int):
     _check(lib().cfd_batch_tuning_times(bt, ms, 6 * n))
     return {(d, c, p): ms[(d * n + c) * 2 + p] for d in range(3) for c in range(n) for p in range(2)
             if ms[(d * n + c) * 2 + p] >= 0}
+
+
+def cfd_sweep_order():
+    """Directions (0 = xi, 1 = eta, 2 = zeta) in the order the sweeps run; the last one
+    writes R or the RK stage."""
+    d = (C.c_int * 3)()
+    _check(lib().cfd_sweep_order(d))
+    return list(d)
 
 
 def cfd_tile_config_count() -> int:

@@ -342,8 +342,8 @@ int run_sweeps(cfd_block* b, const double* Q, unsigned mask, int out_kind, doubl
   const bool inv = (mask & CFD_TERM_INV) != 0;
   const bool vis = (mask & CFD_TERM_VIS) != 0 && b->d.params.viscous;
   int dirs[3], nd = 0;
-  for (int d = 0; d < 3; ++d)
-    if (mask & (1u << d)) dirs[nd++] = d;
+  for (int n = 0; n < 3; ++n)
+    if (mask & (1u << kSweepOrder[n])) dirs[nd++] = kSweepOrder[n];
   SweepArgs a;
   std::memset(&a, 0, sizeof a);
   a.b.g = b->g;
@@ -833,14 +833,14 @@ void build_args(cfd_batch* bt, double* const* Qn, double* const* QA, double* con
   for (int st = 0; st < 3; ++st) {
     double* const* cur = st == 0 ? Qn : st == 1 ? QA : QB;
     double* const* outp = st == 0 ? QA : st == 1 ? QB : Qn;
-    for (int d = 0; d < 3; ++d) {
-      SweepCommon& c = bt->sweep_common[st][d];
+    for (int n = 0; n < 3; ++n) {
+      SweepCommon& c = bt->sweep_common[st][kSweepOrder[n]];
       std::memset(&c, 0, sizeof c);
       c.ph = ph;
       c.do_inv = 1;
       c.do_vis = bt->viscous;
-      c.has_prev = d > 0;
-      c.out_kind = d == 2 ? kOutRK : kOutPartial;
+      c.has_prev = n > 0;
+      c.out_kind = n == 2 ? kOutRK : kOutPartial;
       c.dt_dev = dt_dev;
       c.ca = kRK[st][0];
       c.cb = kRK[st][1];
@@ -866,7 +866,7 @@ void build_args(cfd_batch* bt, double* const* Qn, double* const* QA, double* con
         a.vis = B->vis;
         a.rt_in = B->rt;
         a.rt_out = B->rt;
-        a.out = d == 2 ? outp[b] : nullptr;
+        a.out = d == kSweepOrder[2] ? outp[b] : nullptr;
         a.qn = Qn[b];
         sweep_tiling(d, bt->cfg[d], B->g, &a.tiles_c1, &a.tiles_d, &a.tile_len);
       }
@@ -908,7 +908,7 @@ hipError_t enqueue_stage(cfd_batch* bt, int st, double* const* outp) {
                                   : launch_visc_ghost<float>(bt->vbc_dev, bt->nvbc, bt->maxvbc, t, bt->stream);
     if (e != hipSuccess) return e;
   }
-  for (int d = 0; d < 3 && e == hipSuccess; ++d) e = launch_batch_sweep(bt, st, d);
+  for (int n = 0; n < 3 && e == hipSuccess; ++n) e = launch_batch_sweep(bt, st, kSweepOrder[n]);
   if (e != hipSuccess) return e;
   // Q halos of every block: wall reset, interface / periodic copies, ghost fills
   BcArgs ba;
@@ -1197,6 +1197,12 @@ int cfd_batch_step(cfd_batch* bt, const double* dt_dev, double* const* Qn, doubl
 int cfd_batch_tuning(const cfd_batch* bt, int* cfg, int* persist) { return batch_tuning(bt, cfg, persist); }
 int cfd_batch_set_tuning(cfd_batch* bt, const int* cfg, const int* persist) { return batch_set_tuning(bt, cfg, persist); }
 int cfd_batch_tuning_times(const cfd_batch* bt, float* ms, int cap) { return batch_tuning_times(bt, ms, cap); }
+
+int cfd_sweep_order(int* dirs) {
+  if (!dirs) return fail(CFD_ERR_ARG, "null argument");
+  for (int n = 0; n < 3; ++n) dirs[n] = kSweepOrder[n];
+  return CFD_OK;
+}
 
 int cfd_tile_config_count(void) { return kTileCfgs; }
 

@@ -340,11 +340,11 @@ struct LdsIdx {
 
 
 
-// Type of the staged Q / nodal-flux tile: FP64 in FP64 sweeps and in zeta sweeps (the last
-// direction of an RK stage, whose FP64 combination then takes Q from the tile instead of
-// reading it again), the compute type otherwise.
+// Type of the staged Q / nodal-flux tile: FP64 in FP64 sweeps and in the last sweep
+// direction (the one that carries the RK combination, which then takes Q from the tile in
+// FP64 instead of reading it again), the compute type otherwise.
 template <typename R, int DIR>
-using StageT = typename std::conditional<sizeof(R) == 8 || DIR == 2, double, R>::type;
+using StageT = typename std::conditional<sizeof(R) == 8 || DIR == kSweepOrder[2], double, R>::type;
 
 template <int TW, int TS>
 struct SweepLds {

@@ -72,6 +72,10 @@ struct SweepArgs {
   SweepCommon c;
   SweepBlock b;
 };
+// Order of the direction sweeps within an RHS evaluation: zeta first, xi last.  The last
+// sweep carries the output (R or the RK combination); its extra loads are cheapest along
+// xi, whose stencils stay within rows.
+constexpr int kSweepOrder[3] = {2, 1, 0};
 constexpr int kTileCfgs = 6;
 // shape of tile configuration cfg (lines across, nodes along the sweep, threads)
 void tile_shape(int cfg, int* tw, int* ts, int* nt);  // sweep tile configurations (see TileCfg in cfd_kernels.hip)
