@@ -103,3 +103,14 @@ def test_tile_configurations(lib):
     for bad in (-1, n):
         with pytest.raises(B.CfdError):
             B.cfd_tile_config(bad)
+
+
+def test_sweep_order_and_null_handles(lib):
+    order = B.cfd_sweep_order()
+    assert sorted(order) == [0, 1, 2]
+    assert lib.cfd_sweep_order(None) == B.CFD_ERR_ARG
+    cfg = (C.c_int * 3)(0, 0, 0)
+    assert lib.cfd_block_set_tiles(None, cfg) == B.CFD_ERR_ARG
+    assert lib.cfd_block_tiles(None, cfg) == B.CFD_ERR_ARG
+    ms = (C.c_float * 64)()
+    assert lib.cfd_batch_tuning_times(None, ms, 64) == B.CFD_ERR_ARG
