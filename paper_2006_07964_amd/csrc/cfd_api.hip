@@ -117,9 +117,9 @@ struct ProfScope {
 // block
 // =====================================================================================
 // tile shapes of a block's own sweeps until cfd_block_set_tiles (the batched autotuner's
-// usual choice on large blocks): 4 lines x 58 nodes along xi, 16 lines x 14 nodes along
-// eta and zeta, 256 threads each
-constexpr int kDefaultTiles[3] = {5, 2, 2};
+// usual choice on large blocks), [FP64 / mixed][direction]: 4 lines x 58 nodes along xi,
+// 16 x 14 along eta, 8 x 26 (FP64) or 16 x 14 (mixed) along zeta, 256 threads each
+constexpr int kDefaultTiles[2][3] = {{5, 2, 4}, {5, 2, 2}};
 
 struct cfd_block {
   cfd_block_desc d;
@@ -143,7 +143,7 @@ struct cfd_block {
   BcSeg* local_bc_dev = nullptr;
   int n_local_bc = 0, max_local_bc = 0;
   bool has_interface = false;
-  int cfg[3] = {kDefaultTiles[0], kDefaultTiles[1], kDefaultTiles[2]};  // sweep tile shape per direction
+  int cfg[3] = {0, 0, 0};  // sweep tile shape per direction (set at creation)
   // small device scratch for reductions
   unsigned long long* red_dev = nullptr;
   int* flag_dev = nullptr;
@@ -423,6 +423,7 @@ int cfd_block_create(const cfd_block_desc* d, void* hip_stream, cfd_block** out)
   b->g.plane = d->ld_i * d->ld_j * (int64_t)(d->nk + 6);
   b->stream = (hipStream_t)hip_stream;
   b->esize = d->precision == CFD_FP64 ? 8 : 4;
+  for (int dir = 0; dir < 3; ++dir) b->cfg[dir] = kDefaultTiles[d->precision == CFD_FP64 ? 0 : 1][dir];
   (void)hipGetDevice(&b->device);
   const size_t plane = (size_t)b->g.plane;
   auto cleanup = [&](int code, const std::string& msg) {
@@ -786,7 +787,7 @@ int batch_create(cfd_block* const* blocks, int nb, cfd_exchange* x, void* hip_st
   bt->precision = blocks[0]->d.precision;
   bt->viscous = blocks[0]->d.params.viscous != 0;
   for (int d = 0; d < 3; ++d) {
-    bt->cfg[d] = kDefaultTiles[d];
+    bt->cfg[d] = kDefaultTiles[bt->precision == CFD_FP64 ? 0 : 1][d];
     for (int c = 0; c < kTileCfgs; ++c) bt->tune_ms[d][c][0] = bt->tune_ms[d][c][1] = -1.f;
   }
   hipDeviceProp_t prop;
