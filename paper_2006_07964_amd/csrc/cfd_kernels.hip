@@ -357,12 +357,15 @@ struct SweepLds {
 // direction tile fastest, then the cross tile c1, then the cross index c2).
 template <int DIR, typename R, int TW, int TS, int NT>
 __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBlock& b, int t, R* sF, StageT<R, DIR>* sFn,
-                                           double* sM) {
+                                           double* sM, R* sV) {
   constexpr int NH = SweepLds<TW, TS>::NH;
   constexpr int NN = SweepLds<TW, TS>::NN;
   constexpr int NW = SweepLds<TW, TS>::NW;
   using L = LdsIdx<DIR, TW>;
   using S = StageT<R, DIR>;
+  // FP64 sweeps stage the direction's viscous fluxes with the tile (their stencil then reads
+  // LDS); FP32 sweeps keep the LDS for a seventh workgroup per CU and read them from memory
+  constexpr bool kStageVis = sizeof(R) == 8;
 
   const Geom& g = b.g;
   const int nd = DIR == 0 ? g.ni : DIR == 1 ? g.nj : g.nk;
@@ -408,7 +411,7 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
   double Jo = 0.0, qno[5], qco[5];
   auto fetch = [&]() {
     if (!out_here) return;
-    if (c.do_vis) {
+    if (c.do_vis && !(kStageVis && c.do_inv)) {  // else staged with the tile
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const GP<const R> vp = plane_ptr(vis, v * plane);
@@ -456,6 +459,10 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
       sM[L::f(0, w, s, NN)] = ldg(mx, p);
       sM[L::f(1, w, s, NN)] = ldg(my, p);
       sM[L::f(2, w, s, NN)] = ldg(mz, p);
+      if (kStageVis && c.do_vis) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sV[L::f(v, w, s, NN)] = ldg(plane_ptr(vis, v * plane), p);
+      }
     }
     __syncthreads();
     // ---- characteristic WENO pair and split fluxes (one node per thread); node n = d0-1+s
@@ -556,8 +563,13 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
     }
   }
   if (c.do_vis) {
+    if (kStageVis && c.do_inv) {
 #pragma unroll
-    for (int v = 1; v < 5; ++v) r[v] += d6<R>([&](int m) { return vm[v - 1][m < 0 ? m + 3 : m + 2]; });
+      for (int v = 1; v < 5; ++v) r[v] += d6<R>([&](int m) { return sV[L::f(v - 1, w, s + 3 + m, NN)]; });
+    } else {
+#pragma unroll
+      for (int v = 1; v < 5; ++v) r[v] += d6<R>([&](int m) { return vm[v - 1][m < 0 ? m + 3 : m + 2]; });
+    }
   }
   if (c.has_prev) {
 #pragma unroll
@@ -587,13 +599,14 @@ struct SweepShared {
   R F[5 * TW * SweepLds<TW, TS>::NH];   // interface fluxes f(n+1/2)
   S Fn[5 * TW * SweepLds<TW, TS>::NN];  // staged Q, then nodal fluxes
   double M[3 * TW * SweepLds<TW, TS>::NN];  // node metrics of the sweep direction
+  R V[sizeof(R) == 8 ? 4 * TW * SweepLds<TW, TS>::NN : 1];  // viscous fluxes (FP64 sweeps)
 };
 
 // Single block: one workgroup per tile, ids remapped XCD-contiguously.
 template <int DIR, typename R, int TW, int TS, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep(SweepArgs a) {
   __shared__ SweepShared<R, StageT<R, DIR>, TW, TS> sh;
-  sweep_tile<DIR, R, TW, TS, NT>(a.c, a.b, xcd_remap(blockIdx.x, gridDim.x), sh.F, sh.Fn, sh.M);
+  sweep_tile<DIR, R, TW, TS, NT>(a.c, a.b, xcd_remap(blockIdx.x, gridDim.x), sh.F, sh.Fn, sh.M, sh.V);
 }
 
 // Batched blocks: one launch walks a work list covering the tiles of every block
@@ -609,7 +622,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const int t = xcd_remap(blockIdx.x, gridDim.x);
     int blk = 0;
     while (t >= tl.prefix[blk + 1]) ++blk;
-    sweep_tile<DIR, R, TW, TS, NT>(c, blocks[blk], t - tl.prefix[blk], sh.F, sh.Fn, sh.M);
+    sweep_tile<DIR, R, TW, TS, NT>(c, blocks[blk], t - tl.prefix[blk], sh.F, sh.Fn, sh.M, sh.V);
     return;
   }
   int start, count, lane_wg, nwg_x;
@@ -618,7 +631,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   for (int u = lane_wg; u < count; u += nwg_x) {
     const int t = start + u;
     while (t >= tl.prefix[blk + 1]) ++blk;  // t only grows, so the scan resumes
-    sweep_tile<DIR, R, TW, TS, NT>(c, blocks[blk], t - tl.prefix[blk], sh.F, sh.Fn, sh.M);
+    sweep_tile<DIR, R, TW, TS, NT>(c, blocks[blk], t - tl.prefix[blk], sh.F, sh.Fn, sh.M, sh.V);
     __syncthreads();  // the next tile overwrites the LDS this one read
   }
 }
