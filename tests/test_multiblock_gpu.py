@@ -131,14 +131,18 @@ def test_o_grid_batched_graph_matches_oracle_and_per_block():
         dev.close()
 
 
-@pytest.mark.parametrize("cfg,persist", [((1, 2, 3), (0, 1, 0)), ((3, 0, 1), (1, 0, 1)), ((4, 5, 4), (0, 1, 1)),
-                                         ((5, 4, 5), (1, 0, 0))])
-def test_batched_tilings_agree(cfg, persist):
+@pytest.mark.parametrize("cfg,persist,precision", [((1, 2, 3), (0, 1, 0), B.CFD_FP64),
+                                                   ((3, 0, 1), (1, 0, 1), B.CFD_FP64),
+                                                   ((4, 5, 4), (0, 1, 1), B.CFD_FP64),
+                                                   ((5, 4, 5), (1, 0, 0), B.CFD_FP64),
+                                                   ((5, 2, 2), (0, 0, 0), B.CFD_MIXED),
+                                                   ((2, 4, 0), (1, 1, 0), B.CFD_MIXED)])
+def test_batched_tilings_agree(cfg, persist, precision):
     """The batched launches with a given tile shape per direction, under both schedules,
-    give the same bits as the per-block launches with those shapes."""
+    give the same bits as the per-block launches with those shapes (FP64 and mixed)."""
     import torch
     wl = W.o_grid_vortices(sizes=SMALL_OGRID)
-    a, b = DevMulti(wl), DevMulti(wl)
+    a, b = DevMulti(wl, precision=precision), DevMulti(wl, precision=precision)
     for h in a.h:
         B.cfd_block_set_tiles(h, cfg)
     try:
