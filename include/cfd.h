@@ -161,7 +161,8 @@ int cfd_exchange_destroy(cfd_exchange* x);
  * copies 3-deep face slabs across interfaces, then ghost-fills walls and far field and
  * resets wall nodes (no slip, T = t_wall).  CFD_FIELDS_VISC: block_bufs must be NULL;
  * copies the library's viscous-flux planes (direction-d components across d-faces).
- * Enqueued on hip_stream (NULL: the first block's stream).                              */
+ * Enqueued on hip_stream (NULL: the first block's stream); the caller orders it after the
+ * work that produced the buffers when blocks use other streams.                         */
 int cfd_halo_exchange(cfd_exchange* x, int field_set, void* const* block_bufs, void* hip_stream);
 
 /* ---- time step and checks ---------------------------------------------------------- */

@@ -615,11 +615,16 @@ int cfd_dt_cfl(cfd_block* const* blocks, int nb, const double* const* Q, double 
   if (!(cfl > 0.0)) return fail(CFD_ERR_ARG, "cfl must be positive");
   cfd_block* b0 = blocks[0];
   if (!b0) return fail(CFD_ERR_ARG, "null block");
+  for (int n = 0; n < nb; ++n) {
+    if (!blocks[n] || !Q[n]) return fail(CFD_ERR_ARG, "null block or state");
+    if (!blocks[n]->have_metrics) return fail(CFD_ERR_STATE, "cfd_metrics has not been run on a block");
+  }
+  // the reduction runs on the first block's stream: finish earlier work of the others
+  for (int n = 1; n < nb; ++n)
+    if (blocks[n]->stream != b0->stream) HIP_TRY(hipStreamSynchronize(blocks[n]->stream), "stream synchronize");
   HIP_TRY(hipMemsetAsync(b0->red_dev, 0, sizeof(unsigned long long), b0->stream), "memset");
   for (int n = 0; n < nb; ++n) {
     cfd_block* b = blocks[n];
-    if (!b || !Q[n]) return fail(CFD_ERR_ARG, "null block or state");
-    if (!b->have_metrics) return fail(CFD_ERR_STATE, "cfd_metrics has not been run on a block");
     HIP_TRY(launch_dt_max(b->g, Q[n], b->met, b->d.params.gamma, b0->red_dev, b0->stream), "dt launch");
   }
   unsigned long long bits = 0;
