@@ -1011,6 +1011,8 @@ int batch_step(cfd_batch* bt, const double* dt_dev, double* const* Qn, double* c
   HIP_TRY(hipEventRecord(bt->ev_in, bt->user), "event record");
   HIP_TRY(hipStreamWaitEvent(bt->stream, bt->ev_in, 0), "stream wait");
   if (key != bt->key || !bt->exec) {
+    // the argument tables are rewritten below: earlier replays must have finished reading them
+    HIP_TRY(hipStreamSynchronize(bt->stream), "stream synchronize");
     if (!bt->tuned) {
       int rc = autotune(bt, Qn, QA, QB, dt_dev);
       if (rc) return rc;
