@@ -14,6 +14,13 @@
  *   metrics                met[10][...]: 3*d+c holds the hatted metric (d in xi,eta,zeta;
  *                          c in x,y,z), i.e. xi_x/J etc. (Sec. 2, Eq 7); met[9] holds J.
  * Return values: 0 on success, negative on error (see each function).
+ *
+ * Pins: every function is checked by the CPU tests against closed forms, invariants,
+ * exact solutions or brute force, except where the paper fixes nothing to check against
+ * ("parity unpinned"): the Sutherland constant of oracle_viscosity (only mu(1) = 1 is
+ * pinned), the wall and far-field treatment of oracle_wall_reset / oracle_bc_fill (only
+ * the symmetry of a symmetric channel is checked), and the choice of eigenvector basis in
+ * oracle_eigvec beyond L R = I and L A R = diag(lambda).
  */
 #ifndef CFD_ORACLE_H
 #define CFD_ORACLE_H
@@ -70,9 +77,11 @@ int oracle_rk_step(const oracle_cfg* c, const double* met, double dt, double* Q)
 /* Fill the halo of nvar planes of a single periodic block by periodic wrap.             */
 void oracle_periodic_wrap(const oracle_cfg* c, double* A, int nvar);
 
-/* Wall nodes of one block: zero velocity, T = t_wall at their own density.              */
+/* Wall nodes of one block: zero velocity, T = t_wall at their own density
+ * (parity unpinned: the paper does not specify its boundary conditions).               */
 void oracle_wall_reset(const oracle_cfg* c, double* Q);
-/* Ghost fill of wall / far-field faces of one block (after the halo copies).           */
+/* Ghost fill of wall / far-field faces of one block (after the halo copies; parity
+ * unpinned, as above).                                                                  */
 void oracle_bc_fill(const oracle_cfg* c, double* Q);
 
 /* CFL time step: cfl / max over interior of sum_d (|U_d| + c |grad d|).                 */
@@ -84,13 +93,15 @@ double oracle_dt_cfl(const oracle_cfg* c, const double* met, const double* Q, do
  * out[1] = right-biased value at i-1/2; beta[0..2] receives the smoothness indicators. */
 void oracle_weno5(const double* v, double eps, int linear, double* out, double* beta);
 /* Right eigenvectors R (columns, row-major 5x5) and L = R^-1 of the flux Jacobian in
- * the unit direction k at the conserved state q.                                        */
+ * the unit direction k at the conserved state q (L R = I and L A R = diag are pinned;
+ * the basis of the triple eigenvalue is a reading, parity unpinned beyond that).       */
 int oracle_eigvec(const double* q, const double* k, double gamma, double* L, double* R);
 /* Steger-Warming split fluxes F+ and F- of state q for the hatted metric vector m.     */
 void oracle_split_flux(const double* q, const double* m, double gamma, double* Fp, double* Fm);
 /* Physical (inviscid) flux of Eq 4 for the hatted metric vector m.                     */
 void oracle_phys_flux(const double* q, const double* m, double gamma, double* F);
-/* Sutherland viscosity law used for mu(T).                                             */
+/* Sutherland viscosity law used for mu(T) (parity unpinned: the paper names no law;
+ * mu(1) = 1 is pinned).                                                                 */
 double oracle_viscosity(double T, double suth);
 
 /* ---- multi-block (blocks on one host, 1-to-1 aligned face interfaces) ------------- */
