@@ -291,7 +291,8 @@ def main():
     else:
         cfg["tiles"] = B.cfd_block_tiles(hs[0])
     out = {
-        "metric": "grid-point RK3 stage updates/s",
+        # the headline metric: updates/s is `value`, the HBM GB/s and % of peak are in `roofline`
+        "metric": "grid-point RK3 stage updates/s (FP64 vs mixed/batched) + HBM GB/s % of peak",
         "value": value,
         "unit": "updates/s",
         "n_gpus": 1,
