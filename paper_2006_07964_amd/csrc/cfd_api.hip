@@ -310,11 +310,14 @@ int run_visc(cfd_block* b, const double* Q) {
   va.met_r = b->met_r;
   va.vis = b->vis;
   va.ph = make_phys(b->d.params);
+  // the prepass writes the periodic images itself (they were the only local copies)
+  for (int ax = 0; ax < 3; ++ax)
+    if (b->d.bc[2 * ax] == CFD_BC_PERIODIC) va.periodic |= 1 << ax;
   ProfScope ps(&b->prof, "visc_prepass", b->stream);
   hipError_t e = b->d.precision == CFD_FP64 ? launch_visc<double>(va, b->stream) : launch_visc<float>(va, b->stream);
   ps.done();
   if (e != hipSuccess) return hip_fail(e, "visc_prepass launch");
-  if (b->n_local_copy) {
+  if (b->n_local_copy && !va.periodic) {
     PtrTable t = single_table<double>(b->vis, b->g.plane);
     ProfScope pc(&b->prof, "visc_halo", b->stream);
     e = b->d.precision == CFD_FP64 ? launch_copy<double>(b->local_copy_dev, b->n_local_copy, b->max_local_copy, t, b->stream)

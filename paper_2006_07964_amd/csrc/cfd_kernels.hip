@@ -248,10 +248,24 @@ __device__ __forceinline__ void visc_tile(const ViscArgs& a, int t, ViscShared<R
       for (int c = 0; c < 3; ++c) bet[c] = u * tau[0][c] + v * tau[1][c] + w * tau[2][c] + hs * dx[3][c];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
+        R f[4];
 #pragma unroll
-        for (int n = 0; n < 3; ++n)
-          stg(plane_ptr(out, (4 * d + n) * plane), p, mh[d][0] * tau[n][0] + mh[d][1] * tau[n][1] + mh[d][2] * tau[n][2]);
-        stg(plane_ptr(out, (4 * d + 3) * plane), p, mh[d][0] * bet[0] + mh[d][1] * bet[1] + mh[d][2] * bet[2]);
+        for (int n = 0; n < 3; ++n) f[n] = mh[d][0] * tau[n][0] + mh[d][1] * tau[n][1] + mh[d][2] * tau[n][2];
+        f[3] = mh[d][0] * bet[0] + mh[d][1] * bet[1] + mh[d][2] * bet[2];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) stg(plane_ptr(out, (4 * d + n) * plane), p, f[n]);
+        // a block periodic with itself along d: the node's image in the halo across the
+        // d-faces (the direction-d flux is the one the d sweep differentiates)
+        if (a.periodic & (1 << d)) {
+          const int idx = d == 0 ? i : d == 1 ? j : k;
+          const int nd = d == 0 ? g.ni : d == 1 ? g.nj : g.nk;
+          const uint32_t sd = d == 0 ? 1u : d == 1 ? (uint32_t)g.ld_i : sk;
+          if (idx < kHalo || idx >= nd - kHalo) {
+            const uint32_t pi = idx < kHalo ? p + (uint32_t)nd * sd : p - (uint32_t)nd * sd;
+#pragma unroll
+            for (int n = 0; n < 4; ++n) stg(plane_ptr(out, (4 * d + n) * plane), pi, f[n]);
+          }
+        }
       }
     }
 #pragma unroll

@@ -36,6 +36,8 @@ struct ViscArgs {
   void* vis;  // 12 planes of the compute type
   Phys ph;
   int kc;     // planes per tile (set by visc_tiling)
+  int periodic;  // bit d: the block is periodic with itself along d, the kernel fills
+                 // the direction-d flux halos across the d-faces
 };
 template <typename R>
 hipError_t launch_visc(ViscArgs a, hipStream_t s);
