@@ -17,6 +17,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -56,13 +57,21 @@ def kernel_bytes(table, order):
 HBM_PEAK_GBS = 8000.0
 
 
+def _code_only(text: str) -> str:
+    """Source text without comments and whitespace runs (a comment edit changes no kernel)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def source_sha() -> str:
+    """Hash of the kernel and library sources (code only), to tie measured counters to them."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2006_07964_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as fh:
+        with open(os.path.join(csrc, name), encoding="utf-8") as fh:
             h.update(name.encode())
-            h.update(fh.read())
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -339,9 +339,11 @@ template hipError_t launch_visc_batch<float>(const ViscArgs*, const TileList&, h
 // RK3 stage of Eq 20).
 //
 // A workgroup owns a tile of TW grid lines (cross direction c1) by TS output nodes along
-// the sweep direction.  Phase 1 evaluates, per node, the characteristic WENO pair and the
-// two split fluxes (nodes d0-1 .. d0+TS) and the nodal fluxes (d0-3 .. d0+TS+2) into LDS;
-// phase 2 assembles Eq 19 per output node.
+// the sweep direction.  It stages Q, the direction's node metrics and (FP64) viscous
+// fluxes of nodes d0-3 .. d0+TS+2 in LDS; evaluates per node the characteristic WENO pair
+// and the two split fluxes (nodes d0-1 .. d0+TS, one per thread) into interface fluxes;
+// replaces the staged Q by the nodal fluxes; and assembles Eq 19, the viscous derivative
+// and the output per output node (one per thread).
 // =====================================================================================
 template <int DIR, int TW>
 struct LdsIdx {
@@ -351,8 +353,6 @@ struct LdsIdx {
     return DIR == 0 ? (v * TW + w) * len + s : (v * len + s) * TW + w;
   }
 };
-
-
 
 // Type of the staged Q / nodal-flux tile: FP64 in FP64 sweeps and in the last sweep
 // direction (the one that carries the RK combination, which then takes Q from the tile in
