@@ -955,12 +955,13 @@ int autotune(cfd_batch* bt, double* const* Qn, double* const* QA, double* const*
   HIP_TRY(hipEventCreate(&e1), "event");
   int rc = CFD_OK;
   if (bt->viscous) {  // the sweeps read the viscous-flux planes of the state being tuned on
-    if ((rc = upload_args(bt, Qn, QA, QB, dt_dev)) != CFD_OK) return rc;
-    const int nb = (int)bt->blocks.size();
-    hipError_t e = bt->precision == CFD_FP64
-                       ? launch_visc_batch<double>(bt->visc_args_dev, bt->visc_tl, bt->stream)
-                       : launch_visc_batch<float>(bt->visc_args_dev, bt->visc_tl, bt->stream);
-    if (e != hipSuccess) rc = hip_fail(e, "tuning prepass");
+    rc = upload_args(bt, Qn, QA, QB, dt_dev);
+    if (rc == CFD_OK) {
+      hipError_t e = bt->precision == CFD_FP64
+                         ? launch_visc_batch<double>(bt->visc_args_dev, bt->visc_tl, bt->stream)
+                         : launch_visc_batch<float>(bt->visc_args_dev, bt->visc_tl, bt->stream);
+      if (e != hipSuccess) rc = hip_fail(e, "tuning prepass");
+    }
   }
   for (int d = 0; d < 3 && rc == CFD_OK; ++d) {
     float best = 1e30f;

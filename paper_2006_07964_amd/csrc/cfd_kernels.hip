@@ -125,9 +125,9 @@ hipError_t launch_metrics(const MetricArgs& a, hipStream_t s) {
 // formed about twice per chunk instead of at each of its eighteen stencil uses, and Q is
 // read once per column.
 // =====================================================================================
-constexpr int VI = 64, VJ = 8, VNT = VI * VJ;
-constexpr int kViscChunk = 32;      // planes per workgroup (fewer when nk is smaller)
-constexpr int kViscMinTiles = 1024;  // workgroups a single-block launch aims for
+constexpr int VI = 64, VJ = 16, VNT = VI * VJ;
+constexpr int kViscChunk = 64;     // most planes per workgroup (fewer when nk is smaller)
+constexpr int kViscMinTiles = 256;  // workgroups a single-block launch aims for (one per CU)
 
 template <typename R>
 struct ViscShared {
@@ -294,13 +294,15 @@ hipError_t launch_round(const double* src, float* dst, int64_t n, hipStream_t s)
 }
 
 // chunk length and tile count of one block (i-tile fastest, then j-tile, then k-chunk):
-// kViscChunk planes per tile, halved (down to 8) while the block would give fewer than
-// min_tiles workgroups; a longer chunk re-reads fewer priming planes, more tiles fill the chip
+// at most kViscChunk planes per tile, that bound halved (down to 8) while the block would
+// give fewer than min_tiles workgroups, and nk split into the fewest chunks of equal length
+// under it; a longer chunk re-reads fewer priming planes, more tiles fill the chip
 void visc_tiling(const Geom& g, int min_tiles, int* kc, int* tiles) {
   const int cols = ((g.ni + VI - 1) / VI) * ((g.nj + VJ - 1) / VJ);
   int c = kViscChunk;
   while (c > 8 && cols * ((g.nk + c - 1) / c) < min_tiles) c /= 2;
-  *kc = g.nk < c ? g.nk : c;
+  const int nch = (g.nk + c - 1) / c;
+  *kc = (g.nk + nch - 1) / nch;
   *tiles = cols * ((g.nk + *kc - 1) / *kc);
 }
 
