@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 
 XI, ETA, ZETA, INV, VIS, ALL = 1, 2, 4, 8, 16, 31
+AFWENO_MODIFIED, AFWENO_ORIGINAL = 0, 1
 BC_PERIODIC, BC_INTERFACE, BC_WALL, BC_FARFIELD = 0, 1, 2, 3
 
 
@@ -35,7 +36,7 @@ class Cfg(C.Structure):
         ("ni", C.c_int), ("nj", C.c_int), ("nk", C.c_int),
         ("gamma", C.c_double), ("mach", C.c_double), ("reynolds", C.c_double),
         ("prandtl", C.c_double), ("suth", C.c_double), ("eps", C.c_double),
-        ("viscous", C.c_int), ("linear_weights", C.c_int), ("bc", C.c_int * 6),
+        ("viscous", C.c_int), ("linear_weights", C.c_int), ("scheme", C.c_int), ("bc", C.c_int * 6),
         ("t_wall", C.c_double), ("qinf", C.c_double * 5),
     ]
 
@@ -92,13 +93,14 @@ def _p(a: np.ndarray):
 
 
 def make_cfg(ni, nj, nk, gamma=1.4, mach=0.5, reynolds=1000.0, prandtl=0.71,
-             suth=110.4 / 288.15, eps=1e-6, viscous=True, linear_weights=False,
+             suth=110.4 / 288.15, eps=1e-6, viscous=True, linear_weights=False, scheme=0,
              bc=(0, 0, 0, 0, 0, 0), t_wall=1.0, qinf=(1.0, 0.0, 0.0, 0.0, 1.0 / (1.4 * 0.4))) -> Cfg:
     c = Cfg()
     c.ni, c.nj, c.nk = ni, nj, nk
     c.gamma, c.mach, c.reynolds, c.prandtl, c.suth, c.eps = gamma, mach, reynolds, prandtl, suth, eps
     c.viscous = int(bool(viscous))
     c.linear_weights = int(bool(linear_weights))
+    c.scheme = int(scheme)
     for n in range(6):
         c.bc[n] = int(bc[n])
     c.t_wall = t_wall

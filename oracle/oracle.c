@@ -572,6 +572,76 @@ static void afweno_line(const oracle_cfg* c, int n, const double (*q)[5], const 
 #undef MHALF
 }
 
+/* ------------------------------------------------------------------------------------ */
+/* Inviscid derivative along one grid line with the original AFWENO (Sec. 4.5.1, Fig 9): */
+/* the characteristic space of each half point i+1/2 is built there, and the two split  */
+/* fluxes of that half point come from two complete WENO interpolations in it.  Same   */
+/* line layout as afweno_line.                                                          */
+/* Readings: the state at i+1/2 is the arithmetic mean of the conserved states at i and  */
+/* i+1 (the paper names no average); the direction of the characteristic space is the   */
+/* half-point metric of the split fluxes, normalised.                                   */
+/* ------------------------------------------------------------------------------------ */
+static void afweno_line_original(const oracle_cfg* c, int n, const double (*q)[5], const double (*m)[3],
+                                 double (*D)[5], double (*fnode)[5], double (*fhalf)[5]) {
+  int node, v, t, a;
+  for (node = -1; node <= n - 1; ++node) {
+    double mh[3], kt[3], mag, qa[5], L[25], R[25], Vl[5][5], Vr[5][5], vl[5], vr[5], ul[5], ur[5];
+    double Fpp[5], Fmm[5], Fpm[5], Fmp[5];
+    /* half-point metrics (same sixth-order interpolation as the modified scheme) */
+    for (a = 0; a < 3; ++a)
+      mh[a] = (3.0 * m[node - 2 + 3][a] - 25.0 * m[node - 1 + 3][a] + 150.0 * m[node + 3][a] +
+               150.0 * m[node + 1 + 3][a] - 25.0 * m[node + 2 + 3][a] + 3.0 * m[node + 3 + 3][a]) / 256.0;
+    mag = sqrt(mh[0] * mh[0] + mh[1] * mh[1] + mh[2] * mh[2]);
+    for (a = 0; a < 3; ++a) kt[a] = mh[a] / mag;
+    /* left and right eigenvectors at i+1/2 */
+    for (v = 0; v < 5; ++v) qa[v] = 0.5 * (q[node + 3][v] + q[node + 1 + 3][v]);
+    oracle_eigvec(qa, kt, c->gamma, L, R);
+    /* characteristic variables of (i-2..i+2) for the value left of i+1/2 and of
+     * (i-1..i+3) for the value right of it, both in the space of i+1/2 */
+    for (t = 0; t < 5; ++t)
+      for (v = 0; v < 5; ++v) {
+        double al = 0.0, ar = 0.0;
+        for (a = 0; a < 5; ++a) {
+          al += L[v * 5 + a] * q[node - 2 + t + 3][a];
+          ar += L[v * 5 + a] * q[node - 1 + t + 3][a];
+        }
+        Vl[t][v] = al;
+        Vr[t][v] = ar;
+      }
+    /* two WENO interpolations per field: the left-biased value at i+1/2 of the stencil
+     * centred on i, and the right-biased value at (i+1)-1/2 of the stencil centred on i+1 */
+    for (v = 0; v < 5; ++v) {
+      double col[5], out[2];
+      for (t = 0; t < 5; ++t) col[t] = Vl[t][v];
+      oracle_weno5(col, c->eps, c->linear_weights, out, NULL);
+      vl[v] = out[0];
+      for (t = 0; t < 5; ++t) col[t] = Vr[t][v];
+      oracle_weno5(col, c->eps, c->linear_weights, out, NULL);
+      vr[v] = out[1];
+    }
+    /* back to conserved variables with R at i+1/2 */
+    for (v = 0; v < 5; ++v) {
+      double al = 0.0, ar = 0.0;
+      for (a = 0; a < 5; ++a) { al += R[v * 5 + a] * vl[a]; ar += R[v * 5 + a] * vr[a]; }
+      ul[v] = al;
+      ur[v] = ar;
+    }
+    /* f(i+1/2) = F+(left value) + F-(right value), both through the half-point metric */
+    oracle_split_flux(ul, mh, c->gamma, Fpp, Fpm);
+    oracle_split_flux(ur, mh, c->gamma, Fmp, Fmm);
+    for (v = 0; v < 5; ++v) fhalf[node + 1][v] = Fpp[v] + Fmm[v];
+  }
+  /* nodal physical flux, Eq 4, and the assembly of Eq 19 as in the modified scheme */
+  for (node = -3; node <= n + 2; ++node) oracle_phys_flux(q[node + 3], m[node + 3], c->gamma, fnode[node + 3]);
+  for (node = 0; node < n; ++node)
+    for (v = 0; v < 5; ++v) {
+      const double fp = fhalf[node + 1][v], fm = fhalf[node][v];
+      D[node][v] = fp - fm + 17.0 / 256.0 * (fnode[node + 1 + 3][v] - fnode[node - 1 + 3][v]) -
+                   13.0 / 320.0 * (fnode[node + 2 + 3][v] - fnode[node - 2 + 3][v]) +
+                   19.0 / 3840.0 * (fnode[node + 3 + 3][v] - fnode[node - 3 + 3][v]);
+    }
+}
+
 /* Rtilde contributions of all requested terms, then R = J * Rtilde (Eq 2, A: Q is
  * stored without 1/J and the grid is stationary, so dQ/dt = J * Rtilde).             */
 static void rhs_core(const oracle_cfg* c, const double* met, const double* Q, const double* V,
@@ -611,7 +681,9 @@ static void rhs_core(const oracle_cfg* c, const double* met, const double* Q, co
         for (v = 0; v < 5; ++v) q[s + 3][v] = Q[v * sd.plane + pp];
         for (v = 0; v < 3; ++v) m[s + 3][v] = met[(3 * dir + v) * sd.plane + pp];
       }
-      if (mask & ORACLE_INV) {
+      if ((mask & ORACLE_INV) && c->scheme == ORACLE_AFWENO_ORIGINAL) {
+        afweno_line_original(c, n, (const double(*)[5])q, (const double(*)[3])m, D, fn, fh);
+      } else if (mask & ORACLE_INV) {
         afweno_line(c, n, (const double(*)[5])q, (const double(*)[3])m, D, Fp, Fm, fn, fh);
       } else {
         for (node = 0; node < n; ++node)
@@ -651,6 +723,7 @@ static void rhs_core(const oracle_cfg* c, const double* met, const double* Q, co
 
 static int check_cfg(const oracle_cfg* c) {
   if (c->ni < 7 || c->nj < 7 || c->nk < 7) return -1;
+  if (c->scheme != ORACLE_AFWENO_MODIFIED && c->scheme != ORACLE_AFWENO_ORIGINAL) return -1;
   return 0;
 }
 

@@ -19,8 +19,10 @@
  * exact solutions or brute force, except where the paper fixes nothing to check against
  * ("parity unpinned"): the Sutherland constant of oracle_viscosity (only mu(1) = 1 is
  * pinned), the wall and far-field treatment of oracle_wall_reset / oracle_bc_fill (only
- * the symmetry of a symmetric channel is checked), and the choice of eigenvector basis in
- * oracle_eigvec beyond L R = I and L A R = diag(lambda).
+ * the symmetry of a symmetric channel is checked), the choice of eigenvector basis in
+ * oracle_eigvec beyond L R = I and L A R = diag(lambda), and, for the original AFWENO
+ * scheme, the arithmetic mean as the state of the half-point characteristic space beyond
+ * its mirror symmetry (any symmetric average of the two nodes passes the pins).
  */
 #ifndef CFD_ORACLE_H
 #define CFD_ORACLE_H
@@ -29,6 +31,10 @@
 #ifdef __cplusplus
 extern "C" {
 #endif
+
+/* inviscid scheme: characteristic space at the nodes (modified AFWENO, Sec. 4.5.1,
+ * Figs 10-11) or at the half points (original AFWENO, Fig 9) */
+enum { ORACLE_AFWENO_MODIFIED = 0, ORACLE_AFWENO_ORIGINAL = 1 };
 
 /* face boundary kinds, one per face in the order (i-,i+,j-,j+,k-,k+) */
 enum { ORACLE_BC_PERIODIC = 0, ORACLE_BC_INTERFACE = 1, ORACLE_BC_WALL = 2, ORACLE_BC_FARFIELD = 3 };
@@ -42,6 +48,7 @@ typedef struct oracle_cfg {
   double eps;              /* WENO epsilon (Eq 15)                                */
   int viscous;             /* 1: add the viscous terms, 0: Euler                  */
   int linear_weights;      /* 1: ideal weights gamma_j instead of Eq 15           */
+  int scheme;              /* ORACLE_AFWENO_MODIFIED (Fig 11) or _ORIGINAL (Fig 9) */
   int bc[6];               /* face kinds (ORACLE_BC_*)                            */
   double t_wall;           /* isothermal wall temperature                         */
   double qinf[5];          /* far-field conserved state                           */

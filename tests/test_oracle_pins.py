@@ -153,13 +153,13 @@ def test_eq18_exact_on_even_powers():
     assert sum(c * x ** 2 for c, x in zip(f4, xs)) == 0
 
 
-def _entropy_wave_line(n, rho_of_x, u=2.0, direction=0, viscous=False, linear=True):
+def _entropy_wave_line(n, rho_of_x, u=2.0, direction=0, viscous=False, linear=True, scheme=O.AFWENO_MODIFIED):
     """Cartesian block with unit spacing; rho varies along one axis, u along that axis."""
     ni = nj = nk = 7
     dims = [ni, nj, nk]
     dims[direction] = n
     ni, nj, nk = dims
-    c = O.make_cfg(ni, nj, nk, viscous=viscous, linear_weights=linear)
+    c = O.make_cfg(ni, nj, nk, viscous=viscous, linear_weights=linear, scheme=scheme)
     xyz = W.cartesian_grid(ni, nj, nk, ni, nj, nk)
     met = O.metrics(c, xyz)
     K, J, I = W.index_grid(ni, nj, nk, halo=3)
@@ -190,12 +190,15 @@ def test_inviscid_operator_exact_on_quintics(direction):
     np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12)
 
 
-def test_inviscid_stencil_is_the_paper_scheme():
+@pytest.mark.parametrize("scheme", [O.AFWENO_MODIFIED, O.AFWENO_ORIGINAL])
+def test_inviscid_stencil_is_the_paper_scheme(scheme):
     """Impulse response of the supersonic entropy wave equals the stencil built from the
-    printed coefficients: upwind 5-point interpolation (Eqs 13-14, 16) + Eq 19."""
+    printed coefficients: upwind 5-point interpolation (Eqs 13-14, 16) + Eq 19.  Both the
+    modified AFWENO (characteristic space at the nodes) and the original one (at the half
+    points, Fig 9) reduce to it with ideal weights."""
     n = 24
     amp = 1e-3
-    c, met, q0, s = _entropy_wave_line(n, lambda x: np.ones_like(x), u=2.0, direction=0)
+    c, met, q0, s = _entropy_wave_line(n, lambda x: np.ones_like(x), u=2.0, direction=0, scheme=scheme)
     base = O.rhs(c, met, q0, O.INV | O.XI)
     # exact-fraction stencil: f(i+1/2) from nodes i-2..i+2, then Eq 19
     interp = _vandermonde_weights([-2, -1, 0, 1, 2], Fraction(1, 2))
@@ -351,9 +354,10 @@ def test_metrics_converge_to_analytic_on_wavy_grid():
 # --------------------------------------------------------------------------------------
 # invariants of the full right-hand side
 # --------------------------------------------------------------------------------------
-def test_free_stream_preservation_on_wavy_grid():
+@pytest.mark.parametrize("scheme", [O.AFWENO_MODIFIED, O.AFWENO_ORIGINAL])
+def test_free_stream_preservation_on_wavy_grid(scheme):
     wl = W.vortex_wavy(32, seed=None)
-    c = O.cfg_from_workload(wl)
+    c = O.cfg_from_workload(wl, scheme=scheme)
     met = O.metrics(c, wl.blocks[0].xyz)
     q = W.uniform_state(wl.blocks[0].q.shape[1:], u=0.5, v=-0.2, w=0.1)
     r = O.rhs(c, met, q)
@@ -681,11 +685,11 @@ def test_sod_exact_solver_textbook_values():
     assert abs(rl - 0.42632) < 1e-5 and abs(rr - 0.26557) < 1e-5 and abs(s - 1.75216) < 1e-5
 
 
-def _double_shock_tube(n, t_end=0.15):
+def _double_shock_tube(n, t_end=0.15, scheme=O.AFWENO_MODIFIED):
     """The two mirror-image shock tubes of workloads.double_shock_tube, advanced to t_end
     with the oracle (Euler, WENO-JS, fixed dt = 0.3 dx)."""
     wl = W.double_shock_tube(n)
-    c = O.cfg_from_workload(wl)
+    c = O.cfg_from_workload(wl, scheme=scheme)
     met = O.metrics(c, wl.blocks[0].xyz)
     q = wl.blocks[0].q.copy()
     dx = 1.0 / n
@@ -703,14 +707,17 @@ def _double_shock_tube(n, t_end=0.15):
     return q[0, 3:-3, 3:-3, 3:-3], exact
 
 
-def test_shock_tube_weno_js_bounded_and_converging():
+@pytest.mark.parametrize("scheme", [O.AFWENO_MODIFIED, O.AFWENO_ORIGINAL])
+def test_shock_tube_weno_js_bounded_and_converging(scheme):
     """P15: WENO-JS with the characteristic projection and Steger-Warming splitting on two
     mirror-image shock tubes: the solution is uniform across the tube, mirror symmetric,
     free of overshoots beyond 1% of the density jump, and its L1 density error against the
-    exact Riemann solution falls with the resolution."""
+    exact Riemann solution falls with the resolution.  For the original AFWENO the mirror
+    symmetry also pins the state of the half-point characteristic space: it has to be a
+    symmetric function of the two neighbouring nodes."""
     errs = []
     for n in (64, 128, 256):
-        rho, exact = _double_shock_tube(n)
+        rho, exact = _double_shock_tube(n, scheme=scheme)
         assert np.max(np.abs(rho - rho[:1, :1, :])) < 1e-12  # no variation across the tube
         line = rho[0, 0]
         # mirror symmetry about x = 0.5 - dx/2: node i <-> node n - 1 - i
@@ -721,3 +728,63 @@ def test_shock_tube_weno_js_bounded_and_converging():
     print("L1 density errors", errs)
     assert errs[0] > errs[1] > errs[2]
     assert errs[2] < 0.01
+
+
+# ---- original AFWENO (Fig 9) against the modified one ---------------------------------
+def _vortex_with_step(n=20, seed=11):
+    """C1-like wavy periodic block, isentropic vortex plus noise, with steps in density and
+    pressure at i = 0 and i = n/2 so that the nonlinear weights depart from the ideal ones."""
+    wl = W.vortex_wavy(n, seed=seed, viscous=False)
+    q = wl.blocks[0].q.copy()
+    K, J, I = W.index_grid(n, n, n, halo=3)
+    bump = 1.0 + 0.3 * ((I % n) >= n // 2)
+    q *= bump[None]  # scales rho, rho u, E alike: velocity and T unchanged, rho and p jump
+    return wl, q
+
+
+def test_original_afweno_equals_modified_with_ideal_weights():
+    """With ideal weights both schemes interpolate Q itself (R L = I cancels the
+    projection): the left value at i+1/2 is the 5-point interpolant of nodes i-2..i+2 and
+    the right one that of i-1..i+3, whichever node or half point hosts the characteristic
+    space.  The two RHS agree to round-off on a curvilinear grid in every direction."""
+    wl, q = _vortex_with_step()
+    cm = O.cfg_from_workload(wl, linear_weights=True, viscous=False)
+    co = O.cfg_from_workload(wl, linear_weights=True, viscous=False, scheme=O.AFWENO_ORIGINAL)
+    met = O.metrics(cm, wl.blocks[0].xyz)
+    rm = interior(O.rhs(cm, met, q, O.INV | O.XI | O.ETA | O.ZETA))
+    ro = interior(O.rhs(co, met, q, O.INV | O.XI | O.ETA | O.ZETA))
+    scale = np.max(np.abs(rm), axis=(1, 2, 3))
+    err = np.max(np.abs(ro - rm), axis=(1, 2, 3)) / scale
+    print("ideal weights, original vs modified", err)
+    assert np.all(err < 1e-12)
+
+
+def test_original_afweno_differs_from_modified_with_weno_js():
+    """With the nonlinear weights the characteristic space matters: the two schemes give
+    different fluxes at density steps and agree closely on a resolved smooth wave."""
+    n = 24
+    wl = W.vortex_wavy(n, seed=None, viscous=False)
+    cm = O.cfg_from_workload(wl, viscous=False)
+    co = O.cfg_from_workload(wl, viscous=False, scheme=O.AFWENO_ORIGINAL)
+    met = O.metrics(cm, wl.blocks[0].xyz)
+    K, J, I = W.index_grid(n, n, n, halo=3)
+    ii = I % n
+    rho = 1.0 + 0.1 * np.sin(2 * np.pi * ii / n) + 0.5 * ((ii >= n // 4) & (ii < 3 * n // 4))
+    one = np.ones_like(rho)
+    q = W.conserved(rho, 0.3 * one, 0.1 * one, 0.0 * one, one / 1.4)
+    rm = interior(O.rhs(cm, met, q, O.INV | O.XI))
+    ro = interior(O.rhs(co, met, q, O.INV | O.XI))
+    d = np.max(np.abs(ro - rm), axis=(0, 1, 2))  # per i
+    near = [i for i in range(n) if min(abs(i - n // 4), abs(i - 3 * n // 4)) <= 4]
+    far = [i for i in range(n) if i not in near]
+    scale = np.max(np.abs(rm))
+    print("WENO-JS, |original - modified| near / away from the steps", d[near].max() / scale, d[far].max() / scale)
+    assert d[near].max() > 1e-5 * scale
+    assert d[far].max() < 1e-2 * d[near].max()
+
+
+def test_original_afweno_rejects_unknown_scheme():
+    c = O.make_cfg(8, 8, 8, scheme=7)
+    met = np.zeros(O.state_shape(c, 10))
+    with pytest.raises(ValueError):
+        O.rhs(c, met, np.ones(O.state_shape(c)))
