@@ -113,12 +113,12 @@ def build_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(wl, workload_name):
+def cpu_baseline(wl, workload_name, scheme=0):
     """The oracle, as it stands, timed on the host: one full RK3 step (three stages) of the
-    same workload."""
+    same workload with the same inviscid scheme."""
     import oracle as O
     b = wl.blocks[0]
-    c = O.cfg_from_workload(wl)
+    c = O.cfg_from_workload(wl, scheme=scheme)
     met = O.metrics(c, b.xyz)
     dt = O.dt_cfl(c, met, b.q, wl.cfl)
     t0 = time.perf_counter()
@@ -161,6 +161,9 @@ def main():
     ap.add_argument("--form", default=None, choices=["single", "perblock", "batched"],
                     help="single-block calls, per-block launches, or the batched graph form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--scheme", default="modified", choices=["modified", "original"],
+                    help="inviscid scheme: modified AFWENO (characteristic space at the nodes) or the "
+                         "original one (at the half points); the batched form runs the modified one")
     ap.add_argument("--tiles", default=None,
                     help="sweep tile shapes xi,eta,zeta of the single / per-block forms (library default if unset)")
     args = ap.parse_args()
@@ -183,10 +186,13 @@ def main():
     form = args.form or ("single" if nb == 1 else "perblock")
     if form == "single" and nb != 1:
         raise SystemExit("--form single needs a single-block workload")
+    scheme = B.CFD_AFWENO_ORIGINAL if args.scheme == "original" else B.CFD_AFWENO_MODIFIED
+    if form == "batched" and scheme != B.CFD_AFWENO_MODIFIED:
+        raise SystemExit("the batched form runs the modified AFWENO scheme only")
     descs, hs, qs, qas, qbs = [], [], [], [], []
     for bi, blk in enumerate(wl.blocks):
         # rows padded to 16 doubles and offset so that interior rows start 128-byte lines
-        desc = B.desc_from_workload(wl, bi, prec, ld_i=B.aligned_pitch(blk.ni))
+        desc = B.desc_from_workload(wl, bi, prec, ld_i=B.aligned_pitch(blk.ni), scheme=scheme)
         h = B.cfd_block_create(desc, stream)
         if args.tiles:
             B.cfd_block_set_tiles(h, [int(v) for v in args.tiles.split(",")])
@@ -289,6 +295,7 @@ def main():
     copy_gbs = copy_bandwidth(torch)
 
     cfg = {"workload": wname, "blocks": nb, "points": points, "precision": args.precision, "form": form,
+           "scheme": args.scheme,
            "cfl": wl.cfl, "dt": dt, "parallelism": "single GPU"}
     if nb == 1:
         cfg["grid"] = [blk.ni, blk.nj, blk.nk]
@@ -321,7 +328,7 @@ def main():
         "step_alg_GBps": round(stage_bytes * 3 * args.steps / el / 1e9, 1),
     }
     if not args.no_cpu and nb == 1:
-        out["cpu_baseline"] = cpu_baseline(wl, wname)
+        out["cpu_baseline"] = cpu_baseline(wl, wname, scheme)
     if bt is not None:
         B.cfd_batch_destroy(bt)
     B.cfd_exchange_destroy(x)

@@ -45,6 +45,10 @@ extern "C" {
 /* ---- enumerations ------------------------------------------------------------------ */
 enum { CFD_FP64 = 0, CFD_MIXED = 1 };                  /* arithmetic of the RHS        */
 enum { CFD_WENO_JS = 0, CFD_WENO_LINEAR = 1 };         /* Eq 15 weights or ideal ones  */
+/* inviscid scheme (Sec. 4.5.1): characteristic space at the nodes, one WENO stencil giving
+ * the values on both sides of the node (modified AFWENO, Figs 10-11), or at the half
+ * points, two WENO interpolations per half point (original AFWENO, Fig 9)              */
+enum { CFD_AFWENO_MODIFIED = 0, CFD_AFWENO_ORIGINAL = 1 };
 enum { CFD_BC_PERIODIC = 0, CFD_BC_INTERFACE = 1, CFD_BC_WALL = 2, CFD_BC_FARFIELD = 3 };
 enum { CFD_FIELDS_Q = 0, CFD_FIELDS_VISC = 1 };        /* field sets of an exchange    */
 
@@ -66,6 +70,9 @@ typedef struct cfd_params {
   double weno_eps;  /* epsilon of Eq 15 (paper: 1e-6)                                   */
   int32_t viscous;  /* 1: Navier-Stokes, 0: Euler                                       */
   int32_t weights;  /* CFD_WENO_JS or CFD_WENO_LINEAR                                   */
+  int32_t scheme;   /* CFD_AFWENO_MODIFIED (default) or CFD_AFWENO_ORIGINAL; the batched
+                       form (cfd_batch_*) runs the modified scheme only                 */
+  int32_t reserved; /* must be 0                                                         */
   double t_wall;    /* isothermal wall temperature (CFD_BC_WALL faces)                  */
   double qinf[5];   /* conserved far-field state (CFD_BC_FARFIELD faces)                */
 } cfd_params;

@@ -163,12 +163,14 @@ Phys make_phys(const cfd_params& p) {
   ph.suth = p.suth;
   ph.eps = p.weno_eps;
   ph.linear = p.weights == CFD_WENO_LINEAR;
+  ph.scheme = p.scheme;
   return ph;
 }
 
 bool same_params(const cfd_params& a, const cfd_params& b) {
   bool same = a.gamma == b.gamma && a.mach == b.mach && a.reynolds == b.reynolds && a.prandtl == b.prandtl &&
               a.suth == b.suth && a.weno_eps == b.weno_eps && a.viscous == b.viscous && a.weights == b.weights &&
+              a.scheme == b.scheme &&
               a.t_wall == b.t_wall;
   for (int v = 0; v < 5; ++v) same = same && a.qinf[v] == b.qinf[v];
   return same;
@@ -279,6 +281,8 @@ int validate_desc(const cfd_block_desc* d) {
   if (!(p.gamma > 1.0) || !(p.reynolds > 0.0) || !(p.prandtl > 0.0) || !(p.weno_eps > 0.0) || !(p.suth > 0.0))
     return fail(CFD_ERR_ARG, "gamma > 1, Re, Pr, Sutherland constant and WENO epsilon > 0 required");
   if (p.weights != CFD_WENO_JS && p.weights != CFD_WENO_LINEAR) return fail(CFD_ERR_ARG, "unknown WENO weights");
+  if (p.scheme != CFD_AFWENO_MODIFIED && p.scheme != CFD_AFWENO_ORIGINAL) return fail(CFD_ERR_ARG, "unknown AFWENO scheme");
+  if (p.reserved != 0) return fail(CFD_ERR_ARG, "cfd_params.reserved must be 0");
   for (int f = 0; f < 6; ++f)
     if (d->bc[f] < CFD_BC_PERIODIC || d->bc[f] > CFD_BC_FARFIELD) return fail(CFD_ERR_ARG, "unknown face kind");
   for (int ax = 0; ax < 3; ++ax)
@@ -780,6 +784,8 @@ int batch_create(cfd_block* const* blocks, int nb, cfd_exchange* x, void* hip_st
     if (!same_params(blocks[b]->d.params, blocks[0]->d.params))
       return fail(CFD_ERR_ARG, "blocks of a batch share one set of physical parameters");
   }
+  if (blocks[0]->d.params.scheme != CFD_AFWENO_MODIFIED)
+    return fail(CFD_ERR_UNSUPPORTED, "the batched form runs the modified AFWENO scheme only");
   cfd_batch* bt = new cfd_batch();
   bt->blocks.assign(blocks, blocks + nb);
   bt->x = x;

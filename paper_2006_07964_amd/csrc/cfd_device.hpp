@@ -69,6 +69,7 @@ struct Phys {
   double suth;
   double eps;
   int linear;  // ideal WENO weights
+  int scheme;  // 0: modified AFWENO (characteristic space at nodes), 1: original (half points)
 };
 
 // The same constants in the compute type.
@@ -303,6 +304,28 @@ __device__ __forceinline__ void weno_pair(R a, R b, R c, R d, R e, R eps, bool l
     vl = nl * rcp(dl);
     vr = nr * rcp(dr);
   }
+}
+
+// ---- one WENO value: the left-biased value at i+1/2 from the values at i-2..i+2 -------
+// (the right-biased value at i-1/2 is this function of the mirrored stencil e..a).
+// Same sub-stencils, ideal weights and indicators as weno_pair, one side only; the
+// original AFWENO takes the two sides of a half point from two different stencils.
+template <typename R>
+__device__ __forceinline__ R weno_left(R a, R b, R c, R d, R e, R eps, bool linear) {
+  const R p0 = R(3.0 / 128.0) * a - R(5.0 / 64.0) * b + R(15.0 / 128.0) * c;
+  const R p1 = R(-5.0 / 64.0) * b + R(15.0 / 32.0) * c + R(15.0 / 64.0) * d;
+  const R p2 = R(15.0 / 128.0) * c + R(15.0 / 64.0) * d - R(5.0 / 128.0) * e;
+  if (linear) return p0 + p1 + p2;
+  const R d0 = a - R(2) * b + c, e0 = a - R(4) * b + R(3) * c;
+  const R d1 = b - R(2) * c + d, e1 = b - d;
+  const R d2 = c - R(2) * d + e, e2 = R(3) * c - R(4) * d + e;
+  const R k13 = R(13.0 / 12.0), k14 = R(0.25);
+  const R t0 = eps + (k13 * d0 * d0 + k14 * e0 * e0);
+  const R t1 = eps + (k13 * d1 * d1 + k14 * e1 * e1);
+  const R t2 = eps + (k13 * d2 * d2 + k14 * e2 * e2);
+  const R s0 = t0 * t0, s1 = t1 * t1, s2 = t2 * t2;
+  const R q0 = s1 * s2, q1 = s0 * s2, q2 = s0 * s1;
+  return (q0 * p0 + q1 * p1 + q2 * p2) * rcp(R(0.0625) * q0 + R(0.625) * q1 + R(0.3125) * q2);
 }
 
 // ---- sixth-order half-point interpolation of node metrics ---------------------------

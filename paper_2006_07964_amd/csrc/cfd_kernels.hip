@@ -369,9 +369,13 @@ struct SweepLds {
   static constexpr int NW = TS + 2;  // nodes with a WENO evaluation
 };
 
+// Inviscid scheme of a sweep (Sec. 4.5.1): characteristic space at the nodes (modified
+// AFWENO, Figs 10-11) or at the half points (original AFWENO, Fig 9).
+constexpr int kModified = 0, kOriginal = 1;
+
 // One tile of a direction sweep: t is the logical tile index inside the block (sweep-
 // direction tile fastest, then the cross tile c1, then the cross index c2).
-template <int DIR, typename R, int TW, int TS, int NT>
+template <int DIR, typename R, int TW, int TS, int NT, int SCHEME = kModified>
 __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBlock& b, int t, R* sF, StageT<R, DIR>* sFn,
                                            double* sM, R* sV) {
   constexpr int NH = SweepLds<TW, TS>::NH;
@@ -481,54 +485,103 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
       }
     }
     __syncthreads();
-    // ---- characteristic WENO pair and split fluxes (one node per thread); node n = d0-1+s
-    // sits at staged index s+2.  F+ at n+1/2 goes to LDS now; F- at n-1/2 is added to the
-    // same interface after the barrier, so sF holds f(n+1/2) = F+(n) + F-(n+1). ----------
-    static_assert(TW * NW <= NT, "one WENO node per thread");
     R Fkeep[5];
-    const int ew = threadIdx.x;
-    const int sw_ = DIR == 0 ? ew % NW : ew / TW;
-    const int ww = DIR == 0 ? ew / NW : ew % TW;
-    const bool wvalid = ew < TW * NW && sw_ < nw && c1_0 + ww < n1 && d0 - 1 + sw_ <= nd;
-    const bool need_p = wvalid && sw_ <= ts && d0 - 1 + sw_ <= nd - 1;  // F+ at n+1/2
-    const bool need_m = wvalid && sw_ >= 1;                             // F- at n-1/2
-    if (need_p || need_m) {
-      const int s = sw_, w = ww;
-      const int sc = s + 2;
-      R q0[5];
+    bool need_m = false;
+    int ww = 0, sw_ = 0;
+    if constexpr (SCHEME == kModified) {
+      // ---- characteristic WENO pair and split fluxes (one node per thread); node n = d0-1+s
+      // sits at staged index s+2.  F+ at n+1/2 goes to LDS now; F- at n-1/2 is added to the
+      // same interface after the barrier, so sF holds f(n+1/2) = F+(n) + F-(n+1). ----------
+      static_assert(TW * NW <= NT, "one WENO node per thread");
+      const int ew = threadIdx.x;
+      sw_ = DIR == 0 ? ew % NW : ew / TW;
+      ww = DIR == 0 ? ew / NW : ew % TW;
+      const bool wvalid = ew < TW * NW && sw_ < nw && c1_0 + ww < n1 && d0 - 1 + sw_ <= nd;
+      const bool need_p = wvalid && sw_ <= ts && d0 - 1 + sw_ <= nd - 1;  // F+ at n+1/2
+      need_m = wvalid && sw_ >= 1;                                        // F- at n-1/2
+      if (need_p || need_m) {
+        const int s = sw_, w = ww;
+        const int sc = s + 2;
+        R q0[5];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) q0[v] = R(sFn[L::f(v, w, sc, NN)]);
-      const Basis<R> B =
-          make_basis(q0, R(sM[L::f(0, w, sc, NN)]), R(sM[L::f(1, w, sc, NN)]), R(sM[L::f(2, w, sc, NN)]), G);
-      R V[5][5];  // V[t][field] at node n + t - 2
+        for (int v = 0; v < 5; ++v) q0[v] = R(sFn[L::f(v, w, sc, NN)]);
+        const Basis<R> B =
+            make_basis(q0, R(sM[L::f(0, w, sc, NN)]), R(sM[L::f(1, w, sc, NN)]), R(sM[L::f(2, w, sc, NN)]), G);
+        R V[5][5];  // V[t][field] at node n + t - 2
 #pragma unroll
-      for (int tt = 0; tt < 5; ++tt) {
-        R qq[5];
+        for (int tt = 0; tt < 5; ++tt) {
+          R qq[5];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) qq[v] = R(sFn[L::f(v, w, s + tt, NN)]);
-        project(B, G, qq, V[tt]);
+          for (int v = 0; v < 5; ++v) qq[v] = R(sFn[L::f(v, w, s + tt, NN)]);
+          project(B, G, qq, V[tt]);
+        }
+        R vl[5], vr[5];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) weno_pair(V[0][f], V[1][f], V[2][f], V[3][f], V[4][f], eps, linear, vl[f], vr[f]);
+        if (need_p) {
+          R ul[5], F[5];
+          unproject(B, G, vl, ul);
+          const R hx = R(half_metric([&](int m) { return sM[L::f(0, w, sc + m, NN)]; }));
+          const R hy = R(half_metric([&](int m) { return sM[L::f(1, w, sc + m, NN)]; }));
+          const R hz = R(half_metric([&](int m) { return sM[L::f(2, w, sc + m, NN)]; }));
+          sw_flux<+1>(ul, hx, hy, hz, G, F);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) sF[L::f(v, w, s, NH)] = F[v];
+        }
+        if (need_m) {
+          R ur[5];
+          unproject(B, G, vr, ur);
+          // half point n-1/2 = (n-1)+1/2, centred on staged index sc-1
+          const R hx = R(half_metric([&](int m) { return sM[L::f(0, w, sc - 1 + m, NN)]; }));
+          const R hy = R(half_metric([&](int m) { return sM[L::f(1, w, sc - 1 + m, NN)]; }));
+          const R hz = R(half_metric([&](int m) { return sM[L::f(2, w, sc - 1 + m, NN)]; }));
+          sw_flux<-1>(ur, hx, hy, hz, G, Fkeep);
+        }
       }
-      R vl[5], vr[5];
+    } else {
+      // ---- original AFWENO: one half point per thread.  Slot s holds n+1/2 with
+      // n = d0-1+s (staged index s+2), whose stencil is staged s .. s+5.  The
+      // characteristic space sits at the half point: the mean state of n and n+1 and the
+      // direction of the half-point metric; the value left of n+1/2 comes from nodes
+      // n-2..n+2, the value right of it from n-1..n+3, and f(n+1/2) = F+ + F- directly.
+      static_assert(TW * NH <= NT, "one half point per thread");
+      const int eh = threadIdx.x;
+      const int s = DIR == 0 ? eh % NH : eh / TW;
+      const int w = DIR == 0 ? eh / NH : eh % TW;
+      if (eh < TW * NH && s <= ts && c1_0 + w < n1 && d0 - 1 + s <= nd - 1) {
+        const int sc = s + 2;
+        // half-point metric, formed again where it is used rather than held in registers
+        auto hm = [&](int c) { return R(half_metric([&](int m) { return sM[L::f(c, w, sc + m, NN)]; })); };
+        R qa[5];
 #pragma unroll
-      for (int f = 0; f < 5; ++f) weno_pair(V[0][f], V[1][f], V[2][f], V[3][f], V[4][f], eps, linear, vl[f], vr[f]);
-      if (need_p) {
-        R ul[5], F[5];
-        unproject(B, G, vl, ul);
-        const R hx = R(half_metric([&](int m) { return sM[L::f(0, w, sc + m, NN)]; }));
-        const R hy = R(half_metric([&](int m) { return sM[L::f(1, w, sc + m, NN)]; }));
-        const R hz = R(half_metric([&](int m) { return sM[L::f(2, w, sc + m, NN)]; }));
-        sw_flux<+1>(ul, hx, hy, hz, G, F);
+        for (int v = 0; v < 5; ++v) qa[v] = R(0.5) * (R(sFn[L::f(v, w, sc, NN)]) + R(sFn[L::f(v, w, sc + 1, NN)]));
+        const Basis<R> B = make_basis(qa, hm(0), hm(1), hm(2), G);
+        // V[t][field] at node n + t - 2; node n+3 replaces node n-2 once the left value is
+        // formed, which keeps five stencil points live instead of six
+        R V[5][5];
+        auto proj = [&](int tt, R out[5]) {
+          R qq[5];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) qq[v] = R(sFn[L::f(v, w, s + tt, NN)]);
+          project(B, G, qq, out);
+        };
+#pragma unroll
+        for (int tt = 0; tt < 5; ++tt) proj(tt, V[tt]);
+        R vl[5], vr[5], uh[5], F[5];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) vl[f] = weno_left(V[0][f], V[1][f], V[2][f], V[3][f], V[4][f], eps, linear);
+        proj(5, V[0]);
+#pragma unroll
+        for (int f = 0; f < 5; ++f) vr[f] = weno_left(V[0][f], V[4][f], V[3][f], V[2][f], V[1][f], eps, linear);
+        // this thread alone writes slot s: F+ goes to LDS, F- is added to it
+        unproject(B, G, vl, uh);
+        sw_flux<+1>(uh, hm(0), hm(1), hm(2), G, F);
 #pragma unroll
         for (int v = 0; v < 5; ++v) sF[L::f(v, w, s, NH)] = F[v];
-      }
-      if (need_m) {
-        R ur[5];
-        unproject(B, G, vr, ur);
-        // half point n-1/2 = (n-1)+1/2, centred on staged index sc-1
-        const R hx = R(half_metric([&](int m) { return sM[L::f(0, w, sc - 1 + m, NN)]; }));
-        const R hy = R(half_metric([&](int m) { return sM[L::f(1, w, sc - 1 + m, NN)]; }));
-        const R hz = R(half_metric([&](int m) { return sM[L::f(2, w, sc - 1 + m, NN)]; }));
-        sw_flux<-1>(ur, hx, hy, hz, G, Fkeep);
+        unproject(B, G, vr, uh);
+        sw_flux<-1>(uh, hm(0), hm(1), hm(2), G, F);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sF[L::f(v, w, s, NH)] += F[v];
       }
     }
     // a staged Q in FP64 is exact: the output node's copy for the RK combination is read
@@ -619,10 +672,10 @@ struct SweepShared {
 };
 
 // Single block: one workgroup per tile, ids remapped XCD-contiguously.
-template <int DIR, typename R, int TW, int TS, int NT>
+template <int DIR, typename R, int TW, int TS, int NT, int SCHEME>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep(SweepArgs a) {
   __shared__ SweepShared<R, StageT<R, DIR>, TW, TS> sh;
-  sweep_tile<DIR, R, TW, TS, NT>(a.c, a.b, xcd_remap(blockIdx.x, gridDim.x), sh.F, sh.Fn, sh.M, sh.V);
+  sweep_tile<DIR, R, TW, TS, NT, SCHEME>(a.c, a.b, xcd_remap(blockIdx.x, gridDim.x), sh.F, sh.Fn, sh.M, sh.V);
 }
 
 // Batched blocks: one launch walks a work list covering the tiles of every block
@@ -708,17 +761,23 @@ int sweep_threads(int cfg) {
   return nt[cfg];
 }
 
-template <typename R, int CFG>
-hipError_t launch_sweep_cfg(int dir, const SweepArgs& a, int64_t nwg, hipStream_t s) {
+template <typename R, int CFG, int SCHEME>
+hipError_t launch_sweep_scheme(int dir, const SweepArgs& a, int64_t nwg, hipStream_t s) {
   using C = TileCfg<CFG>;
   dim3 grid((unsigned)nwg);
   if (dir == 0)
-    hipLaunchKernelGGL((k_sweep<0, R, C::TW, C::TS, C::NT>), grid, dim3(C::NT), 0, s, a);
+    hipLaunchKernelGGL((k_sweep<0, R, C::TW, C::TS, C::NT, SCHEME>), grid, dim3(C::NT), 0, s, a);
   else if (dir == 1)
-    hipLaunchKernelGGL((k_sweep<1, R, C::TW, C::TS, C::NT>), grid, dim3(C::NT), 0, s, a);
+    hipLaunchKernelGGL((k_sweep<1, R, C::TW, C::TS, C::NT, SCHEME>), grid, dim3(C::NT), 0, s, a);
   else
-    hipLaunchKernelGGL((k_sweep<2, R, C::TW, C::TS, C::NT>), grid, dim3(C::NT), 0, s, a);
+    hipLaunchKernelGGL((k_sweep<2, R, C::TW, C::TS, C::NT, SCHEME>), grid, dim3(C::NT), 0, s, a);
   return hipGetLastError();
+}
+
+template <typename R, int CFG>
+hipError_t launch_sweep_cfg(int dir, const SweepArgs& a, int64_t nwg, hipStream_t s) {
+  return a.c.ph.scheme == kOriginal ? launch_sweep_scheme<R, CFG, kOriginal>(dir, a, nwg, s)
+                                    : launch_sweep_scheme<R, CFG, kModified>(dir, a, nwg, s);
 }
 
 template <typename R>
