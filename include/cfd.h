@@ -178,6 +178,30 @@ int cfd_halo_exchange(cfd_exchange* x, int field_set, void* const* block_bufs, v
  * (the CFL-controlled global step of Sec. 4.5.3).  Q[b] device.  Synchronises.          */
 int cfd_dt_cfl(cfd_block* const* blocks, int nb, const double* const* Q, double cfl,
                double* dt_out);
+/* The same step written to device memory: *dt_dev (one double, device) receives the
+ * value, or NaN when the spectral radius is not positive and finite.  Stream-ordered on
+ * blocks[0]'s stream, after the work already enqueued on every block's stream (event
+ * waits, no host synchronisation; no memset), so a time loop can recompute the step
+ * every iteration and hand dt_dev to cfd_rk_stage_dev or cfd_batch_step (the reduced-
+ * dimensional CFL minimum of Sec. 4.5.3 done on the device).  Uses blocks[0]'s reduction
+ * scratch: calls that share blocks[0] must not overlap on different streams.
+ * Errors: CFD_ERR_ARG, CFD_ERR_STATE (no metrics), CFD_ERR_HIP.                        */
+int cfd_dt_cfl_dev(cfd_block* const* blocks, int nb, const double* const* Q, double cfl,
+                   double* dt_dev);
+/* Residual norms (the residual evaluation that closes each iteration of Fig 2, a
+ * reduced-dimensional reduction of Sec. 4.5.3): with d = scale * (A[b] - B[b]) over the
+ * interior points of all nb blocks (B or B[b] NULL: d = scale * A[b]),
+ *   out[f]     = sqrt(sum d_f^2 / N)  (root mean square, N = all interior points),
+ *   out[5 + f] = max |d_f|,           f = rho, rho u, rho v, rho w, e.
+ * A[b], B[b]: device states in block b's layout; out: 10 host doubles.  E.g. the RHS
+ * residual is A = R, B = NULL, scale = 1; the step residual (Q^{n+1} - Q^n)/dt is
+ * A = Q^{n+1}, B = Q^n, scale = 1/dt.  Sums run in a fixed order (bitwise reproducible).
+ * Runs on blocks[0]'s stream after every block's enqueued work; synchronises.  The first
+ * call allocates blocks[0]'s residual scratch (about 1.3 MB).  Errors: CFD_ERR_ARG
+ * (nb outside 1..64, null arrays, non-finite scale), CFD_ERR_ALLOC, CFD_ERR_HIP,
+ * CFD_ERR_NONFINITE (a norm is not finite).                                             */
+int cfd_residual(cfd_block* const* blocks, int nb, const double* const* A, const double* const* B,
+                 double scale, double* out);
 /* *ok = 1 if every interior value of Q is finite, else 0 (and CFD_ERR_NONFINITE).
  * Synchronises.                                                                        */
 int cfd_check_finite(cfd_block* b, const double* Q, int* ok);

@@ -183,6 +183,25 @@ def dt_cfl(c: Cfg, met, q, cfl) -> float:
     return float(lib().oracle_dt_cfl(C.byref(c), _p(met), _p(np.ascontiguousarray(q)), cfl))
 
 
+def residual(a_arrays, b_arrays=None, scale: float = 1.0):
+    """Residual norms of the iteration loop (Fig 2's residual evaluation; Sec. 4.5.3 forms
+    them by reductions over the grid).  Reading: per conserved quantity, the root mean
+    square and the maximum of |d| with d = scale * (A - B) over the interior points of all
+    blocks (B absent: d = scale * A).  Plain numpy in FP64: returns (rms[5], max[5])."""
+    sq = np.zeros(5)
+    mx = np.zeros(5)
+    n = 0
+    for bi, a in enumerate(a_arrays):
+        d = np.asarray(a, dtype=np.float64)[:, 3:-3, 3:-3, 3:-3]
+        if b_arrays is not None and b_arrays[bi] is not None:
+            d = d - np.asarray(b_arrays[bi], dtype=np.float64)[:, 3:-3, 3:-3, 3:-3]
+        d = scale * d
+        sq += np.sum(d * d, axis=(1, 2, 3))
+        mx = np.maximum(mx, np.max(np.abs(d), axis=(1, 2, 3)))
+        n += d[0].size
+    return list(np.sqrt(sq / n)), list(mx)
+
+
 def weno5(v: Sequence[float], eps: float = 1e-6, linear: bool = False):
     vv = np.ascontiguousarray(v, dtype=np.float64)
     out = np.zeros(2)

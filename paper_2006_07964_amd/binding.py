@@ -83,6 +83,8 @@ def lib():
         "cfd_exchange_destroy": ([_VP], C.c_int),
         "cfd_halo_exchange": ([_VP, C.c_int, C.POINTER(_VP), _VP], C.c_int),
         "cfd_dt_cfl": ([C.POINTER(_VP), C.c_int, C.POINTER(_VP), C.c_double, _DP], C.c_int),
+        "cfd_dt_cfl_dev": ([C.POINTER(_VP), C.c_int, C.POINTER(_VP), C.c_double, _VP], C.c_int),
+        "cfd_residual": ([C.POINTER(_VP), C.c_int, C.POINTER(_VP), C.POINTER(_VP), C.c_double, _DP], C.c_int),
         "cfd_check_finite": ([_VP, _VP, C.POINTER(C.c_int)], C.c_int),
         "cfd_sync": ([_VP], C.c_int),
         "cfd_batch_create": ([C.POINTER(_VP), C.c_int, _VP, _VP, C.POINTER(_VP)], C.c_int),
@@ -219,6 +221,19 @@ def cfd_dt_cfl(blocks: Sequence[int], qs: Sequence, cfl: float) -> float:
     out = C.c_double()
     _check(lib().cfd_dt_cfl(arr, len(blocks), _vp_array(qs), cfl, C.byref(out)))
     return out.value
+
+
+def cfd_dt_cfl_dev(blocks: Sequence[int], qs: Sequence, cfl: float, dt_dev) -> None:
+    arr = (_VP * len(blocks))(*blocks)
+    _check(lib().cfd_dt_cfl_dev(arr, len(blocks), _vp_array(qs), cfl, _ptr(dt_dev)))
+
+
+def cfd_residual(blocks: Sequence[int], a: Sequence, b: Optional[Sequence] = None, scale: float = 1.0):
+    """(rms[5], max[5]) of scale * (a - b) over the interior points of all blocks."""
+    arr = (_VP * len(blocks))(*blocks)
+    out = (C.c_double * 10)()
+    _check(lib().cfd_residual(arr, len(blocks), _vp_array(a), None if b is None else _vp_array(b), scale, out))
+    return list(out[:5]), list(out[5:])
 
 
 def cfd_check_finite(b: int, q) -> bool:

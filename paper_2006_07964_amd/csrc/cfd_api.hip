@@ -147,6 +147,8 @@ struct cfd_block {
   // small device scratch for reductions
   unsigned long long* red_dev = nullptr;
   int* flag_dev = nullptr;
+  double* res_dev = nullptr;  // residual partial rows of up to kMaxBlocks blocks (allocated on first use)
+  hipEvent_t ev = nullptr;    // orders this block's stream before another block's
   Profiler prof;
 };
 
@@ -448,6 +450,7 @@ int cfd_block_create(const cfd_block_desc* d, void* hip_stream, cfd_block** out)
   if (hipMalloc((void**)&b->red_dev, sizeof(unsigned long long)) != hipSuccess ||
       hipMalloc((void**)&b->flag_dev, sizeof(int)) != hipSuccess)
     return cleanup(CFD_ERR_ALLOC, "reduction scratch");
+  if (hipEventCreateWithFlags(&b->ev, hipEventDisableTiming) != hipSuccess) return cleanup(CFD_ERR_HIP, "block event");
   b->bytes = (int64_t)plane * (10 * 8 + (b->esize == sizeof(double) ? 17 : 27) * (int64_t)b->esize);
   // block-local viscous halo work
   std::vector<CopySeg> cs;
@@ -482,6 +485,8 @@ int cfd_block_destroy(cfd_block* b) {
   (void)hipFree(b->rt_raw);
   (void)hipFree(b->red_dev);
   (void)hipFree(b->flag_dev);
+  (void)hipFree(b->res_dev);
+  if (b->ev) (void)hipEventDestroy(b->ev);
   (void)hipFree(b->local_copy_dev);
   (void)hipFree(b->local_bc_dev);
   delete b;
@@ -641,6 +646,68 @@ int cfd_dt_cfl(cfd_block* const* blocks, int nb, const double* const* Q, double 
   std::memcpy(&smax, &bits, sizeof smax);
   if (!(smax > 0.0) || !std::isfinite(smax)) return fail(CFD_ERR_NONFINITE, "spectral radius is not positive and finite");
   *dt_out = cfl / smax;
+  return CFD_OK;
+}
+
+// Work of every block up to now, ordered before later work on blocks[0]'s stream.
+static int order_on_first(cfd_block* const* blocks, int nb) {
+  cfd_block* b0 = blocks[0];
+  for (int n = 1; n < nb; ++n) {
+    if (blocks[n]->stream == b0->stream) continue;
+    HIP_TRY(hipEventRecord(blocks[n]->ev, blocks[n]->stream), "event record");
+    HIP_TRY(hipStreamWaitEvent(b0->stream, blocks[n]->ev, 0), "stream wait");
+  }
+  return CFD_OK;
+}
+
+int cfd_dt_cfl_dev(cfd_block* const* blocks, int nb, const double* const* Q, double cfl, double* dt_dev) {
+  if (!blocks || nb <= 0 || !Q || !dt_dev) return fail(CFD_ERR_ARG, "null argument");
+  if (!(cfl > 0.0)) return fail(CFD_ERR_ARG, "cfl must be positive");
+  for (int n = 0; n < nb; ++n) {
+    if (!blocks[n] || !Q[n]) return fail(CFD_ERR_ARG, "null block or state");
+    if (!blocks[n]->have_metrics) return fail(CFD_ERR_STATE, "cfd_metrics has not been run on a block");
+  }
+  cfd_block* b0 = blocks[0];
+  int rc = order_on_first(blocks, nb);
+  if (rc != CFD_OK) return rc;
+  HIP_TRY(launch_dt_reset(b0->red_dev, b0->stream), "dt reset launch");
+  for (int n = 0; n < nb; ++n) {
+    cfd_block* b = blocks[n];
+    HIP_TRY(launch_dt_max(b->g, Q[n], b->met, b->d.params.gamma, b0->red_dev, b0->stream), "dt launch");
+  }
+  HIP_TRY(launch_dt_finish(b0->red_dev, cfl, dt_dev, b0->stream), "dt finish launch");
+  return CFD_OK;
+}
+
+int cfd_residual(cfd_block* const* blocks, int nb, const double* const* A, const double* const* Bm, double scale,
+                 double* out) {
+  if (!blocks || nb <= 0 || nb > kMaxBlocks || !A || !out) return fail(CFD_ERR_ARG, "need 1..64 blocks, A and out");
+  int64_t npts = 0;
+  for (int n = 0; n < nb; ++n) {
+    if (!blocks[n] || !A[n]) return fail(CFD_ERR_ARG, "null block or array");
+    npts += (int64_t)blocks[n]->g.ni * blocks[n]->g.nj * blocks[n]->g.nk;
+  }
+  if (!std::isfinite(scale)) return fail(CFD_ERR_ARG, "scale must be finite");
+  cfd_block* b0 = blocks[0];
+  if (!b0->res_dev) {
+    HIP_TRY(hipStreamSynchronize(b0->stream), "stream synchronize");
+    if (hipMalloc((void**)&b0->res_dev, ((size_t)kMaxBlocks * kResGroups * 10 + 10) * sizeof(double)) != hipSuccess) {
+      b0->res_dev = nullptr;
+      return fail(CFD_ERR_ALLOC, "residual scratch");
+    }
+  }
+  int rc = order_on_first(blocks, nb);
+  if (rc != CFD_OK) return rc;
+  for (int n = 0; n < nb; ++n)
+    HIP_TRY(launch_res_partial(blocks[n]->g, A[n], Bm ? Bm[n] : nullptr, scale, b0->res_dev + (int64_t)n * kResGroups * 10,
+                               b0->stream),
+            "residual launch");
+  double* res_out = b0->res_dev + (int64_t)kMaxBlocks * kResGroups * 10;
+  HIP_TRY(launch_res_final(b0->res_dev, nb * kResGroups, 1.0 / (double)npts, res_out, b0->stream), "residual launch");
+  HIP_TRY(hipMemcpyAsync(out, res_out, 10 * sizeof(double), hipMemcpyDeviceToHost, b0->stream), "copy residual");
+  HIP_TRY(hipStreamSynchronize(b0->stream), "stream synchronize");
+  for (int v = 0; v < 10; ++v)
+    if (!std::isfinite(out[v])) return fail(CFD_ERR_NONFINITE, "non-finite residual");
   return CFD_OK;
 }
 

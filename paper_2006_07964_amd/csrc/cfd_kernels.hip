@@ -1046,4 +1046,105 @@ hipError_t launch_finite(const Geom& g, const double* q, int* flag, hipStream_t 
   return hipGetLastError();
 }
 
+// ---- CFL time step into device memory (no host round trip) -------------------------
+__global__ void k_dt_reset(unsigned long long* acc) { *acc = 0ull; }
+
+__global__ void k_dt_finish(const unsigned long long* acc, double cfl, double* dt) {
+  const double smax = __longlong_as_double((long long)*acc);
+  *dt = (smax > 0.0 && smax <= 1.7976931348623157e308) ? cfl / smax : __builtin_nan("");
+}
+
+hipError_t launch_dt_reset(unsigned long long* acc, hipStream_t s) {
+  hipLaunchKernelGGL(k_dt_reset, dim3(1), dim3(1), 0, s, acc);
+  return hipGetLastError();
+}
+hipError_t launch_dt_finish(const unsigned long long* acc, double cfl, double* dt, hipStream_t s) {
+  hipLaunchKernelGGL(k_dt_finish, dim3(1), dim3(1), 0, s, acc, cfl, dt);
+  return hipGetLastError();
+}
+
+// ---- residual norms: reduced-dimensional reductions (Sec. 4.5) ------------------------
+// 3D -> lines: each wave walks grid lines (j, k) of the block, its lanes striding along i
+// (coalesced), and keeps per lane the sums of squares and the maxima of the five fields of
+// scale * (a - b) (b may be null); lines -> workgroup: a fixed-order tree in LDS; the
+// kResGroups partial rows of every block are then reduced by one workgroup, again in a
+// fixed order, so the result does not depend on timing.
+__global__ __launch_bounds__(256) void k_res_partial(Geom g, const double* __restrict__ a, const double* __restrict__ b,
+                                                     double scale, double* __restrict__ part) {
+  __shared__ double red[10][256];
+  double sq[5] = {0, 0, 0, 0, 0}, mx[5] = {0, 0, 0, 0, 0};
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lines = g.nj * g.nk;
+  for (int l = blockIdx.x * 4 + wave; l < lines; l += gridDim.x * 4) {
+    const int j = l % g.nj, k = l / g.nj;
+    for (int i = lane; i < g.ni; i += 64) {
+      const int64_t p = at(g, i, j, k);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        const double d = scale * (b ? a[v * g.plane + p] - b[v * g.plane + p] : a[v * g.plane + p]);
+        sq[v] += d * d;
+        mx[v] = fmax(mx[v], fabs(d));
+      }
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    red[v][threadIdx.x] = sq[v];
+    red[5 + v][threadIdx.x] = mx[v];
+  }
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        red[v][threadIdx.x] += red[v][threadIdx.x + h];
+        red[5 + v][threadIdx.x] = fmax(red[5 + v][threadIdx.x], red[5 + v][threadIdx.x + h]);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 10) part[(int64_t)blockIdx.x * 10 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(256) void k_res_final(const double* __restrict__ part, int nparts, double inv_n,
+                                                   double* __restrict__ out) {
+  __shared__ double red[10][256];
+  double sq[5] = {0, 0, 0, 0, 0}, mx[5] = {0, 0, 0, 0, 0};
+  for (int r = threadIdx.x; r < nparts; r += 256) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      sq[v] += part[(int64_t)r * 10 + v];
+      mx[v] = fmax(mx[v], part[(int64_t)r * 10 + 5 + v]);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    red[v][threadIdx.x] = sq[v];
+    red[5 + v][threadIdx.x] = mx[v];
+  }
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        red[v][threadIdx.x] += red[v][threadIdx.x + h];
+        red[5 + v][threadIdx.x] = fmax(red[5 + v][threadIdx.x], red[5 + v][threadIdx.x + h]);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 5) out[threadIdx.x] = sqrt(red[threadIdx.x][0] * inv_n);
+  else if (threadIdx.x < 10) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+hipError_t launch_res_partial(const Geom& g, const double* a, const double* b, double scale, double* part,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_res_partial, dim3(kResGroups), dim3(256), 0, s, g, a, b, scale, part);
+  return hipGetLastError();
+}
+hipError_t launch_res_final(const double* part, int nparts, double inv_n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_res_final, dim3(1), dim3(256), 0, s, part, nparts, inv_n, out);
+  return hipGetLastError();
+}
+
 }  // namespace cfd

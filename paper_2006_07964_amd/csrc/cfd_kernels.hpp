@@ -130,5 +130,13 @@ hipError_t launch_visc_ghost(const BcSeg* segs_dev, int nseg, int max_elems, con
 hipError_t launch_dt_max(const Geom& g, const double* q, const double* met, double gamma,
                          unsigned long long* acc, hipStream_t s);
 hipError_t launch_finite(const Geom& g, const double* q, int* flag, hipStream_t s);
+hipError_t launch_dt_reset(unsigned long long* acc, hipStream_t s);
+hipError_t launch_dt_finish(const unsigned long long* acc, double cfl, double* dt, hipStream_t s);
+// residual norms: kResGroups partial rows (10 doubles: 5 sums of squares, 5 maxima) per
+// block, then one reduction of nparts rows to (5 RMS values, 5 maxima)
+constexpr int kResGroups = 256;
+hipError_t launch_res_partial(const Geom& g, const double* a, const double* b, double scale, double* part,
+                              hipStream_t s);
+hipError_t launch_res_final(const double* part, int nparts, double inv_n, double* out, hipStream_t s);
 
 }  // namespace cfd

@@ -788,3 +788,33 @@ def test_original_afweno_rejects_unknown_scheme():
     met = np.zeros(O.state_shape(c, 10))
     with pytest.raises(ValueError):
         O.rhs(c, met, np.ones(O.state_shape(c)))
+
+
+# ---- residual norms (Fig 2's residual evaluation) -----------------------------------------
+def test_residual_norms_closed_forms():
+    """Constant fields give |c| in both norms; a sine over whole periods along i has mean
+    square 1/2; halo values do not enter; a split into two blocks gives the single-block
+    norms; scale and the difference A - B enter linearly."""
+    n = 12
+    shape = (5, 7 + 6, 9 + 6, n + 6)
+    a = np.full(shape, np.nan)  # halos must not be read
+    i = np.arange(n)
+    for v in range(5):
+        a[v, 3:-3, 3:-3, 3:-3] = (v - 2.0) if v != 1 else np.sin(2 * np.pi * i / n)[None, None, :]
+    rms, mx = O.residual([a])
+    assert rms[0] == pytest.approx(2.0, rel=1e-15) and mx[0] == pytest.approx(2.0, rel=1e-15)
+    assert rms[2] == 0.0 and mx[2] == 0.0
+    assert rms[1] == pytest.approx(np.sqrt(0.5), rel=1e-14)
+    assert mx[1] == pytest.approx(1.0, rel=1e-15)  # sin(pi/2) is a node at n = 12
+    b = np.zeros(shape)
+    b[:, 3:-3, 3:-3, 3:-3] = 0.5
+    rms2, mx2 = O.residual([a], [b], scale=4.0)
+    assert rms2[4] == pytest.approx(4.0 * 1.5, rel=1e-15) and mx2[0] == pytest.approx(4.0 * 2.5, rel=1e-15)
+    # split along i into two blocks of 5 and 7 points (each with its own halo)
+    left = np.full((5, 13, 15, 5 + 6), np.nan)
+    right = np.full((5, 13, 15, 7 + 6), np.nan)
+    left[:, 3:-3, 3:-3, 3:-3] = a[:, 3:-3, 3:-3, 3:8]
+    right[:, 3:-3, 3:-3, 3:-3] = a[:, 3:-3, 3:-3, 8:15]
+    rs, ms = O.residual([left, right])
+    np.testing.assert_allclose(rs, rms, rtol=1e-14)
+    np.testing.assert_array_equal(ms, mx)
