@@ -42,7 +42,8 @@ class Cfg(C.Structure):
 
 
 class Iface(C.Structure):
-    _fields_ = [("block_a", C.c_int), ("face_a", C.c_int), ("block_b", C.c_int), ("face_b", C.c_int)]
+    _fields_ = [("block_a", C.c_int), ("face_a", C.c_int), ("block_b", C.c_int), ("face_b", C.c_int),
+                ("orient", C.c_int)]
 
 
 _lib = None
@@ -248,6 +249,7 @@ def _ifaces(ifc):
     arr = (Iface * max(1, len(ifc)))()
     for n, f in enumerate(ifc):
         arr[n].block_a, arr[n].face_a, arr[n].block_b, arr[n].face_b = f.block_a, f.face_a, f.block_b, f.face_b
+        arr[n].orient = getattr(f, "orient", 0)
     return arr
 
 

@@ -834,37 +834,87 @@ double oracle_dt_cfl(const oracle_cfg* c, const double* met, const double* Q, do
 /* halo of a across f holds b's interior layers adjacent to g, with the tangential      */
 /* indices identical (identity orientation).                                            */
 /* ------------------------------------------------------------------------------------ */
+/* The axes of block B that the index directions of block A run along across the face
+ * pair (fa, fb) with tangential map `orient` (see oracle_iface), and their senses:
+ * dir[d] is B's axis for A's axis d, sgn[d] = +1 if both indices increase together.     */
+static void face_dirs(int fa, int fb, int orient, int* dir, int* sgn) {
+  int axa = fa / 2, axb = fb / 2, outa = (fa % 2) ? +1 : -1, outb = (fb % 2) ? +1 : -1;
+  int ta[2], tb[2], q;
+  ta[0] = axa == 0 ? 1 : 0; ta[1] = axa == 2 ? 1 : 2;
+  tb[0] = axb == 0 ? 1 : 0; tb[1] = axb == 2 ? 1 : 2;
+  /* across the face, A's normal index grows outward while B's grows inward from fb */
+  dir[axa] = axb;
+  sgn[axa] = -outa * outb;
+  for (q = 0; q < 2; ++q) {
+    dir[ta[q]] = (orient & 1) ? tb[1 - q] : tb[q];
+    sgn[ta[q]] = ((orient >> (1 + q)) & 1) ? -1 : +1;
+  }
+}
+
+/* Ghost layers beyond face fa of block A from the interior layers inside face fb of
+ * block B.  visc = 0: nvar planes copied as they are.  visc = 1: the 12 viscous-flux
+ * planes, 4 per index direction (Eqs 5-6 through that direction's hatted metric): A's
+ * direction d is B's direction dir[d], so A's planes of d take B's planes of dir[d],
+ * with the sign of sgn[d] (a reversed index reverses the hatted metric and the flux).   */
 static void copy_face(const oracle_cfg* ca, double* A, int fa, const oracle_cfg* cb, const double* B,
-                      int fb, int nvar) {
+                      int fb, int orient, int nvar, int visc) {
   const dims_t da = state_dims(ca), db = state_dims(cb);
-  int axis = fa / 2, outa = (fa % 2) ? +1 : -1, outb = (fb % 2) ? +1 : -1;
-  int wa = (fa % 2) ? npts(ca, axis) - 1 : 0;
-  int wb = (fb % 2) ? npts(cb, axis) - 1 : 0;
-  int na = npts(ca, (axis + 1) % 3), nb = npts(ca, (axis + 2) % 3);
-  int a, b, m, v;
-  for (b = 0; b < nb; ++b)
-    for (a = 0; a < na; ++a)
+  int axa = fa / 2, axb = fb / 2, outa = (fa % 2) ? +1 : -1, outb = (fb % 2) ? +1 : -1;
+  int wa = (fa % 2) ? npts(ca, axa) - 1 : 0;
+  int wb = (fb % 2) ? npts(cb, axb) - 1 : 0;
+  int ta0 = axa == 0 ? 1 : 0, ta1 = axa == 2 ? 1 : 2;
+  int dir[3], sgn[3];
+  int a, b, m, v, d;
+  face_dirs(fa, fb, orient, dir, sgn);
+  for (b = 0; b < npts(ca, ta1); ++b)
+    for (a = 0; a < npts(ca, ta0); ++a)
       for (m = 1; m <= HS; ++m) {
         int ia[3], ib[3];
-        ia[(axis + 1) % 3] = a; ia[(axis + 2) % 3] = b; ia[axis] = wa + outa * m;
+        long pa, pb;
+        ia[ta0] = a; ia[ta1] = b; ia[axa] = wa + outa * m;
         /* ghost m beyond face fa is interior layer m-1 inside face fb */
-        ib[(axis + 1) % 3] = a; ib[(axis + 2) % 3] = b; ib[axis] = wb - outb * (m - 1);
-        for (v = 0; v < nvar; ++v)
-          A[v * da.plane + sidx(&da, ia[0], ia[1], ia[2])] = B[v * db.plane + sidx(&db, ib[0], ib[1], ib[2])];
+        ib[axb] = wb - outb * (m - 1);
+        ib[dir[ta0]] = sgn[ta0] > 0 ? a : npts(cb, dir[ta0]) - 1 - a;
+        ib[dir[ta1]] = sgn[ta1] > 0 ? b : npts(cb, dir[ta1]) - 1 - b;
+        pa = sidx(&da, ia[0], ia[1], ia[2]);
+        pb = sidx(&db, ib[0], ib[1], ib[2]);
+        if (!visc) {
+          for (v = 0; v < nvar; ++v) A[v * da.plane + pa] = B[v * db.plane + pb];
+        } else {
+          for (d = 0; d < 3; ++d)
+            for (v = 0; v < 4; ++v) A[(4 * d + v) * da.plane + pa] = sgn[d] * B[(4 * dir[d] + v) * db.plane + pb];
+        }
       }
+}
+
+static int exchange(const oracle_cfg* cfgs, int nb, double* const* arrays, int nvar, int visc,
+                    const oracle_iface* ifc, int nifc) {
+  int n, d;
+  for (n = 0; n < nifc; ++n) {
+    const oracle_iface* f = &ifc[n];
+    int dir[3], sgn[3];
+    if (f->block_a < 0 || f->block_a >= nb || f->block_b < 0 || f->block_b >= nb) return -1;
+    if (f->face_a < 0 || f->face_a > 5 || f->face_b < 0 || f->face_b > 5 || f->orient < 0 || f->orient > 7) return -1;
+    face_dirs(f->face_a, f->face_b, f->orient, dir, sgn);
+    for (d = 0; d < 3; ++d)
+      if (d != f->face_a / 2 && npts(&cfgs[f->block_a], d) != npts(&cfgs[f->block_b], dir[d])) return -1;
+  }
+  for (n = 0; n < nifc; ++n) {
+    const oracle_iface* f = &ifc[n];
+    /* the same interface seen from b: swap stays, the reversals follow their axes */
+    int r1 = (f->orient >> 1) & 1, r2 = (f->orient >> 2) & 1;
+    int inv = (f->orient & 1) ? (1 | (r2 << 1) | (r1 << 2)) : f->orient;
+    copy_face(&cfgs[f->block_a], arrays[f->block_a], f->face_a, &cfgs[f->block_b], arrays[f->block_b], f->face_b,
+              f->orient, nvar, visc);
+    copy_face(&cfgs[f->block_b], arrays[f->block_b], f->face_b, &cfgs[f->block_a], arrays[f->block_a], f->face_a,
+              inv, nvar, visc);
+  }
+  return 0;
 }
 
 int oracle_exchange(const oracle_cfg* cfgs, int nb, double* const* arrays, int nvar,
                     const oracle_iface* ifc, int nifc) {
-  int n;
-  for (n = 0; n < nifc; ++n) {
-    const oracle_iface* f = &ifc[n];
-    if (f->block_a < 0 || f->block_a >= nb || f->block_b < 0 || f->block_b >= nb) return -1;
-    if (f->face_a / 2 != f->face_b / 2) return -1;
-    copy_face(&cfgs[f->block_a], arrays[f->block_a], f->face_a, &cfgs[f->block_b], arrays[f->block_b], f->face_b, nvar);
-    copy_face(&cfgs[f->block_b], arrays[f->block_b], f->face_b, &cfgs[f->block_a], arrays[f->block_a], f->face_a, nvar);
-  }
-  return 0;
+  return exchange(cfgs, nb, arrays, nvar, 0, ifc, nifc);
 }
 
 int oracle_rhs_multi(const oracle_cfg* cfgs, int nb, const double* const* met, const double* const* Q,
@@ -878,7 +928,7 @@ int oracle_rhs_multi(const oracle_cfg* cfgs, int nb, const double* const* met, c
       if (cfgs[b].viscous) V[b] = visc_planes(&cfgs[b], met[b], Q[b]);
       else V[b] = (double*)calloc((size_t)12 * state_dims(&cfgs[b]).plane, sizeof(double));
     /* viscous flux layers across interfaces (interior scheme at block interfaces) */
-    rc = oracle_exchange(cfgs, nb, V, 12, ifc, nifc);
+    rc = exchange(cfgs, nb, V, 12, 1, ifc, nifc);
   }
   if (!rc)
     for (b = 0; b < nb; ++b) rhs_core(&cfgs[b], met[b], Q[b], V[b], R[b], mask, 0, cfgs[b].nk);

@@ -112,11 +112,19 @@ void oracle_phys_flux(const double* q, const double* m, double gamma, double* F)
 double oracle_viscosity(double T, double suth);
 
 /* ---- multi-block (blocks on one host, 1-to-1 aligned face interfaces) ------------- */
+/* A 1-to-1 face connection: ghost layer m (1..3) beyond face_a of block_a is interior
+ * layer m-1 inside face_b of block_b (faces may lie on different axes).  orient maps the
+ * tangential indices, t1 < t2 being the two axes tangential to a face: bit 0 set pairs a's
+ * t1 with b's t2 and a's t2 with b's t1 (else t1-t1, t2-t2); bit 1 set sends index p of
+ * a's t1 to n-1-p on its partner axis; bit 2 the same for a's t2.                       */
 typedef struct oracle_iface {
   int block_a, face_a, block_b, face_b;  /* face = 0..5 in (i-,i+,j-,j+,k-,k+) */
+  int orient;                            /* 0..7, 0 = aligned blocks            */
 } oracle_iface;
 
-/* Copy the 3-wide halos of nvar planes across every interface (both directions).      */
+/* Copy the 3-wide halos of nvar planes (values that do not depend on the index
+ * directions, e.g. the state) across every interface, both directions.  Returns -1 on an
+ * index out of range, orient outside 0..7 or faces of different sizes.                 */
 int oracle_exchange(const oracle_cfg* cfgs, int nb, double* const* arrays, int nvar,
                     const oracle_iface* ifc, int nifc);
 

@@ -50,12 +50,15 @@ class Block:
 
 @dataclasses.dataclass
 class Interface:
-    """A 1-to-1 face connection with identity orientation of the tangential indices."""
+    """A 1-to-1 face connection.  orient maps the tangential indices of face_a onto those
+    of face_b (t1 < t2 the tangential axes of a face): bit 0 swaps t1 and t2, bit 1
+    reverses a's t1, bit 2 reverses a's t2; 0 is the identity of aligned blocks."""
 
     block_a: int
     face_a: int
     block_b: int
     face_b: int
+    orient: int = 0
 
 
 @dataclasses.dataclass
@@ -281,6 +284,71 @@ def structured_interfaces(na, nb, nc, periodic=(True, True, True)):
                     out.append(Interface(me, 3, _block_index(a, (b + 1) % nb, c, na, nb), 2))
                 if c + 1 < nc or periodic[2]:
                     out.append(Interface(me, 5, _block_index(a, b, (c + 1) % nc, na, nb), 4))
+    return out
+
+
+def _sample(arr: np.ndarray, halo: int, gi, gj, gk) -> np.ndarray:
+    """arr[:, k, j, i] at global indices (arrays of equal shape) of an array stored with
+    `halo` layers on every face."""
+    return np.ascontiguousarray(arr[:, gk + halo, gj + halo, gi + halo])
+
+
+def rotated_split(wl_single: Workload, n1: int, about: str = "i") -> Workload:
+    """Cut a periodic single-block workload along i into A = [0, n1) and B = [n1, ni), and
+    store B with its index axes rotated, so that the two blocks meet through oriented
+    interfaces.  about="i": B's (i', j', k') is global (n1 + i', nj-1-k', j') (a quarter
+    turn about i; A's i faces meet B's i faces with A's j along B's reversed k', orient 3).
+    about="k": B's (i', j', k') is global (ni-1-j', i', k') (a quarter turn about k; A's
+    i+ face meets B's j+ face and A's i- face B's j- face, orient 0, the normal index of B
+    running against A's).  Coordinates and states are sampled from the single block, whose
+    halos hold the periodic images, so both blocks carry identical data."""
+    b = wl_single.blocks[0]
+    ni, nj, nk = b.ni, b.nj, b.nk
+    assert 0 < n1 < ni
+
+    def local(nx, ny, nz, h):
+        k, j, i = np.meshgrid(np.arange(-h, nz + h), np.arange(-h, ny + h), np.arange(-h, nx + h), indexing="ij")
+        return i, j, k
+
+    def block_a(h, arr):
+        i, j, k = local(n1, nj, nk, h)
+        return _sample(arr, h, i, j, k)
+
+    if about == "i":
+        dims = (ni - n1, nk, nj)
+        to_global = lambda i, j, k: (n1 + i, nj - 1 - k, j)
+        ifc = [Interface(0, 1, 1, 0, 3), Interface(0, 0, 1, 1, 3)]
+        bc_b = (BC_INTERFACE, BC_INTERFACE, BC_PERIODIC, BC_PERIODIC, BC_PERIODIC, BC_PERIODIC)
+    elif about == "k":
+        dims = (nj, ni - n1, nk)
+        to_global = lambda i, j, k: (ni - 1 - j, i, k)
+        ifc = [Interface(0, 1, 1, 3, 0), Interface(0, 0, 1, 2, 0)]
+        bc_b = (BC_PERIODIC, BC_PERIODIC, BC_INTERFACE, BC_INTERFACE, BC_PERIODIC, BC_PERIODIC)
+    else:
+        raise ValueError(about)
+
+    def block_b(h, arr):
+        i, j, k = local(*dims, h)
+        return _sample(arr, h, *to_global(i, j, k))
+
+    bc_a = (BC_INTERFACE, BC_INTERFACE, BC_PERIODIC, BC_PERIODIC, BC_PERIODIC, BC_PERIODIC)
+    blocks = [Block(n1, nj, nk, block_a(CHALO, b.xyz), block_a(HALO, b.q), bc_a),
+              Block(*dims, block_b(CHALO, b.xyz), block_b(HALO, b.q), bc_b)]
+    return dataclasses.replace(wl_single, name=wl_single.name + f"_rotated_{about}", blocks=blocks, interfaces=ifc)
+
+
+def rotated_to_single(about: str, ni: int, nj: int, nk: int, n1: int, arr_b: np.ndarray) -> np.ndarray:
+    """Block B's interior values of rotated_split placed at their global (k, j, i) positions
+    (an array of shape (nvar, nk, nj, ni - n1) for the global i range [n1, ni))."""
+    nvar = arr_b.shape[0]
+    out = np.empty((nvar, nk, nj, ni - n1))
+    inner = arr_b[:, HALO:-HALO, HALO:-HALO, HALO:-HALO]
+    kb, jb, ib = np.meshgrid(*(np.arange(n) for n in inner.shape[1:]), indexing="ij")
+    if about == "i":
+        gi, gj, gk = n1 + ib, nj - 1 - kb, jb
+    else:
+        gi, gj, gk = ni - 1 - jb, ib, kb
+    out[:, gk, gj, gi - n1] = inner
     return out
 
 

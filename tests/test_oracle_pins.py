@@ -818,3 +818,31 @@ def test_residual_norms_closed_forms():
     rs, ms = O.residual([left, right])
     np.testing.assert_allclose(rs, rms, rtol=1e-14)
     np.testing.assert_array_equal(ms, mx)
+
+
+# ---- oriented block interfaces ----------------------------------------------------------
+@pytest.mark.parametrize("about", ["i", "k"])
+def test_rotated_blocks_reproduce_the_single_block(about):
+    """A periodic box cut into two blocks, the second stored with its index axes turned a
+    quarter about i (tangential indices swapped and reversed across the interfaces) or
+    about k (A's i faces meet B's j faces, B's normal index running against A's): the
+    two-block RHS, with the state and the face-normal viscous fluxes exchanged through the
+    oriented interfaces, equals the single-block RHS at every point.  The directions are
+    summed in another order on the turned block, so the agreement is to round-off: 1e-13
+    with ideal weights and for the viscous terms alone (whose exchanged fluxes change sign
+    where an index reverses), and the WENO-JS bound of 1e-10 (Eq 15 amplifies last-bit
+    differences of the smoothness indicators by up to ~2/eps)."""
+    single = W.vortex_wavy(16, nj=10, nk=8, amp=0.06)
+    rot = W.rotated_split(single, 8, about)
+    for linear, mask, tol in ((True, O.ALL, 1e-13), (False, O.VIS | 7, 1e-13), (False, O.ALL, 1e-10)):
+        c = O.cfg_from_workload(single, linear_weights=linear)
+        ref = interior(O.rhs(c, O.metrics(c, single.blocks[0].xyz), single.blocks[0].q, mask))
+        cfgs = [O.cfg_from_workload(rot, bi, linear_weights=linear) for bi in range(2)]
+        mets = [O.metrics(cc, b.xyz) for cc, b in zip(cfgs, rot.blocks)]
+        rs = O.rhs_multi(cfgs, mets, [b.q for b in rot.blocks], rot.interfaces, mask)
+        scale = np.max(np.abs(ref))
+        err_a = np.max(np.abs(interior(rs[0]) - ref[..., :8])) / scale
+        got_b = W.rotated_to_single(about, 16, 10, 8, 8, rs[1])
+        err_b = np.max(np.abs(got_b - ref[..., 8:])) / scale
+        print(about, linear, mask, err_a, err_b)
+        assert err_a < tol and err_b < tol
