@@ -85,9 +85,19 @@ typedef struct cfd_block_desc {
   cfd_params params;
 } cfd_block_desc;
 
-typedef struct cfd_interface {  /* 1-to-1 face connection, identity orientation        */
+/* 1-to-1 face connection (Sec. 4.2).  Ghost layer m (1..3) beyond face_a of block_a is
+ * interior layer m-1 inside face_b of block_b, and the other way round.  The faces may lie
+ * on different axes.  orient maps the tangential indices: with t1 < t2 the two axes
+ * tangential to a face (i < j < k), bit 0 set means a's t1 runs along b's t2 and a's t2
+ * along b's t1 (else t1 along t1, t2 along t2); bit 1 set means index p along a's t1 is
+ * index n-1-p on its partner axis (else p), bit 2 the same for a's t2.  orient = 0 is the
+ * identity of aligned blocks.  The map from a's indices to b's must keep the handedness
+ * (both blocks have positive Jacobians); the viscous flux of a's face-normal direction
+ * is taken from b's face-normal direction, negated when the two run opposite ways.     */
+typedef struct cfd_interface {
   int32_t block_a, face_a;      /* face index 0..5 in the order of cfd_block_desc.bc   */
-  int32_t block_b, face_b;      /* faces must be on the same axis and of equal size    */
+  int32_t block_b, face_b;      /* faces of equal size after the orientation           */
+  int32_t orient;               /* 0..7 as above                                       */
 } cfd_interface;
 
 typedef struct cfd_block cfd_block;
@@ -157,9 +167,11 @@ int cfd_rk_sweeps(cfd_block* b, int stage, double dt, const double* Qn, const do
 
 /* ---- halo exchange ----------------------------------------------------------------- */
 /* Plan the halo traffic of nb blocks: ifc lists the 1-to-1 interfaces (a face of a block
- * listed with itself on the opposite face is a periodic wrap); every face whose kind is
- * CFD_BC_PERIODIC must appear, CFD_BC_WALL / CFD_BC_FARFIELD faces get ghost fills.
- * Errors: CFD_ERR_ARG on mismatched face sizes, axes or kinds.                          */
+ * listed with another face of itself is a periodic wrap, possibly with a rotation);
+ * faces of kind CFD_BC_PERIODIC wrap onto the opposite face of their own block,
+ * CFD_BC_WALL / CFD_BC_FARFIELD faces get ghost fills.
+ * Errors: CFD_ERR_ARG on mismatched face sizes or kinds, orient outside 0..7, a map that
+ * reverses handedness, or a face used twice.                                          */
 int cfd_exchange_create(cfd_block* const* blocks, int nb, const cfd_interface* ifc, int nifc,
                         cfd_exchange** out);
 int cfd_exchange_destroy(cfd_exchange* x);

@@ -48,7 +48,8 @@ class cfd_block_desc(C.Structure):
 
 
 class cfd_interface(C.Structure):
-    _fields_ = [("block_a", C.c_int32), ("face_a", C.c_int32), ("block_b", C.c_int32), ("face_b", C.c_int32)]
+    _fields_ = [("block_a", C.c_int32), ("face_a", C.c_int32), ("block_b", C.c_int32), ("face_b", C.c_int32),
+                ("orient", C.c_int32)]
 
 
 _lib = None
@@ -202,6 +203,7 @@ def cfd_exchange_create(blocks: Sequence[int], interfaces: Sequence) -> int:
     ifc = (cfd_interface * max(1, n))()
     for k, f in enumerate(interfaces):
         ifc[k].block_a, ifc[k].face_a, ifc[k].block_b, ifc[k].face_b = f.block_a, f.face_a, f.block_b, f.face_b
+        ifc[k].orient = getattr(f, "orient", 0)
     h = _VP()
     _check(lib().cfd_exchange_create(arr, len(blocks), ifc, n, C.byref(h)))
     return h.value

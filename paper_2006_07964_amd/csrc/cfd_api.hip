@@ -200,33 +200,81 @@ void tangential(int axis, int* ta, int* tb) {
   *tb = axis == 2 ? 1 : 2;
 }
 
-CopySeg make_copy(const Geom& A, int ia, int fa, const Geom& B, int ib, int fb, int plane0, int nplanes) {
+// Tangential index map of an interface (orient bits: 0 swap, 1 reverse a's t1, 2 reverse
+// a's t2): a's tangential axis q (0: t1, 1: t2) runs along b's axis map_axis[q], reversed
+// when map_rev[q].
+struct FaceMap {
+  int axis_a, axis_b;      // face-normal axes
+  int ta[2], tb[2];        // tangential axes of both faces (increasing)
+  int map_axis[2];         // b's axis that a's ta[q] runs along
+  bool map_rev[2];
+  int normal_sign;         // +1: a's normal index and b's run the same way through the face
+};
+
+FaceMap face_map(int fa, int fb, int orient) {
+  FaceMap m;
+  m.axis_a = fa / 2;
+  m.axis_b = fb / 2;
+  tangential(m.axis_a, &m.ta[0], &m.ta[1]);
+  tangential(m.axis_b, &m.tb[0], &m.tb[1]);
+  const bool swap = orient & 1;
+  m.map_axis[0] = swap ? m.tb[1] : m.tb[0];
+  m.map_axis[1] = swap ? m.tb[0] : m.tb[1];
+  m.map_rev[0] = (orient >> 1) & 1;
+  m.map_rev[1] = (orient >> 2) & 1;
+  const int outa = (fa % 2) ? +1 : -1, outb = (fb % 2) ? +1 : -1;
+  m.normal_sign = -outa * outb;  // ghost m of a = interior m-1 of b: a steps outward as b steps inward
+  return m;
+}
+
+// determinant of the signed axis permutation taking a's index directions to b's
+int face_map_det(const FaceMap& m) {
+  int M[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // M[b axis][a axis]
+  M[m.axis_b][m.axis_a] = m.normal_sign;
+  for (int q = 0; q < 2; ++q) M[m.map_axis[q]][m.ta[q]] = m.map_rev[q] ? -1 : 1;
+  return M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+         M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+}
+
+// orient of the same interface seen from b
+int inverse_orient(int orient) {
+  const int r1 = (orient >> 1) & 1, r2 = (orient >> 2) & 1;
+  return (orient & 1) ? (1 | (r2 << 1) | (r1 << 2)) : orient;
+}
+
+// halo copy of face fa of block A (index ia) from face fb of block B (index ib) under the
+// tangential map orient: ghost layer m (1..3) beyond fa <- interior layer m-1 inside fb.
+// Planes plane0.. of A receive planes src_plane0.. of B, negated if negate.
+CopySeg make_copy(const Geom& A, int ia, int fa, const Geom& B, int ib, int fb, int plane0, int nplanes,
+                  int orient = 0, int src_plane0 = -1, int negate = 0) {
   int axis, wa, outa, wb, outb;
   face_geom(A, fa, &axis, &wa, &outa);
   int axis_b;
   face_geom(B, fb, &axis_b, &wb, &outb);
-  int ta, tb;
-  tangential(axis, &ta, &tb);
+  const FaceMap m = face_map(fa, fb, orient);
   CopySeg s;
   std::memset(&s, 0, sizeof s);
   s.layer_fast = axis == 0;  // on i faces the three halo layers are the contiguous run
   s.dst = ia;
   s.src = ib;
-  s.na = npts(A, ta);
-  s.nb = npts(A, tb);
+  s.na = npts(A, m.ta[0]);
+  s.nb = npts(A, m.ta[1]);
   s.plane0 = plane0;
+  s.src_plane0 = src_plane0 < 0 ? plane0 : src_plane0;
+  s.negate = negate;
   s.nplanes = nplanes;
   int ida[3] = {0, 0, 0}, idb[3] = {0, 0, 0};
   ida[axis] = wa + outa;  // ghost layer 1
-  idb[axis] = wb;         // interior layer 0
+  idb[axis_b] = wb;       // interior layer 0
+  for (int q = 0; q < 2; ++q) idb[m.map_axis[q]] = m.map_rev[q] ? npts(B, m.map_axis[q]) - 1 : 0;
   s.dst_off = at_h(A, ida[0], ida[1], ida[2]);
   s.src_off = at_h(B, idb[0], idb[1], idb[2]);
-  s.dst_sa = stride(A, ta);
-  s.dst_sb = stride(A, tb);
+  s.dst_sa = stride(A, m.ta[0]);
+  s.dst_sb = stride(A, m.ta[1]);
   s.dst_sl = outa * stride(A, axis);
-  s.src_sa = stride(B, ta);
-  s.src_sb = stride(B, tb);
-  s.src_sl = -outb * stride(B, axis);
+  s.src_sa = (m.map_rev[0] ? -1 : 1) * stride(B, m.map_axis[0]);
+  s.src_sb = (m.map_rev[1] ? -1 : 1) * stride(B, m.map_axis[1]);
+  s.src_sl = -outb * stride(B, axis_b);
   return s;
 }
 
@@ -1175,21 +1223,27 @@ int cfd_exchange_create(cfd_block* const* blocks, int nb, const cfd_interface* i
     if (f.block_a < 0 || f.block_a >= nb || f.block_b < 0 || f.block_b >= nb || f.face_a < 0 || f.face_a > 5 ||
         f.face_b < 0 || f.face_b > 5)
       return fail(CFD_ERR_ARG, "interface index out of range");
-    if (f.face_a / 2 != f.face_b / 2 || f.face_a == f.face_b)
-      return fail(CFD_ERR_ARG, "interface faces must be opposite faces of one axis");
+    if (f.block_a == f.block_b && f.face_a == f.face_b) return fail(CFD_ERR_ARG, "an interface joins two faces");
+    if (f.orient < 0 || f.orient > 7) return fail(CFD_ERR_ARG, "interface orient must be 0..7");
     const cfd_block* A = blocks[f.block_a];
     const cfd_block* B = blocks[f.block_b];
     if (A->d.bc[f.face_a] != CFD_BC_INTERFACE || B->d.bc[f.face_b] != CFD_BC_INTERFACE)
       return fail(CFD_ERR_ARG, "interface faces must have kind CFD_BC_INTERFACE");
-    const int ax = f.face_a / 2;
-    for (int t = 1; t <= 2; ++t)
-      if (npts(A->g, (ax + t) % 3) != npts(B->g, (ax + t) % 3)) return fail(CFD_ERR_ARG, "interface face sizes differ");
+    const FaceMap m = face_map(f.face_a, f.face_b, f.orient);
+    for (int q = 0; q < 2; ++q)
+      if (npts(A->g, m.ta[q]) != npts(B->g, m.map_axis[q])) return fail(CFD_ERR_ARG, "interface face sizes differ");
+    if (face_map_det(m) != 1) return fail(CFD_ERR_ARG, "interface orientation reverses handedness");
     if (used[6 * f.block_a + f.face_a]++ || used[6 * f.block_b + f.face_b]++)
       return fail(CFD_ERR_ARG, "a face appears in more than one interface");
-    qs.push_back(make_copy(A->g, f.block_a, f.face_a, B->g, f.block_b, f.face_b, 0, 5));
-    qs.push_back(make_copy(B->g, f.block_b, f.face_b, A->g, f.block_a, f.face_a, 0, 5));
-    vs.push_back(make_copy(A->g, f.block_a, f.face_a, B->g, f.block_b, f.face_b, 4 * ax, 4));
-    vs.push_back(make_copy(B->g, f.block_b, f.face_b, A->g, f.block_a, f.face_a, 4 * ax, 4));
+    const int inv = inverse_orient(f.orient);
+    const int neg = m.normal_sign < 0;
+    qs.push_back(make_copy(A->g, f.block_a, f.face_a, B->g, f.block_b, f.face_b, 0, 5, f.orient));
+    qs.push_back(make_copy(B->g, f.block_b, f.face_b, A->g, f.block_a, f.face_a, 0, 5, inv));
+    // the face-normal direction's viscous flux: a's direction axis_a is b's axis_b
+    vs.push_back(make_copy(A->g, f.block_a, f.face_a, B->g, f.block_b, f.face_b, 4 * m.axis_a, 4, f.orient,
+                           4 * m.axis_b, neg));
+    vs.push_back(make_copy(B->g, f.block_b, f.face_b, A->g, f.block_a, f.face_a, 4 * m.axis_b, 4, inv,
+                           4 * m.axis_a, neg));
   }
   for (int n = 0; n < nb; ++n) {
     const cfd_block* B = blocks[n];

@@ -855,7 +855,7 @@ __global__ __launch_bounds__(256) void k_copy(const CopySeg* segs, PtrTable t) {
   const T* src = static_cast<const T*>(t.p[S.src]);
   const int64_t pd = t.plane[S.dst], ps = t.plane[S.src];
   for (int e = blockIdx.x * 256 + threadIdx.x; e < total; e += gridDim.x * 256) {
-    const int v = S.plane0 + e / per_plane;
+    const int vv = e / per_plane;
     int r = e % per_plane;
     int a, l;
     if (S.layer_fast) {
@@ -870,8 +870,8 @@ __global__ __launch_bounds__(256) void k_copy(const CopySeg* segs, PtrTable t) {
       r /= kHalo;
     }
     const int b = r;
-    dst[v * pd + S.dst_off + a * S.dst_sa + b * S.dst_sb + l * S.dst_sl] =
-        src[v * ps + S.src_off + a * S.src_sa + b * S.src_sb + l * S.src_sl];
+    const T x = src[(S.src_plane0 + vv) * ps + S.src_off + a * S.src_sa + b * S.src_sb + l * S.src_sl];
+    dst[(S.plane0 + vv) * pd + S.dst_off + a * S.dst_sa + b * S.dst_sb + l * S.dst_sl] = S.negate ? -x : x;
   }
 }
 

@@ -97,6 +97,8 @@ struct CopySeg {
   int32_t na, nb;            // tangential extents
   int32_t plane0, nplanes;   // planes copied
   int32_t layer_fast, pad;   // 1: halo layer is the fastest thread index, else a
+  int32_t src_plane0;        // first source plane (dst planes start at plane0)
+  int32_t negate;            // 1: copy the negated values
   int64_t dst_off, src_off;  // element offsets of (a=0, b=0, layer 0)
   int64_t dst_sa, dst_sb, dst_sl;
   int64_t src_sa, src_sb, src_sl;

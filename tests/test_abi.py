@@ -66,7 +66,7 @@ int main(void) {
 
 def test_argument_errors_without_gpu(lib):
     for bad in (dict(ni=5), dict(ld_i=10), dict(precision=7), dict(weights=3), dict(gamma=1.0),
-                dict(bc=(0, 2, 0, 0, 0, 0))):
+                dict(bc=(0, 2, 0, 0, 0, 0)), dict(scheme=2)):
         kw = dict(ni=16, nj=16, nk=16)
         kw.update(bad)
         ni = kw.pop("ni")
@@ -77,6 +77,16 @@ def test_argument_errors_without_gpu(lib):
             B.cfd_block_create(desc)
         assert e.value.code == B.CFD_ERR_ARG
         assert B.cfd_last_error()
+    # one plane of a block (pitched rows x columns x (nk + 6)) must stay below 2^29 points:
+    # pitches 1024 x 1024 with nk = 506 give exactly 2^29 and are refused before any allocation
+    desc = B.make_desc(1018, 1018, 506, ld_i=1024, ld_j=1024)
+    with pytest.raises(B.CfdError) as e:
+        B.cfd_block_create(desc)
+    assert e.value.code == B.CFD_ERR_UNSUPPORTED
+    for call in (lambda: B.cfd_residual([], []), lambda: B.cfd_dt_cfl_dev([], [], 0.5, None)):
+        with pytest.raises(B.CfdError) as e:
+            call()
+        assert e.value.code == B.CFD_ERR_ARG
     with pytest.raises(B.CfdError) as e:
         B.cfd_exchange_create([], [])
     assert e.value.code == B.CFD_ERR_ARG
