@@ -67,6 +67,9 @@ def lib():
         L.oracle_bc_fill.restype = None
         L.oracle_dt_cfl.argtypes = [cp, P, P, C.c_double]
         L.oracle_dt_cfl.restype = C.c_double
+        L.oracle_dt_local.argtypes = [cp, P, P, C.c_double, P]
+        L.oracle_dt_local.restype = None
+        L.oracle_rk_step_local.argtypes = [cp, P, P, P]
         L.oracle_weno5.argtypes = [P, C.c_double, C.c_int, P, P]
         L.oracle_weno5.restype = None
         L.oracle_eigvec.argtypes = [P, P, C.c_double, P, P]
@@ -201,6 +204,21 @@ def residual(a_arrays, b_arrays=None, scale: float = 1.0):
         mx = np.maximum(mx, np.max(np.abs(d), axis=(1, 2, 3)))
         n += d[0].size
     return list(np.sqrt(sq / n)), list(mx)
+
+
+def dt_local(c: Cfg, met, q, cfl) -> np.ndarray:
+    """Per-point CFL steps (one plane in the state layout; halo entries zero)."""
+    out = np.zeros(state_shape(c, 1))
+    lib().oracle_dt_local(C.byref(c), _p(met), _p(np.ascontiguousarray(q)), cfl, _p(out))
+    return out
+
+
+def rk_step_local(c: Cfg, met, dt_field, q) -> np.ndarray:
+    out = np.array(q, dtype=np.float64, copy=True)
+    rc = lib().oracle_rk_step_local(C.byref(c), _p(met), _p(np.ascontiguousarray(dt_field, dtype=np.float64)), _p(out))
+    if rc != 0:
+        raise ValueError(f"oracle_rk_step_local failed ({rc})")
+    return out
 
 
 def weno5(v: Sequence[float], eps: float = 1e-6, linear: bool = False):

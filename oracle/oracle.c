@@ -753,21 +753,28 @@ int oracle_rhs(const oracle_cfg* c, const double* met, const double* Q, double* 
 /* Eq 20 coefficients (a, b, c) of Qout = a Qn + b Qcur + c dt R(Qcur) */
 static const double RK3[3][3] = {{1.0, 0.0, 1.0}, {3.0 / 4.0, 1.0 / 4.0, 1.0 / 4.0}, {1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0}};
 
-static void rk_combine(const oracle_cfg* c, int stage, double dt, const double* Qn, const double* Qcur,
-                       const double* R, double* Qout) {
+/* dtf: a time step per point (one plane in the state layout) in place of dt, or NULL */
+static void rk_combine_dt(const oracle_cfg* c, int stage, double dt, const double* dtf, const double* Qn,
+                          const double* Qcur, const double* R, double* Qout) {
   const dims_t sd = state_dims(c);
   int i, j, k, v;
   for (v = 0; v < 5; ++v)
     for (k = 0; k < c->nk; ++k)
       for (j = 0; j < c->nj; ++j)
         for (i = 0; i < c->ni; ++i) {
-          long p = v * sd.plane + sidx(&sd, i, j, k);
-          Qout[p] = RK3[stage][0] * Qn[p] + RK3[stage][1] * Qcur[p] + RK3[stage][2] * dt * R[p];
+          long pp = sidx(&sd, i, j, k), p = v * sd.plane + pp;
+          double h = dtf ? dtf[pp] : dt;
+          Qout[p] = RK3[stage][0] * Qn[p] + RK3[stage][1] * Qcur[p] + RK3[stage][2] * h * R[p];
         }
 }
 
-int oracle_rk_stage(const oracle_cfg* c, const double* met, int stage, double dt, const double* Qn,
-                    const double* Qcur, double* Qout) {
+static void rk_combine(const oracle_cfg* c, int stage, double dt, const double* Qn, const double* Qcur,
+                       const double* R, double* Qout) {
+  rk_combine_dt(c, stage, dt, NULL, Qn, Qcur, R, Qout);
+}
+
+static int rk_stage_dt(const oracle_cfg* c, const double* met, int stage, double dt, const double* dtf,
+                       const double* Qn, const double* Qcur, double* Qout) {
   const dims_t sd = state_dims(c);
   double* R;
   int rc;
@@ -775,7 +782,7 @@ int oracle_rk_stage(const oracle_cfg* c, const double* met, int stage, double dt
   R = (double*)calloc((size_t)5 * sd.plane, sizeof(double));
   rc = oracle_rhs(c, met, Qcur, R, ORACLE_ALL, 0, c->nk);
   if (rc == 0) {
-    rk_combine(c, stage, dt, Qn, Qcur, R, Qout);
+    rk_combine_dt(c, stage, dt, dtf, Qn, Qcur, R, Qout);
     oracle_wall_reset(c, Qout);
     oracle_periodic_wrap(c, Qout, 5);
     oracle_bc_fill(c, Qout);
@@ -784,7 +791,12 @@ int oracle_rk_stage(const oracle_cfg* c, const double* met, int stage, double dt
   return rc;
 }
 
-int oracle_rk_step(const oracle_cfg* c, const double* met, double dt, double* Q) {
+int oracle_rk_stage(const oracle_cfg* c, const double* met, int stage, double dt, const double* Qn,
+                    const double* Qcur, double* Qout) {
+  return rk_stage_dt(c, met, stage, dt, NULL, Qn, Qcur, Qout);
+}
+
+static int rk_step_dt(const oracle_cfg* c, const double* met, double dt, const double* dtf, double* Q) {
   const dims_t sd = state_dims(c);
   size_t bytes = (size_t)5 * sd.plane * sizeof(double);
   double* A = (double*)malloc(bytes);
@@ -792,13 +804,22 @@ int oracle_rk_step(const oracle_cfg* c, const double* met, double dt, double* Q)
   int rc;
   memcpy(A, Q, bytes);
   memcpy(B, Q, bytes);
-  rc = oracle_rk_stage(c, met, 0, dt, Q, Q, A);
-  if (!rc) rc = oracle_rk_stage(c, met, 1, dt, Q, A, B);
-  if (!rc) rc = oracle_rk_stage(c, met, 2, dt, Q, B, A);
+  rc = rk_stage_dt(c, met, 0, dt, dtf, Q, Q, A);
+  if (!rc) rc = rk_stage_dt(c, met, 1, dt, dtf, Q, A, B);
+  if (!rc) rc = rk_stage_dt(c, met, 2, dt, dtf, Q, B, A);
   if (!rc) memcpy(Q, A, bytes);
   free(A);
   free(B);
   return rc;
+}
+
+int oracle_rk_step(const oracle_cfg* c, const double* met, double dt, double* Q) {
+  return rk_step_dt(c, met, dt, NULL, Q);
+}
+
+int oracle_rk_step_local(const oracle_cfg* c, const double* met, const double* dt_field, double* Q) {
+  if (!dt_field) return -1;
+  return rk_step_dt(c, met, 0.0, dt_field, Q);
 }
 
 /* Reading: dt = CFL / max over interior points of sum_d (|U_d| + c |grad d|) with the
@@ -827,6 +848,33 @@ double oracle_dt_cfl(const oracle_cfg* c, const double* met, const double* Q, do
       }
   }
   return cfl / smax;
+}
+
+/* Local time steps (steady runs): the same spectral radius, point by point.  Reading: the
+ * stored step of each point is cfl / sum_d (|U_d| + c |grad d|) (inviscid limit only, as
+ * for the global step); halo entries are left untouched.                                */
+void oracle_dt_local(const oracle_cfg* c, const double* met, const double* Q, double cfl, double* dt_field) {
+  const dims_t sd = state_dims(c);
+  int k;
+#pragma omp parallel for schedule(static)
+  for (k = 0; k < c->nk; ++k) {
+    int i, j, d, n;
+    for (j = 0; j < c->nj; ++j)
+      for (i = 0; i < c->ni; ++i) {
+        long p = sidx(&sd, i, j, k);
+        double q[5], sum = 0.0, Jp = met[9 * sd.plane + p];
+        prim_t s;
+        for (n = 0; n < 5; ++n) q[n] = Q[n * sd.plane + p];
+        s = primitives(q, c->gamma);
+        for (d = 0; d < 3; ++d) {
+          double mx = Jp * met[(3 * d + 0) * sd.plane + p];
+          double my = Jp * met[(3 * d + 1) * sd.plane + p];
+          double mz = Jp * met[(3 * d + 2) * sd.plane + p];
+          sum += fabs(mx * s.u + my * s.v + mz * s.w) + s.c * sqrt(mx * mx + my * my + mz * mz);
+        }
+        dt_field[p] = cfl / sum;
+      }
+  }
 }
 
 /* ------------------------------------------------------------------------------------ */

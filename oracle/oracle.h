@@ -93,6 +93,11 @@ void oracle_bc_fill(const oracle_cfg* c, double* Q);
 
 /* CFL time step: cfl / max over interior of sum_d (|U_d| + c |grad d|).                 */
 double oracle_dt_cfl(const oracle_cfg* c, const double* met, const double* Q, double cfl);
+/* Local time steps for steady runs: dt_field (one plane, state layout) receives
+ * cfl / sum_d (|U_d| + c |grad d|) at every interior point; halo entries untouched.       */
+void oracle_dt_local(const oracle_cfg* c, const double* met, const double* Q, double cfl, double* dt_field);
+/* One RK3 step in place on Q with a time step per point (dt_field) in Eq 20.              */
+int oracle_rk_step_local(const oracle_cfg* c, const double* met, const double* dt_field, double* Q);
 
 /* ---- point-level pieces, exposed so that tests can pin them individually ---------- */
 /* Eqs 13-17 (with the sub-stencil pairing of the 5th-order interpolant): from the five

@@ -846,3 +846,29 @@ def test_rotated_blocks_reproduce_the_single_block(about):
         err_b = np.max(np.abs(got_b - ref[..., 8:])) / scale
         print(about, linear, mask, err_a, err_b)
         assert err_a < tol and err_b < tol
+
+
+# ---- local time steps (steady runs) -------------------------------------------------------
+def test_local_time_steps():
+    """Uniform flow on a Cartesian grid of spacings (hx, hy, hz): each stored step is
+    cfl / sum_d (|u_d| + c) / h_d; on a curvilinear state the smallest stored step is the
+    global CFL step exactly; a constant field of steps reproduces the scalar RK step."""
+    ni, nj, nk = 10, 8, 7
+    c = O.make_cfg(ni, nj, nk, viscous=False)
+    xyz = W.cartesian_grid(ni, nj, nk, 2.0, 1.0, 0.5)
+    met = O.metrics(c, xyz)
+    u, v, w = 0.3, -0.2, 0.1
+    q = W.uniform_state((nk + 6, nj + 6, ni + 6), u=u, v=v, w=w)
+    dtf = O.dt_local(c, met, q, 0.7)
+    h = (2.0 / ni, 1.0 / nj, 0.5 / nk)
+    expect = 0.7 / ((abs(u) + 1.0) / h[0] + (abs(v) + 1.0) / h[1] + (abs(w) + 1.0) / h[2])
+    np.testing.assert_allclose(dtf[0, 3:-3, 3:-3, 3:-3], expect, rtol=1e-13)
+    wl = W.vortex_wavy(16, seed=1)
+    c = O.cfg_from_workload(wl)
+    met = O.metrics(c, wl.blocks[0].xyz)
+    q = wl.blocks[0].q
+    dtf = O.dt_local(c, met, q, 0.5)
+    dt = O.dt_cfl(c, met, q, 0.5)
+    assert np.min(dtf[0, 3:-3, 3:-3, 3:-3]) == dt
+    const = np.full_like(dtf, dt)
+    np.testing.assert_array_equal(O.rk_step_local(c, met, const, q), O.rk_step(c, met, dt, q))
