@@ -200,6 +200,18 @@ int cfd_dt_cfl(cfd_block* const* blocks, int nb, const double* const* Q, double 
  * Errors: CFD_ERR_ARG, CFD_ERR_STATE (no metrics), CFD_ERR_HIP.                        */
 int cfd_dt_cfl_dev(cfd_block* const* blocks, int nb, const double* const* Q, double cfl,
                    double* dt_dev);
+/* Local time steps for steady runs (the stored step per point that Sec. 4.4 lists for
+ * local time stepping): dt_field[b] (device, one plane in block b's layout, caller-owned)
+ * receives cfl / sum_d (|U_d| + c |grad d|) at every interior point of block b (the
+ * spectral radius of cfd_dt_cfl, point by point; halo entries untouched).  Enqueued on
+ * each block's stream; no synchronisation.  Errors: CFD_ERR_ARG, CFD_ERR_STATE, CFD_ERR_HIP. */
+int cfd_dt_local(cfd_block* const* blocks, int nb, const double* const* Q, double cfl,
+                 double* const* dt_field);
+/* Make every later RK stage of block b (cfd_rk_stage[_dev], cfd_rk_sweeps and the batched
+ * steps) take the step of each point from dt_field (device, one plane in b's layout,
+ * caller-owned, kept alive while set) instead of the scalar dt, which is then ignored;
+ * NULL restores the scalar step.  A batch notices the change at its next step.          */
+int cfd_block_set_local_dt(cfd_block* b, const double* dt_field);
 /* Residual norms (the residual evaluation that closes each iteration of Fig 2, a
  * reduced-dimensional reduction of Sec. 4.5.3): with d = scale * (A[b] - B[b]) over the
  * interior points of all nb blocks (B or B[b] NULL: d = scale * A[b]),

@@ -85,6 +85,8 @@ def lib():
         "cfd_halo_exchange": ([_VP, C.c_int, C.POINTER(_VP), _VP], C.c_int),
         "cfd_dt_cfl": ([C.POINTER(_VP), C.c_int, C.POINTER(_VP), C.c_double, _DP], C.c_int),
         "cfd_dt_cfl_dev": ([C.POINTER(_VP), C.c_int, C.POINTER(_VP), C.c_double, _VP], C.c_int),
+        "cfd_dt_local": ([C.POINTER(_VP), C.c_int, C.POINTER(_VP), C.c_double, C.POINTER(_VP)], C.c_int),
+        "cfd_block_set_local_dt": ([_VP, _VP], C.c_int),
         "cfd_residual": ([C.POINTER(_VP), C.c_int, C.POINTER(_VP), C.POINTER(_VP), C.c_double, _DP], C.c_int),
         "cfd_check_finite": ([_VP, _VP, C.POINTER(C.c_int)], C.c_int),
         "cfd_sync": ([_VP], C.c_int),
@@ -228,6 +230,15 @@ def cfd_dt_cfl(blocks: Sequence[int], qs: Sequence, cfl: float) -> float:
 def cfd_dt_cfl_dev(blocks: Sequence[int], qs: Sequence, cfl: float, dt_dev) -> None:
     arr = (_VP * len(blocks))(*blocks)
     _check(lib().cfd_dt_cfl_dev(arr, len(blocks), _vp_array(qs), cfl, _ptr(dt_dev)))
+
+
+def cfd_dt_local(blocks: Sequence[int], qs: Sequence, cfl: float, dt_fields: Sequence) -> None:
+    arr = (_VP * len(blocks))(*blocks)
+    _check(lib().cfd_dt_local(arr, len(blocks), _vp_array(qs), cfl, _vp_array(dt_fields)))
+
+
+def cfd_block_set_local_dt(b: int, dt_field) -> None:
+    _check(lib().cfd_block_set_local_dt(b, _ptr(dt_field)))
 
 
 def cfd_residual(blocks: Sequence[int], a: Sequence, b: Optional[Sequence] = None, scale: float = 1.0):

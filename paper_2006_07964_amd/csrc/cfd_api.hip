@@ -148,6 +148,7 @@ struct cfd_block {
   unsigned long long* red_dev = nullptr;
   int* flag_dev = nullptr;
   double* res_dev = nullptr;  // residual partial rows of up to kMaxBlocks blocks (allocated on first use)
+  const double* dt_field = nullptr;  // caller's per-point time steps (local time stepping) or null
   hipEvent_t ev = nullptr;    // orders this block's stream before another block's
   Profiler prof;
 };
@@ -408,6 +409,7 @@ int run_sweeps(cfd_block* b, const double* Q, unsigned mask, int out_kind, doubl
   a.b.met = b->met;
   a.b.vis = b->vis;
   a.b.qn = qn;
+  a.b.dt_field = b->dt_field;
   a.c.ph = make_phys(b->d.params);
   a.c.do_inv = inv;
   a.c.do_vis = vis;
@@ -727,6 +729,26 @@ int cfd_dt_cfl_dev(cfd_block* const* blocks, int nb, const double* const* Q, dou
   return CFD_OK;
 }
 
+int cfd_dt_local(cfd_block* const* blocks, int nb, const double* const* Q, double cfl, double* const* dt_field) {
+  if (!blocks || nb <= 0 || !Q || !dt_field) return fail(CFD_ERR_ARG, "null argument");
+  if (!(cfl > 0.0)) return fail(CFD_ERR_ARG, "cfl must be positive");
+  for (int n = 0; n < nb; ++n) {
+    if (!blocks[n] || !Q[n] || !dt_field[n]) return fail(CFD_ERR_ARG, "null block, state or step field");
+    if (!blocks[n]->have_metrics) return fail(CFD_ERR_STATE, "cfd_metrics has not been run on a block");
+  }
+  for (int n = 0; n < nb; ++n) {
+    cfd_block* b = blocks[n];
+    HIP_TRY(launch_dt_local(b->g, Q[n], b->met, b->d.params.gamma, cfl, dt_field[n], b->stream), "local dt launch");
+  }
+  return CFD_OK;
+}
+
+int cfd_block_set_local_dt(cfd_block* b, const double* dt_field) {
+  if (!b) return fail(CFD_ERR_ARG, "null block");
+  b->dt_field = dt_field;
+  return CFD_OK;
+}
+
 int cfd_residual(cfd_block* const* blocks, int nb, const double* const* A, const double* const* Bm, double scale,
                  double* out) {
   if (!blocks || nb <= 0 || nb > kMaxBlocks || !A || !out) return fail(CFD_ERR_ARG, "need 1..64 blocks, A and out");
@@ -998,6 +1020,7 @@ void build_args(cfd_batch* bt, double* const* Qn, double* const* QA, double* con
         a.rt_out = B->rt;
         a.out = d == kSweepOrder[2] ? outp[b] : nullptr;
         a.qn = Qn[b];
+        a.dt_field = B->dt_field;
         sweep_tiling(d, bt->cfg[d], B->g, &a.tiles_c1, &a.tiles_d, &a.tile_len);
       }
     }
@@ -1131,6 +1154,7 @@ int batch_step(cfd_batch* bt, const double* dt_dev, double* const* Qn, double* c
     key.push_back(Qn[b]);
     key.push_back(QA[b]);
     key.push_back(QB[b]);
+    key.push_back(bt->blocks[b]->dt_field);
   }
   // order the batch stream after the caller's work
   HIP_TRY(hipEventRecord(bt->ev_in, bt->user), "event record");

@@ -654,7 +654,9 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
 #pragma unroll
       for (int v = 0; v < 5; ++v) stg(plane_ptr(out, v * plane), po, Jo * double(r[v]));
     } else {
-      const double dt = c.dt_dev ? *c.dt_dev : c.dt;
+      // local time stepping reads the point's own step here rather than with the other
+      // operands: the common scalar-step path keeps its register budget
+      const double dt = b.dt_field ? ldg(to_global(b.dt_field), po) : c.dt_dev ? *c.dt_dev : c.dt;
       const double cdt = c.cc * dt * Jo;
 #pragma unroll
       for (int v = 0; v < 5; ++v) stg(plane_ptr(out, v * plane), po, c.ca * qno[v] + c.cb * qco[v] + cdt * double(r[v]));
@@ -1043,6 +1045,40 @@ hipError_t launch_finite(const Geom& g, const double* q, int* flag, hipStream_t 
   int bx = (int)((total + 255) / 256);
   if (bx > 8192) bx = 8192;
   hipLaunchKernelGGL(k_finite, dim3(bx), dim3(256), 0, s, g, q, flag);
+  return hipGetLastError();
+}
+
+// ---- local time steps: the CFL step of every interior point ---------------------------
+__global__ __launch_bounds__(256) void k_dt_local(Geom g, const double* q, const double* met, double gamma, double cfl,
+                                                  double* dt_field) {
+  const int64_t total = (int64_t)g.ni * g.nj * g.nk;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int i = (int)(e % g.ni);
+    const int64_t r = e / g.ni;
+    const int j = (int)(r % g.nj), k = (int)(r / g.nj);
+    const int64_t p = at(g, i, j, k);
+    const double rho = q[p], rinv = 1.0 / rho;
+    const double u = q[g.plane + p] * rinv, v = q[2 * g.plane + p] * rinv, w = q[3 * g.plane + p] * rinv;
+    const double pr = (gamma - 1.0) * (q[4 * g.plane + p] - 0.5 * rho * (u * u + v * v + w * w));
+    const double c = sqrt(gamma * pr * rinv);
+    const double J = met[9 * g.plane + p];
+    double sum = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      const double ax = J * met[(3 * d) * g.plane + p], ay = J * met[(3 * d + 1) * g.plane + p],
+                   az = J * met[(3 * d + 2) * g.plane + p];
+      sum += fabs(ax * u + ay * v + az * w) + c * sqrt(ax * ax + ay * ay + az * az);
+    }
+    dt_field[p] = cfl / sum;
+  }
+}
+
+hipError_t launch_dt_local(const Geom& g, const double* q, const double* met, double gamma, double cfl,
+                           double* dt_field, hipStream_t s) {
+  const int64_t total = (int64_t)g.ni * g.nj * g.nk;
+  int bx = (int)((total + 255) / 256);
+  if (bx > 8192) bx = 8192;
+  if (bx < 1) bx = 1;
+  hipLaunchKernelGGL(k_dt_local, dim3(bx), dim3(256), 0, s, g, q, met, gamma, cfl, dt_field);
   return hipGetLastError();
 }
 

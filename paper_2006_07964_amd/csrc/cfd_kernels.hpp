@@ -60,6 +60,7 @@ struct SweepBlock {
   void* rt_out;       // partial sums out (kOutPartial)
   double* out;        // R (kOutRhs) or Qout (kOutRK)
   const double* qn;   // RK base state (kOutRK)
+  const double* dt_field;  // a time step per point (one plane) in place of the scalar one, or null
   int tiles_c1, tiles_d, tile_len;  // filled by the launcher
 };
 // part shared by every block of a launch
@@ -133,6 +134,8 @@ hipError_t launch_dt_max(const Geom& g, const double* q, const double* met, doub
                          unsigned long long* acc, hipStream_t s);
 hipError_t launch_finite(const Geom& g, const double* q, int* flag, hipStream_t s);
 hipError_t launch_dt_reset(unsigned long long* acc, hipStream_t s);
+hipError_t launch_dt_local(const Geom& g, const double* q, const double* met, double gamma, double cfl,
+                           double* dt_field, hipStream_t s);
 hipError_t launch_dt_finish(const unsigned long long* acc, double cfl, double* dt, hipStream_t s);
 // residual norms: kResGroups partial rows (10 doubles: 5 sums of squares, 5 maxima) per
 // block, then one reduction of nparts rows to (5 RMS values, 5 maxima)

@@ -142,3 +142,83 @@ def test_residual_argument_errors():
             B.cfd_residual([dev.h], [dev.q], None, float("inf"))
     finally:
         dev.close()
+
+
+def _dt_plane(desc):
+    return B.state_tensor(desc, 1)
+
+
+def test_local_time_steps_match_the_oracle():
+    """Per-point CFL steps and three RK steps with them (a steady-state iteration), against
+    the oracle's local steps and its RK step with a step per point."""
+    wl = W.vortex_wavy(24, nj=20, nk=16, seed=1)
+    dev = DevBlock(wl, pitched=True)
+    try:
+        c = O.cfg_from_workload(wl)
+        met = O.metrics(c, wl.blocks[0].xyz)
+        dtf = _dt_plane(dev.desc)
+        B.cfd_dt_local([dev.h], [dev.q], 0.5, [dtf])
+        got = B.download_state(dev.desc, dtf)[0, 3:-3, 3:-3, 3:-3]
+        ref_f = O.dt_local(c, met, wl.blocks[0].q, 0.5)
+        assert _rel(got, ref_f[0, 3:-3, 3:-3, 3:-3]) < 1e-14
+        B.cfd_block_set_local_dt(dev.h, dtf)
+        q = wl.blocks[0].q
+        for step in range(3):
+            dev.step(123.0)  # the scalar step is ignored while a step field is set
+            q = O.rk_step_local(c, met, ref_f, q)
+            err = normwise(dev.host(dev.q), q)
+            print(step, err)
+            assert np.all(err < 1e-12), (step, err)
+    finally:
+        dev.close()
+
+
+def test_constant_step_field_equals_the_scalar_step():
+    import torch
+    wl = W.vortex_wavy(20, nj=16, nk=12, seed=2)
+    a = DevBlock(wl)
+    b = DevBlock(wl)
+    try:
+        dt = 2e-3
+        dtf = _dt_plane(b.desc)
+        dtf.fill_(dt)
+        B.cfd_block_set_local_dt(b.h, dtf)
+        a.step(dt)
+        b.step(0.0)
+        assert torch.equal(a.q, b.q)
+        B.cfd_block_set_local_dt(b.h, None)  # back to the scalar step
+        a.step(dt)
+        b.step(dt)
+        assert torch.equal(a.q, b.q)
+    finally:
+        a.close()
+        b.close()
+
+
+def test_batched_steps_with_local_time_steps():
+    """Eight uneven blocks, steps per point set on every block: the batched graph follows
+    the per-block launches (which follow the oracle above)."""
+    import torch
+    single = W.vortex_wavy(24, nj=20, nk=16, amp=0.06)
+    wl = W.split_block(single, [[10, 14], [9, 11], [7, 9]])
+    per = DevMulti(wl)
+    bat = DevMulti(wl)
+    try:
+        fields = []
+        for dev in (per, bat):
+            f = [_dt_plane(d) for d in dev.descs]
+            B.cfd_dt_local(dev.h, dev.q, 0.5, f)
+            for h, t in zip(dev.h, f):
+                B.cfd_block_set_local_dt(h, t)
+            fields.append(f)
+        dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")  # ignored
+        for step in range(2):
+            per.step(0.0)
+            bat.batch_step(dt_dev)
+            torch.cuda.synchronize()
+            for b in range(len(wl.blocks)):
+                err = normwise(bat.host(b), per.host(b))
+                assert np.all(err < 1e-13), (step, b, err)
+    finally:
+        per.close()
+        bat.close()
