@@ -18,7 +18,7 @@ _SO = os.path.join(_HERE, "liboracle.so")
 
 XI, ETA, ZETA, INV, VIS, ALL = 1, 2, 4, 8, 16, 31
 AFWENO_MODIFIED, AFWENO_ORIGINAL = 0, 1
-BC_PERIODIC, BC_INTERFACE, BC_WALL, BC_FARFIELD = 0, 1, 2, 3
+BC_PERIODIC, BC_INTERFACE, BC_WALL, BC_FARFIELD, BC_FARFIELD_CHAR = 0, 1, 2, 3, 4
 
 
 def build(force: bool = True) -> str:
@@ -65,6 +65,10 @@ def lib():
         L.oracle_periodic_wrap.restype = None
         L.oracle_bc_fill.argtypes = [cp, P]
         L.oracle_bc_fill.restype = None
+        L.oracle_bc_fill_met.argtypes = [cp, P, P]
+        L.oracle_bc_fill_met.restype = None
+        L.oracle_char_farfield.argtypes = [P, P, P, C.c_double, P]
+        L.oracle_char_farfield.restype = None
         L.oracle_dt_cfl.argtypes = [cp, P, P, C.c_double]
         L.oracle_dt_cfl.restype = C.c_double
         L.oracle_dt_local.argtypes = [cp, P, P, C.c_double, P]
@@ -167,9 +171,19 @@ def periodic_wrap(c: Cfg, a: np.ndarray) -> np.ndarray:
     return out
 
 
-def bc_fill(c: Cfg, q: np.ndarray) -> np.ndarray:
+def bc_fill(c: Cfg, q: np.ndarray, met: np.ndarray = None) -> np.ndarray:
     out = np.array(q, dtype=np.float64, copy=True)
-    lib().oracle_bc_fill(C.byref(c), _p(out))
+    if met is None:
+        lib().oracle_bc_fill(C.byref(c), _p(out))
+    else:
+        lib().oracle_bc_fill_met(C.byref(c), _p(np.ascontiguousarray(met)), _p(out))
+    return out
+
+
+def char_farfield(qb, n, qf, gamma=1.4) -> np.ndarray:
+    a, nn, f = (np.ascontiguousarray(x, dtype=np.float64) for x in (qb, n, qf))
+    out = np.zeros(5)
+    lib().oracle_char_farfield(_p(a), _p(nn), _p(f), gamma, _p(out))
     return out
 
 

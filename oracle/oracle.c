@@ -419,12 +419,85 @@ void oracle_wall_reset(const oracle_cfg* c, double* Q) {
   }
 }
 
-void oracle_bc_fill(const oracle_cfg* c, double* Q) {
+/* Characteristic far field (reading; the paper names no far-field treatment): locally
+ * one-dimensional Riemann invariants along the outward unit normal n.  From the boundary
+ * node's state b and the far-field state f, with u_n = u.n:
+ *   u_n,b >= c_b: every wave leaves, the ghost state is b;  u_n,b <= -c_b: every wave
+ *   enters, the ghost state is f;  otherwise R+ = u_n,b + 2 c_b/(gamma-1) comes from b and
+ *   R- = u_n,f - 2 c_f/(gamma-1) from f, u_n = (R+ + R-)/2, c = (gamma-1)(R+ - R-)/4, and
+ *   the entropy p/rho^gamma and the tangential velocity come from b if u_n > 0 (outflow),
+ *   else from f.                                                                      */
+void oracle_char_farfield(const double* qb, const double* n, const double* qf, double gamma, double* qg) {
+  prim_t b = primitives(qb, gamma), f = primitives(qf, gamma);
+  double unb = b.u * n[0] + b.v * n[1] + b.w * n[2];
+  double unf = f.u * n[0] + f.v * n[1] + f.w * n[2];
+  double rp, rm, un, c, s, ut[3], rho, p, u[3];
+  int a;
+  if (unb >= b.c) {
+    for (a = 0; a < 5; ++a) qg[a] = qb[a];
+    return;
+  }
+  if (unb <= -b.c) {
+    for (a = 0; a < 5; ++a) qg[a] = qf[a];
+    return;
+  }
+  rp = unb + 2.0 * b.c / (gamma - 1.0);
+  rm = unf - 2.0 * f.c / (gamma - 1.0);
+  un = 0.5 * (rp + rm);
+  c = 0.25 * (gamma - 1.0) * (rp - rm);
+  if (un > 0.0) {
+    s = b.p / pow(b.rho, gamma);
+    ut[0] = b.u - unb * n[0]; ut[1] = b.v - unb * n[1]; ut[2] = b.w - unb * n[2];
+  } else {
+    s = f.p / pow(f.rho, gamma);
+    ut[0] = f.u - unf * n[0]; ut[1] = f.v - unf * n[1]; ut[2] = f.w - unf * n[2];
+  }
+  rho = pow(c * c / (gamma * s), 1.0 / (gamma - 1.0));
+  p = rho * c * c / gamma;
+  for (a = 0; a < 3; ++a) u[a] = ut[a] + un * n[a];
+  qg[0] = rho;
+  qg[1] = rho * u[0];
+  qg[2] = rho * u[1];
+  qg[3] = rho * u[2];
+  qg[4] = p / (gamma - 1.0) + 0.5 * rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+}
+
+void oracle_bc_fill(const oracle_cfg* c, double* Q) { oracle_bc_fill_met(c, NULL, Q); }
+
+void oracle_bc_fill_met(const oracle_cfg* c, const double* met, double* Q) {
   const dims_t sd = state_dims(c);
   int f;
   for (f = 0; f < 6; ++f) {
     int axis, w, out, a, b, m, n;
     int na, nb;
+    if (c->bc[f] == ORACLE_BC_FARFIELD_CHAR) {
+      /* ghost layers 1..3 hold the state of oracle_char_farfield at the boundary node, the
+       * normal being the face-normal direction's hatted metric there, pointing outward */
+      if (!met) continue;
+      face_geom(c, f, &axis, &w, &out);
+      na = npts(c, (axis + 1) % 3);
+      nb = npts(c, (axis + 2) % 3);
+      for (b = 0; b < nb; ++b)
+        for (a = 0; a < na; ++a) {
+          int idx[3];
+          long pw;
+          double qb[5], qg[5], nv[3], mag;
+          idx[(axis + 1) % 3] = a;
+          idx[(axis + 2) % 3] = b;
+          idx[axis] = w;
+          pw = sidx(&sd, idx[0], idx[1], idx[2]);
+          for (n = 0; n < 5; ++n) qb[n] = Q[n * sd.plane + pw];
+          for (n = 0; n < 3; ++n) nv[n] = met[(3 * axis + n) * sd.plane + pw];
+          mag = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+          for (n = 0; n < 3; ++n) nv[n] = out * nv[n] / mag;
+          oracle_char_farfield(qb, nv, c->qinf, c->gamma, qg);
+          for (m = 1; m <= HS; ++m) {
+            idx[axis] = w + out * m;
+            for (n = 0; n < 5; ++n) Q[n * sd.plane + sidx(&sd, idx[0], idx[1], idx[2])] = qg[n];
+          }
+        }
+      continue;
+    }
     if (c->bc[f] != ORACLE_BC_WALL && c->bc[f] != ORACLE_BC_FARFIELD) continue;
     face_geom(c, f, &axis, &w, &out);
     na = npts(c, (axis + 1) % 3);
@@ -470,7 +543,7 @@ static void visc_bc_fill(const oracle_cfg* c, double* V) {
   for (f = 0; f < 6; ++f) {
     int axis, w, out, a, b, m, n;
     int na, nb;
-    if (c->bc[f] != ORACLE_BC_WALL && c->bc[f] != ORACLE_BC_FARFIELD) continue;
+    if (c->bc[f] != ORACLE_BC_WALL && c->bc[f] != ORACLE_BC_FARFIELD && c->bc[f] != ORACLE_BC_FARFIELD_CHAR) continue;
     face_geom(c, f, &axis, &w, &out);
     na = npts(c, (axis + 1) % 3);
     nb = npts(c, (axis + 2) % 3);
@@ -785,7 +858,7 @@ static int rk_stage_dt(const oracle_cfg* c, const double* met, int stage, double
     rk_combine_dt(c, stage, dt, dtf, Qn, Qcur, R, Qout);
     oracle_wall_reset(c, Qout);
     oracle_periodic_wrap(c, Qout, 5);
-    oracle_bc_fill(c, Qout);
+    oracle_bc_fill_met(c, met, Qout);
   }
   free(R);
   return rc;
@@ -1008,7 +1081,7 @@ int oracle_rk_step_multi(const oracle_cfg* cfgs, int nb, const double* const* me
     for (b = 0; b < nb; ++b) oracle_wall_reset(&cfgs[b], out[b]);
     for (b = 0; b < nb; ++b) oracle_periodic_wrap(&cfgs[b], out[b], 5);
     rc = oracle_exchange(cfgs, nb, out, 5, ifc, nifc);
-    for (b = 0; b < nb; ++b) oracle_bc_fill(&cfgs[b], out[b]);
+    for (b = 0; b < nb; ++b) oracle_bc_fill_met(&cfgs[b], met[b], out[b]);
   }
   for (b = 0; b < nb && !rc; ++b) memcpy(Q[b], A[b], (size_t)5 * state_dims(&cfgs[b]).plane * sizeof(double));
   for (b = 0; b < nb; ++b) { free(A[b]); free(Bq[b]); free(R[b]); }

@@ -37,7 +37,8 @@ extern "C" {
 enum { ORACLE_AFWENO_MODIFIED = 0, ORACLE_AFWENO_ORIGINAL = 1 };
 
 /* face boundary kinds, one per face in the order (i-,i+,j-,j+,k-,k+) */
-enum { ORACLE_BC_PERIODIC = 0, ORACLE_BC_INTERFACE = 1, ORACLE_BC_WALL = 2, ORACLE_BC_FARFIELD = 3 };
+enum { ORACLE_BC_PERIODIC = 0, ORACLE_BC_INTERFACE = 1, ORACLE_BC_WALL = 2, ORACLE_BC_FARFIELD = 3,
+       ORACLE_BC_FARFIELD_CHAR = 4 };
 
 typedef struct oracle_cfg {
   int ni, nj, nk;          /* interior points per direction (>= 7)               */
@@ -90,6 +91,13 @@ void oracle_wall_reset(const oracle_cfg* c, double* Q);
 /* Ghost fill of wall / far-field faces of one block (after the halo copies; parity
  * unpinned, as above).                                                                  */
 void oracle_bc_fill(const oracle_cfg* c, double* Q);
+/* The same with the metrics at hand, which the characteristic far field needs for its
+ * normal (faces of kind ORACLE_BC_FARFIELD_CHAR; oracle_bc_fill skips them).            */
+void oracle_bc_fill_met(const oracle_cfg* c, const double* met, double* Q);
+/* Characteristic far-field ghost state qg from the boundary node's state qb, the outward
+ * unit normal n and the far-field state qf (locally one-dimensional Riemann invariants;
+ * parity unpinned by the paper, which names no far-field treatment).                    */
+void oracle_char_farfield(const double* qb, const double* n, const double* qf, double gamma, double* qg);
 
 /* CFL time step: cfl / max over interior of sum_d (|U_d| + c |grad d|).                 */
 double oracle_dt_cfl(const oracle_cfg* c, const double* met, const double* Q, double cfl);

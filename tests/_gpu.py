@@ -189,5 +189,5 @@ def oracle_multi(wl, linear=False):
     qs = [O.wall_reset(c, b.q) for c, b in zip(cfgs, wl.blocks)]
     qs = [O.periodic_wrap(c, q) for c, q in zip(cfgs, qs)]
     O.exchange(cfgs, qs, wl.interfaces)
-    qs = [O.bc_fill(c, q) for c, q in zip(cfgs, qs)]
+    qs = [O.bc_fill(c, q, m) for c, q, m in zip(cfgs, qs, mets)]
     return cfgs, mets, qs

@@ -872,3 +872,65 @@ def test_local_time_steps():
     assert np.min(dtf[0, 3:-3, 3:-3, 3:-3]) == dt
     const = np.full_like(dtf, dt)
     np.testing.assert_array_equal(O.rk_step_local(c, met, const, q), O.rk_step(c, met, dt, q))
+
+
+# ---- characteristic far field -------------------------------------------------------------
+def _prim(q, g=1.4):
+    rho = q[0]
+    u = q[1:4] / rho
+    p = (g - 1) * (q[4] - 0.5 * rho * u @ u)
+    return rho, u, p, np.sqrt(g * p / rho)
+
+
+def test_characteristic_far_field_invariants():
+    """Locally one-dimensional Riemann invariants along n: a far-field state reproduces
+    itself; supersonic outflow keeps the boundary state and supersonic inflow takes the far
+    field; subsonic faces keep R+ = u_n + 2c/(g-1) of the boundary node and R- = u_n -
+    2c/(g-1) of the far field, and take entropy and tangential velocity from the upwind
+    side."""
+    g = 1.4
+    rng = np.random.default_rng(7)
+    qf = W.conserved(np.array(1.0), np.array(0.3), np.array(-0.1), np.array(0.05), np.array(1 / g)).ravel()
+    n = np.array([0.6, 0.0, 0.8])
+    np.testing.assert_allclose(O.char_farfield(qf, n, qf), qf, rtol=1e-14)
+    fast_out = W.conserved(np.array(0.9), np.array(1.8 * 0.6), np.array(0.0), np.array(1.8 * 0.8),
+                           np.array(0.6 / g)).ravel()
+    np.testing.assert_array_equal(O.char_farfield(fast_out, n, qf), fast_out)
+    fast_in = W.conserved(np.array(0.9), np.array(-1.8 * 0.6), np.array(0.0), np.array(-1.8 * 0.8),
+                          np.array(0.6 / g)).ravel()
+    np.testing.assert_array_equal(O.char_farfield(fast_in, n, qf), qf)
+    for _ in range(50):
+        rho = rng.uniform(0.7, 1.3)
+        u = rng.normal(scale=0.3, size=3)
+        p = rng.uniform(0.5, 1.0) / g
+        qb = W.conserved(np.array(rho), np.array(u[0]), np.array(u[1]), np.array(u[2]), np.array(p)).ravel()
+        nn = rng.normal(size=3)
+        nn /= np.linalg.norm(nn)
+        qg = O.char_farfield(qb, nn, qf)
+        rb, ub, pb, cb = _prim(qb)
+        rf, uf, pf, cf = _prim(qf)
+        rg, ug, pg, cg = _prim(qg)
+        if abs(ub @ nn) >= cb:
+            continue
+        assert ug @ nn + 2 * cg / (g - 1) == pytest.approx(ub @ nn + 2 * cb / (g - 1), rel=1e-13)
+        assert ug @ nn - 2 * cg / (g - 1) == pytest.approx(uf @ nn - 2 * cf / (g - 1), rel=1e-13, abs=1e-13)
+        rs, us, ps = (rb, ub, pb) if ug @ nn > 0 else (rf, uf, pf)
+        assert pg / rg ** g == pytest.approx(ps / rs ** g, rel=1e-13)
+        np.testing.assert_allclose(ug - (ug @ nn) * nn, us - (us @ nn) * nn, atol=1e-14)
+
+
+def test_characteristic_far_field_faces_use_the_outward_normal():
+    """On a Cartesian block with characteristic far-field faces at i- and i+, a supersonic
+    stream along +x leaves through i+ (ghosts keep the boundary state) and enters through
+    i- (ghosts take the far field): the normal of each face points out of the block."""
+    ni, nj, nk = 9, 7, 7
+    g = 1.4
+    qinf = (1.0, 0.1, 0.0, 0.0, 1.0 / (g * (g - 1)) + 0.005)
+    bc = (O.BC_FARFIELD_CHAR, O.BC_FARFIELD_CHAR, 0, 0, 0, 0)
+    c = O.make_cfg(ni, nj, nk, viscous=False, bc=bc, qinf=qinf)
+    met = O.metrics(c, W.cartesian_grid(ni, nj, nk, 1.0, 1.0, 1.0))
+    q = W.uniform_state((nk + 6, nj + 6, ni + 6), rho=0.8, u=2.0, p=0.9 / g)
+    out = O.bc_fill(c, q, met)
+    np.testing.assert_array_equal(out[:, :, :, ni + 3:], q[:, :, :, ni + 2:ni + 3].repeat(3, axis=3))
+    np.testing.assert_allclose(out[:, 3:-3, 3:-3, :3], np.broadcast_to(np.array(qinf)[:, None, None, None],
+                                                                       (5, nk, nj, 3)), rtol=0, atol=0)
