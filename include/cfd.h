@@ -49,7 +49,12 @@ enum { CFD_WENO_JS = 0, CFD_WENO_LINEAR = 1 };         /* Eq 15 weights or ideal
  * the values on both sides of the node (modified AFWENO, Figs 10-11), or at the half
  * points, two WENO interpolations per half point (original AFWENO, Fig 9)              */
 enum { CFD_AFWENO_MODIFIED = 0, CFD_AFWENO_ORIGINAL = 1 };
-enum { CFD_BC_PERIODIC = 0, CFD_BC_INTERFACE = 1, CFD_BC_WALL = 2, CFD_BC_FARFIELD = 3 };
+/* face kinds; CFD_BC_FARFIELD holds qinf in the ghosts, CFD_BC_FARFIELD_CHAR fills them
+ * from locally one-dimensional Riemann invariants along the outward normal (boundary
+ * node's outgoing invariant, qinf's incoming one, entropy and tangential velocity from the
+ * upwind side; every wave leaving or entering at supersonic normal speed keeps the
+ * boundary state or qinf).  The paper names no far-field treatment: both are readings. */
+enum { CFD_BC_PERIODIC = 0, CFD_BC_INTERFACE = 1, CFD_BC_WALL = 2, CFD_BC_FARFIELD = 3, CFD_BC_FARFIELD_CHAR = 4 };
 enum { CFD_FIELDS_Q = 0, CFD_FIELDS_VISC = 1 };        /* field sets of an exchange    */
 
 /* direction / term mask of cfd_rhs */

@@ -20,7 +20,7 @@ CFD_ERR_JACOBIAN, CFD_ERR_NONFINITE, CFD_ERR_UNSUPPORTED = -5, -6, -7
 CFD_FP64, CFD_MIXED = 0, 1
 CFD_WENO_JS, CFD_WENO_LINEAR = 0, 1
 CFD_AFWENO_MODIFIED, CFD_AFWENO_ORIGINAL = 0, 1
-CFD_BC_PERIODIC, CFD_BC_INTERFACE, CFD_BC_WALL, CFD_BC_FARFIELD = 0, 1, 2, 3
+CFD_BC_PERIODIC, CFD_BC_INTERFACE, CFD_BC_WALL, CFD_BC_FARFIELD, CFD_BC_FARFIELD_CHAR = 0, 1, 2, 3, 4
 CFD_FIELDS_Q, CFD_FIELDS_VISC = 0, 1
 CFD_DIR_XI, CFD_DIR_ETA, CFD_DIR_ZETA, CFD_TERM_INV, CFD_TERM_VIS, CFD_ALL = 1, 2, 4, 8, 16, 31
 

@@ -155,6 +155,9 @@ struct cfd_block {
 
 namespace {
 
+// faces that get ghost fills (and reflected viscous-flux ghosts)
+bool is_physical(int kind) { return kind == CFD_BC_WALL || kind == CFD_BC_FARFIELD || kind == CFD_BC_FARFIELD_CHAR; }
+
 Phys make_phys(const cfd_params& p) {
   Phys ph;
   ph.gamma = p.gamma;
@@ -335,7 +338,7 @@ int validate_desc(const cfd_block_desc* d) {
   if (p.scheme != CFD_AFWENO_MODIFIED && p.scheme != CFD_AFWENO_ORIGINAL) return fail(CFD_ERR_ARG, "unknown AFWENO scheme");
   if (p.reserved != 0) return fail(CFD_ERR_ARG, "cfd_params.reserved must be 0");
   for (int f = 0; f < 6; ++f)
-    if (d->bc[f] < CFD_BC_PERIODIC || d->bc[f] > CFD_BC_FARFIELD) return fail(CFD_ERR_ARG, "unknown face kind");
+    if (d->bc[f] < CFD_BC_PERIODIC || d->bc[f] > CFD_BC_FARFIELD_CHAR) return fail(CFD_ERR_ARG, "unknown face kind");
   for (int ax = 0; ax < 3; ++ax)
     if ((d->bc[2 * ax] == CFD_BC_PERIODIC) != (d->bc[2 * ax + 1] == CFD_BC_PERIODIC))
       return fail(CFD_ERR_ARG, "periodic faces come in pairs on one axis");
@@ -343,6 +346,12 @@ int validate_desc(const cfd_block_desc* d) {
       d->bc[4] == CFD_BC_WALL || d->bc[5] == CFD_BC_WALL) {
     if (!(p.t_wall > 0.0)) return fail(CFD_ERR_ARG, "wall faces need t_wall > 0");
   }
+  for (int f = 0; f < 6; ++f)
+    if (d->bc[f] == CFD_BC_FARFIELD_CHAR) {
+      const double* q = p.qinf;
+      const double pinf = (p.gamma - 1.0) * (q[4] - 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0]);
+      if (!(q[0] > 0.0) || !(pinf > 0.0)) return fail(CFD_ERR_ARG, "a characteristic far field needs qinf with positive density and pressure");
+    }
   return CFD_OK;
 }
 
@@ -512,7 +521,7 @@ int cfd_block_create(const cfd_block_desc* d, void* hip_stream, cfd_block** out)
     }
   }
   for (int f = 0; f < 6; ++f) {
-    if (d->bc[f] == CFD_BC_WALL || d->bc[f] == CFD_BC_FARFIELD) bs.push_back(make_bc(b->g, 0, f, d->bc[f]));
+    if (is_physical(d->bc[f])) bs.push_back(make_bc(b->g, 0, f, d->bc[f]));
     if (d->bc[f] == CFD_BC_INTERFACE) b->has_interface = true;
   }
   for (auto& s : cs) b->max_local_copy = std::max(b->max_local_copy, s.na * s.nb * kHalo * s.nplanes);
@@ -954,7 +963,7 @@ int batch_create(cfd_block* const* blocks, int nb, cfd_exchange* x, void* hip_st
         vc.push_back(make_copy(B->g, b, 2 * ax + 1, B->g, b, 2 * ax, 4 * ax, 4));
       }
     for (int f = 0; f < 6; ++f)
-      if (B->d.bc[f] == CFD_BC_WALL || B->d.bc[f] == CFD_BC_FARFIELD) vb.push_back(make_bc(B->g, b, f, B->d.bc[f]));
+      if (is_physical(B->d.bc[f])) vb.push_back(make_bc(B->g, b, f, B->d.bc[f]));
   }
   for (auto& c : vc) bt->maxvcopy = std::max(bt->maxvcopy, c.na * c.nb * kHalo * c.nplanes);
   for (auto& c : vb) bt->maxvbc = std::max(bt->maxvbc, c.na * c.nb);
@@ -1069,6 +1078,8 @@ hipError_t enqueue_stage(cfd_batch* bt, int st, double* const* outp) {
   for (int b = 0; b < nb; ++b) {
     ba.t.p[b] = outp[b];
     ba.t.plane[b] = bt->blocks[b]->g.plane;
+    ba.mt.p[b] = bt->blocks[b]->met;
+    ba.mt.plane[b] = bt->blocks[b]->g.plane;
   }
   const cfd_params& P = bt->blocks[0]->d.params;
   ba.gamma = P.gamma;
@@ -1278,7 +1289,7 @@ int cfd_exchange_create(cfd_block* const* blocks, int nb, const cfd_interface* i
         qs.push_back(make_copy(B->g, n, f, B->g, n, f + 1, 0, 5));
         qs.push_back(make_copy(B->g, n, f + 1, B->g, n, f, 0, 5));
       }
-      if (k == CFD_BC_WALL || k == CFD_BC_FARFIELD) bs.push_back(make_bc(B->g, n, f, k));
+      if (is_physical(k)) bs.push_back(make_bc(B->g, n, f, k));
     }
   }
   cfd_exchange* x = new cfd_exchange();
@@ -1324,7 +1335,12 @@ int cfd_halo_exchange(cfd_exchange* x, int field_set, void* const* block_bufs, v
       t.plane[n] = x->blocks[n]->g.plane;
     }
     BcArgs ba;
+    std::memset(&ba, 0, sizeof ba);
     ba.t = t;
+    for (int b = 0; b < nb; ++b) {
+      ba.mt.p[b] = x->blocks[b]->met;
+      ba.mt.plane[b] = x->blocks[b]->g.plane;
+    }
     const cfd_params& P = x->blocks[0]->d.params;
     ba.gamma = P.gamma;
     ba.t_wall = P.t_wall;

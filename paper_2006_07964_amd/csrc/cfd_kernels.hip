@@ -905,6 +905,42 @@ __global__ __launch_bounds__(256) void k_wall_reset(const BcSeg* segs, BcArgs A)
   }
 }
 
+// Characteristic far-field state for the boundary node's conserved state qb, the outward
+// unit normal n and the far-field state qf: Riemann invariants u_n +- 2c/(gamma-1) along n,
+// the outgoing one from qb and the incoming one from qf; entropy p/rho^gamma and the
+// tangential velocity from qb on outflow, from qf on inflow; at supersonic normal speed
+// the whole state of the upwind side.
+__device__ void char_farfield(const double qb[5], const double n[3], const double qf[5], double gamma, double qg[5]) {
+  const double gm1 = gamma - 1.0;
+  const double rb = qb[0], ub = qb[1] / rb, vb = qb[2] / rb, wb = qb[3] / rb;
+  const double pb = gm1 * (qb[4] - 0.5 * rb * (ub * ub + vb * vb + wb * wb));
+  const double cb = sqrt(gamma * pb / rb);
+  const double unb = ub * n[0] + vb * n[1] + wb * n[2];
+  if (unb >= cb || unb <= -cb) {
+    const double* src = unb >= cb ? qb : qf;
+    for (int v = 0; v < 5; ++v) qg[v] = src[v];
+    return;
+  }
+  const double rf = qf[0], uf = qf[1] / rf, vf = qf[2] / rf, wf = qf[3] / rf;
+  const double pf = gm1 * (qf[4] - 0.5 * rf * (uf * uf + vf * vf + wf * wf));
+  const double cf = sqrt(gamma * pf / rf);
+  const double unf = uf * n[0] + vf * n[1] + wf * n[2];
+  const double rplus = unb + 2.0 * cb / gm1, rminus = unf - 2.0 * cf / gm1;
+  const double un = 0.5 * (rplus + rminus), c = 0.25 * gm1 * (rplus - rminus);
+  const bool out = un > 0.0;
+  const double s = out ? pb / pow(rb, gamma) : pf / pow(rf, gamma);
+  const double un_s = out ? unb : unf;
+  const double tx = (out ? ub : uf) - un_s * n[0], ty = (out ? vb : vf) - un_s * n[1], tz = (out ? wb : wf) - un_s * n[2];
+  const double rho = pow(c * c / (gamma * s), 1.0 / gm1);
+  const double p = rho * c * c / gamma;
+  const double u = tx + un * n[0], v = ty + un * n[1], w = tz + un * n[2];
+  qg[0] = rho;
+  qg[1] = rho * u;
+  qg[2] = rho * v;
+  qg[3] = rho * w;
+  qg[4] = p / gm1 + 0.5 * rho * (u * u + v * v + w * w);
+}
+
 __global__ __launch_bounds__(256) void k_ghost_fill(const BcSeg* segs, BcArgs A) {
   const BcSeg S = segs[blockIdx.y];
   double* Q = static_cast<double*>(A.t.p[S.blk]);
@@ -920,6 +956,16 @@ __global__ __launch_bounds__(256) void k_ghost_fill(const BcSeg* segs, BcArgs A)
     const int64_t pg = pw + m * S.sout, pm = pw - m * S.sout;
     if (S.kind == CFD_BC_FARFIELD) {
       for (int v = 0; v < 5; ++v) Q[v * pl + pg] = A.qinf[v];
+    } else if (S.kind == CFD_BC_FARFIELD_CHAR) {
+      // outward unit normal: the face-normal direction's hatted metric at the boundary node
+      const double* M = static_cast<const double*>(A.mt.p[S.blk]);
+      double nv[3] = {M[(3 * S.axis) * pl + pw], M[(3 * S.axis + 1) * pl + pw], M[(3 * S.axis + 2) * pl + pw]};
+      const double scale = (S.sout > 0 ? 1.0 : -1.0) / sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+      for (int d = 0; d < 3; ++d) nv[d] *= scale;
+      double qb[5], qg[5];
+      for (int v = 0; v < 5; ++v) qb[v] = Q[v * pl + pw];
+      char_farfield(qb, nv, A.qinf, A.gamma, qg);
+      for (int v = 0; v < 5; ++v) Q[v * pl + pg] = qg[v];
     } else {
       const double rho = Q[pm], rinv = 1.0 / rho;
       const double u = Q[pl + pm] * rinv, v = Q[2 * pl + pm] * rinv, w = Q[3 * pl + pm] * rinv;

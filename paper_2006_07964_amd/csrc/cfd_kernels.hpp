@@ -112,7 +112,7 @@ template <typename T>
 hipError_t launch_copy(const CopySeg* segs_dev, int nseg, int max_elems, const PtrTable& t, hipStream_t s);
 
 struct BcSeg {
-  int32_t blk, kind;  // kind: CFD_BC_WALL or CFD_BC_FARFIELD
+  int32_t blk, kind;  // kind: CFD_BC_WALL, CFD_BC_FARFIELD or CFD_BC_FARFIELD_CHAR
   int32_t na, nb;
   int64_t wall_off;   // element offset of the boundary node (a=0, b=0)
   int64_t sa, sb;     // tangential strides
@@ -121,6 +121,7 @@ struct BcSeg {
 };
 struct BcArgs {
   PtrTable t;
+  PtrTable mt;  // metric planes of the blocks (characteristic far field)
   double gamma, t_wall;
   double qinf[5];
 };

@@ -29,7 +29,7 @@ HALO = 3
 CHALO = 6
 
 # face kinds, faces ordered (i-, i+, j-, j+, k-, k+)
-BC_PERIODIC, BC_INTERFACE, BC_WALL, BC_FARFIELD = 0, 1, 2, 3
+BC_PERIODIC, BC_INTERFACE, BC_WALL, BC_FARFIELD, BC_FARFIELD_CHAR = 0, 1, 2, 3, 4
 
 
 @dataclasses.dataclass

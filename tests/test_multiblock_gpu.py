@@ -183,3 +183,21 @@ def test_channel_walls_rk_steps():
             assert np.all(err < TOL)
     finally:
         dev.close()
+
+
+def _char_far_field(wl):
+    """The same workload with its far-field faces switched to the characteristic condition."""
+    import dataclasses
+    blocks = [dataclasses.replace(b, bc=tuple(W.BC_FARFIELD_CHAR if k == W.BC_FARFIELD else k for k in b.bc))
+              for b in wl.blocks]
+    return dataclasses.replace(wl, blocks=blocks)
+
+
+@pytest.mark.parametrize("batch", [False, True])
+def test_o_grid_characteristic_far_field(batch):
+    """24 uneven O-grid blocks whose outer faces take the characteristic far field (subsonic
+    inflow upstream, outflow downstream): 3 RK3 steps against the oracle."""
+    wl = _char_far_field(W.o_grid_vortices(sizes=SMALL_OGRID))
+    assert any(W.BC_FARFIELD_CHAR in b.bc for b in wl.blocks)
+    dev, _ = _run_compare(wl, 3, batch=batch)
+    dev.close()
