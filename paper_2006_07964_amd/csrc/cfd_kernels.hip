@@ -679,6 +679,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   __shared__ SweepShared<R, StageT<R, DIR>, TW, TS> sh;
   sweep_tile<DIR, R, TW, TS, NT, SCHEME>(a.c, a.b, xcd_remap(blockIdx.x, gridDim.x), sh.F, sh.Fn, sh.M, sh.V);
 }
+// the original scheme in FP64 holds six stencil points and the half-point basis at once:
+// three waves per SIMD give it the registers that four would make it spill
+template <int DIR, typename R, int TW, int TS, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_sweep_w3(SweepArgs a) {
+  __shared__ SweepShared<R, StageT<R, DIR>, TW, TS> sh;
+  sweep_tile<DIR, R, TW, TS, NT, kOriginal>(a.c, a.b, xcd_remap(blockIdx.x, gridDim.x), sh.F, sh.Fn, sh.M, sh.V);
+}
 
 // Batched blocks: one launch walks a work list covering the tiles of every block
 // (prefix[b] = first tile of block b).  The list is split into eight contiguous ranges, one
@@ -767,6 +774,15 @@ template <typename R, int CFG, int SCHEME>
 hipError_t launch_sweep_scheme(int dir, const SweepArgs& a, int64_t nwg, hipStream_t s) {
   using C = TileCfg<CFG>;
   dim3 grid((unsigned)nwg);
+  if constexpr (SCHEME == kOriginal && sizeof(R) == 8) {
+    if (dir == 0)
+      hipLaunchKernelGGL((k_sweep_w3<0, R, C::TW, C::TS, C::NT>), grid, dim3(C::NT), 0, s, a);
+    else if (dir == 1)
+      hipLaunchKernelGGL((k_sweep_w3<1, R, C::TW, C::TS, C::NT>), grid, dim3(C::NT), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_sweep_w3<2, R, C::TW, C::TS, C::NT>), grid, dim3(C::NT), 0, s, a);
+    return hipGetLastError();
+  }
   if (dir == 0)
     hipLaunchKernelGGL((k_sweep<0, R, C::TW, C::TS, C::NT, SCHEME>), grid, dim3(C::NT), 0, s, a);
   else if (dir == 1)
