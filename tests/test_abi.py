@@ -23,7 +23,7 @@ def declared_functions():
 @pytest.fixture(scope="module")
 def lib():
     if not os.path.exists(B.LIB_PATH):
-        pytest.fail("libcfd.so is not built (run __graft_entry__.build())")
+        pytest.fail("libcfd.so is not built (run python -m paper_2006_07964_amd.build)")
     return B.lib()
 
 

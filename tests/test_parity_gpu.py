@@ -6,8 +6,10 @@ within 1e-13.  Right-hand sides are compared over the whole vector: within 1e-12
 ideal (linear) weights (rounding of O(1) fluxes whose differences are O(1e-2), measured
 ~1e-13), and within 1e-10 with the WENO-JS weights of Eq 15, whose
 normalisation divides by (eps + beta)^2 with eps = 1e-6 and so amplifies last-bit
-differences in beta by up to ~2/eps relative (bound derived in the design doc); one RK stage
-multiplies that by dt*|R|/|Q| ~ 1e-2, well inside the 1e-12 state bar.
+differences in beta by up to ~2/eps relative: a weight moves by ~2e-10 where beta << eps,
+the interpolated value by that times the spread of the sub-stencil values (<~ 0.1), i.e.
+~2e-11 of the flux scale or ~5e-11 of max|R|; one RK stage multiplies that by
+dt*|R|/|Q| ~ 1e-2, well inside the 1e-12 state bar.
 """
 import numpy as np
 import pytest
