@@ -168,7 +168,7 @@ def main():
                     help="sweep tile shapes xi,eta,zeta of the single / per-block forms (library default if unset)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-block path runs all blocks on one device)", file=sys.stderr)
         sys.exit(2)
 

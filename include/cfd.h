@@ -40,7 +40,7 @@ extern "C" {
 #define CFD_ERR_STATE (-4)        /* call out of order (e.g. cfd_rhs before cfd_metrics) */
 #define CFD_ERR_JACOBIAN (-5)     /* some 1/J <= 0 (folded or left-handed grid)           */
 #define CFD_ERR_NONFINITE (-6)    /* NaN or Inf found in a state                         */
-#define CFD_ERR_UNSUPPORTED (-7)  /* valid request this build does not implement         */
+#define CFD_ERR_UNSUPPORTED (-7)  /* valid request the library does not implement        */
 
 /* ---- enumerations ------------------------------------------------------------------ */
 enum { CFD_FP64 = 0, CFD_MIXED = 1 };                  /* arithmetic of the RHS        */
