@@ -897,7 +897,7 @@ template <typename T>
 hipError_t launch_copy(const CopySeg* segs_dev, int nseg, int max_elems, const PtrTable& t, hipStream_t s) {
   if (nseg == 0) return hipSuccess;
   int bx = (max_elems + 255) / 256;
-  if (bx > 4096) bx = 4096;
+  if (bx > 256) bx = 256;  // grid-stride: more workgroups mostly idle on short segments
   if (bx < 1) bx = 1;
   hipLaunchKernelGGL(k_copy<T>, dim3(bx, nseg), dim3(256), 0, s, segs_dev, t);
   return hipGetLastError();
@@ -1020,7 +1020,7 @@ __global__ __launch_bounds__(256) void k_visc_ghost(const BcSeg* segs, PtrTable 
 
 static dim3 bc_grid(int max_elems, int nseg) {
   int bx = (max_elems + 255) / 256;
-  if (bx > 4096) bx = 4096;
+  if (bx > 256) bx = 256;  // grid-stride: more workgroups mostly idle on short segments
   if (bx < 1) bx = 1;
   return dim3(bx, nseg);
 }
