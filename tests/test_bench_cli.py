@@ -1,5 +1,5 @@
-"""bench.py's command line without a GPU: the one-GPU build refuses --gpus N > 1 with a
-message and exit status 2 before touching the device."""
+"""bench.py's command line without a GPU: the benchmark runs on one GPU and refuses
+--gpus N > 1 with a message and exit status 2 before touching the device."""
 import os
 import subprocess
 import sys
