@@ -10,9 +10,11 @@
  *    cfd_last_error() returns a thread-local message.  Nothing throws or aborts.
  *  - Work is enqueued on a HIP stream and is asynchronous unless stated otherwise.
  *    Argument errors are reported synchronously; device faults surface at the next
- *    synchronising call (cfd_sync, cfd_dt_cfl, cfd_check_finite, cfd_metrics).
- *  - Pointers named Q, R, Qn, Qcur, Qout, xyz and the block_bufs of cfd_halo_exchange
- *    are device pointers owned by the caller; the library never frees them.  Metrics,
+ *    synchronising call (cfd_sync, cfd_dt_cfl, cfd_check_finite, cfd_metrics,
+ *    cfd_residual).
+ *  - Pointers named Q, R, Qn, Qcur, Qout, xyz, dt_dev, dt_field, the arrays of
+ *    cfd_residual and the block_bufs of cfd_halo_exchange are device pointers owned by
+ *    the caller; the library never frees them.  Metrics,
  *    scratch, exchange tables and work lists are owned by the library and released by the
  *    matching *_destroy.  Handles are not thread-safe.
  *  - State layout: structure of arrays, plane v of a field holds
