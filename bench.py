@@ -130,6 +130,33 @@ def cpu_baseline(wl, workload_name, scheme=0):
                       f"{el:.2f} s on {O.threads()} OpenMP threads"}
 
 
+def cpu_baseline_one_thread(workload: str, scheme=0):
+    """The oracle on one thread (the paper quotes its speed-up over one CPU core): one full
+    RK3 step of a smaller instance of the same workload (same scheme, same arithmetic per
+    point; the full-size step would take minutes on one core), as updates/s."""
+    import oracle as O
+    from paper_2006_07964_amd import workloads as W
+    small = {"tgv256": lambda: W.taylor_green_wavy(128), "vortex32": lambda: W.vortex_wavy(32),
+             "channel": lambda: W.channel(128, 128, 96)}.get(workload)
+    if small is None:
+        return None
+    wl = small()
+    b = wl.blocks[0]
+    c = O.cfg_from_workload(wl, scheme=scheme)
+    met = O.metrics(c, b.xyz)
+    dt = O.dt_cfl(c, met, b.q, wl.cfl)
+    before = O.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        O.rk_step(c, met, dt, b.q)
+        el = time.perf_counter() - t0
+    finally:
+        O.set_threads(before)
+    return {"value": 3 * b.points / el, "unit": "updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"one RK3 step of the {b.ni}x{b.nj}x{b.nk} instance of the same workload, "
+                      f"{el:.2f} s on 1 thread"}
+
+
 def copy_bandwidth(torch):
     """Achievable HBM bandwidth of a plain device copy (GB/s, read + write bytes)."""
     n = 1 << 27  # 1 GiB of float64
@@ -329,6 +356,9 @@ def main():
     }
     if not args.no_cpu and nb == 1:
         out["cpu_baseline"] = cpu_baseline(wl, wname, scheme)
+        one = cpu_baseline_one_thread(args.workload, scheme)
+        if one is not None:
+            out["cpu_baseline_1thread"] = one
     if bt is not None:
         B.cfd_batch_destroy(bt)
     B.cfd_exchange_destroy(x)

@@ -83,6 +83,8 @@ def lib():
         L.oracle_phys_flux.restype = None
         L.oracle_threads.argtypes = []
         L.oracle_threads.restype = C.c_int
+        L.oracle_set_threads.argtypes = [C.c_int]
+        L.oracle_set_threads.restype = C.c_int
         L.oracle_wall_reset.argtypes = [cp, P]
         L.oracle_wall_reset.restype = None
         L.oracle_viscosity.argtypes = [C.c_double, C.c_double]
@@ -195,6 +197,11 @@ def wall_reset(c: Cfg, q: np.ndarray) -> np.ndarray:
 
 def threads() -> int:
     return int(lib().oracle_threads())
+
+
+def set_threads(n: int) -> int:
+    """Use n OpenMP threads from now on; returns the previous count."""
+    return int(lib().oracle_set_threads(int(n)))
 
 
 def dt_cfl(c: Cfg, met, q, cfl) -> float:

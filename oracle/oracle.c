@@ -1096,3 +1096,13 @@ int oracle_threads(void) {
   return 1;
 #endif
 }
+
+int oracle_set_threads(int n) {
+  int before = oracle_threads();
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+  return before;
+}

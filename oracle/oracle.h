@@ -152,6 +152,9 @@ int oracle_rk_step_multi(const oracle_cfg* cfgs, int nb, const double* const* me
 
 /* Number of OpenMP threads the oracle's parallel loops use.                             */
 int oracle_threads(void);
+/* Use n threads from now on (n > 0); returns the previous count.  Results do not depend
+ * on it: every parallel loop writes disjoint outputs in a fixed order per output.        */
+int oracle_set_threads(int n);
 
 #ifdef __cplusplus
 }

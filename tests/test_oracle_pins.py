@@ -934,3 +934,22 @@ def test_characteristic_far_field_faces_use_the_outward_normal():
     np.testing.assert_array_equal(out[:, :, :, ni + 3:], q[:, :, :, ni + 2:ni + 3].repeat(3, axis=3))
     np.testing.assert_allclose(out[:, 3:-3, 3:-3, :3], np.broadcast_to(np.array(qinf)[:, None, None, None],
                                                                        (5, nk, nj, 3)), rtol=0, atol=0)
+
+
+def test_thread_count_does_not_change_results():
+    """The oracle's parallel loops write disjoint outputs: one thread and all threads give
+    the same bits (so the one-thread timing of the benchmark times the same arithmetic)."""
+    wl = W.vortex_wavy(16, seed=1)
+    c = O.cfg_from_workload(wl)
+    met = O.metrics(c, wl.blocks[0].xyz)
+    q = wl.blocks[0].q
+    many = O.rhs(c, met, q)
+    before = O.set_threads(1)
+    try:
+        assert O.threads() == 1
+        one = O.rhs(c, met, q)
+        dt1 = O.dt_cfl(c, met, q, 0.5)
+    finally:
+        O.set_threads(before)
+    np.testing.assert_array_equal(one, many)
+    assert dt1 == O.dt_cfl(c, met, q, 0.5)
