@@ -190,7 +190,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--scheme", default="modified", choices=["modified", "original"],
                     help="inviscid scheme: modified AFWENO (characteristic space at the nodes) or the "
-                         "original one (at the half points); the batched form runs the modified one")
+                         "original one (at the half points)")
     ap.add_argument("--tiles", default=None,
                     help="sweep tile shapes xi,eta,zeta of the single / per-block forms (library default if unset)")
     args = ap.parse_args()
@@ -214,8 +214,6 @@ def main():
     if form == "single" and nb != 1:
         raise SystemExit("--form single needs a single-block workload")
     scheme = B.CFD_AFWENO_ORIGINAL if args.scheme == "original" else B.CFD_AFWENO_MODIFIED
-    if form == "batched" and scheme != B.CFD_AFWENO_MODIFIED:
-        raise SystemExit("the batched form runs the modified AFWENO scheme only")
     descs, hs, qs, qas, qbs = [], [], [], [], []
     for bi, blk in enumerate(wl.blocks):
         # rows padded to 16 doubles and offset so that interior rows start 128-byte lines

@@ -78,7 +78,7 @@ typedef struct cfd_params {
   int32_t viscous;  /* 1: Navier-Stokes, 0: Euler                                       */
   int32_t weights;  /* CFD_WENO_JS or CFD_WENO_LINEAR                                   */
   int32_t scheme;   /* CFD_AFWENO_MODIFIED (default) or CFD_AFWENO_ORIGINAL; the batched
-                       form (cfd_batch_*) runs the modified scheme only                 */
+                       form runs the original one with one workgroup per tile only      */
   int32_t reserved; /* must be 0                                                         */
   double t_wall;    /* isothermal wall temperature (CFD_BC_WALL faces)                  */
   double qinf[5];   /* conserved far-field state (CFD_BC_FARFIELD faces)                */

@@ -930,8 +930,6 @@ int batch_create(cfd_block* const* blocks, int nb, cfd_exchange* x, void* hip_st
     if (!same_params(blocks[b]->d.params, blocks[0]->d.params))
       return fail(CFD_ERR_ARG, "blocks of a batch share one set of physical parameters");
   }
-  if (blocks[0]->d.params.scheme != CFD_AFWENO_MODIFIED)
-    return fail(CFD_ERR_UNSUPPORTED, "the batched form runs the modified AFWENO scheme only");
   cfd_batch* bt = new cfd_batch();
   bt->blocks.assign(blocks, blocks + nb);
   bt->x = x;
@@ -1123,6 +1121,7 @@ int autotune(cfd_batch* bt, double* const* Qn, double* const* QA, double* const*
     int best_cfg = 0, best_p = 0;
     for (int c = 0; c < kTileCfgs && rc == CFD_OK; ++c)
       for (int p = 0; p < 2 && rc == CFD_OK; ++p) {
+        if (p == 1 && bt->blocks[0]->d.params.scheme == CFD_AFWENO_ORIGINAL) continue;  // not built
         bt->cfg[d] = c;
         bt->persist[d] = p;
         fill_tiles(bt);
@@ -1226,6 +1225,9 @@ int batch_set_tuning(cfd_batch* bt, const int* cfg, const int* persist) {
   if (!bt || !cfg || !persist) return fail(CFD_ERR_ARG, "null argument");
   for (int d = 0; d < 3; ++d)
     if (cfg[d] < 0 || cfg[d] >= kTileCfgs) return fail(CFD_ERR_ARG, "tile configuration out of range");
+  if (bt->blocks[0]->d.params.scheme == CFD_AFWENO_ORIGINAL)
+    for (int d = 0; d < 3; ++d)
+      if (persist[d]) return fail(CFD_ERR_UNSUPPORTED, "the original scheme has no persistent schedule");
   for (int d = 0; d < 3; ++d) {
     bt->cfg[d] = cfg[d];
     bt->persist[d] = persist[d] != 0;

@@ -714,6 +714,23 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   }
 }
 
+// Batched original-scheme sweep (one workgroup per tile).  FP64 gets three waves per SIMD
+// (see k_sweep_w3), FP32 the usual four.
+template <int DIR, typename R, int TW, int TS, int NT>
+__device__ __forceinline__ void batch_orig_tile(const SweepBlock* __restrict__ blocks, const SweepCommon& c,
+                                                const TileList& tl, SweepShared<R, StageT<R, DIR>, TW, TS>& sh) {
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  int blk = 0;
+  while (t >= tl.prefix[blk + 1]) ++blk;
+  sweep_tile<DIR, R, TW, TS, NT, kOriginal>(c, blocks[blk], t - tl.prefix[blk], sh.F, sh.Fn, sh.M, sh.V);
+}
+template <int DIR, typename R, int TW, int TS, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 3 : 4))) void k_sweep_batch_orig(
+    const SweepBlock* __restrict__ blocks, SweepCommon c, TileList tl) {
+  __shared__ SweepShared<R, StageT<R, DIR>, TW, TS> sh;
+  batch_orig_tile<DIR, R, TW, TS, NT>(blocks, c, tl, sh);
+}
+
 // tile configurations (lines across x nodes along the sweep x threads)
 template <int CFG>
 struct TileCfg;
@@ -821,6 +838,18 @@ template <typename R, int CFG, bool P>
 hipError_t launch_sweep_batch_cfg(int dir, const SweepBlock* blocks, const SweepCommon& c, const TileList& tl, int nwg,
                                   hipStream_t s) {
   using C = TileCfg<CFG>;
+  if (c.ph.scheme == kOriginal) {
+    // the original scheme runs one workgroup per tile (the persistent schedule is not built
+    // for it); in FP64 at three waves per SIMD like its single-block kernels
+    if (P) return hipErrorInvalidValue;
+    if (dir == 0)
+      hipLaunchKernelGGL((k_sweep_batch_orig<0, R, C::TW, C::TS, C::NT>), dim3(nwg), dim3(C::NT), 0, s, blocks, c, tl);
+    else if (dir == 1)
+      hipLaunchKernelGGL((k_sweep_batch_orig<1, R, C::TW, C::TS, C::NT>), dim3(nwg), dim3(C::NT), 0, s, blocks, c, tl);
+    else
+      hipLaunchKernelGGL((k_sweep_batch_orig<2, R, C::TW, C::TS, C::NT>), dim3(nwg), dim3(C::NT), 0, s, blocks, c, tl);
+    return hipGetLastError();
+  }
   if (dir == 0)
     hipLaunchKernelGGL((k_sweep_batch<0, R, C::TW, C::TS, C::NT, P>), dim3(nwg), dim3(C::NT), 0, s, blocks, c, tl);
   else if (dir == 1)

@@ -171,16 +171,40 @@ def test_original_decomposition_invariance_rhs():
         dev.close()
 
 
-def test_batched_form_rejects_the_original_scheme():
+@pytest.mark.parametrize("precision", [B.CFD_FP64, B.CFD_MIXED])
+def test_batched_original_scheme_matches_oracle(precision):
+    """The batched graph with the original scheme on eight uneven blocks: three RK steps
+    against the oracle (FP64 to 1e-12; mixed within single-precision error), and the
+    persistent schedule, which it does not have, is refused."""
     import torch
-    _, wl = _periodic_split()
-    dev = DevMulti(wl, **ORIG)
+    single, wl = _periodic_split()
+    dev = DevMulti(wl, precision=precision, **ORIG)
     try:
+        cfgs, mets, qs = oracle_multi_orig(wl)
+        dt = min(O.dt_cfl(c, m, q, 0.5) for c, m, q in zip(cfgs, mets, qs))
+        dt_dev = torch.tensor([dt], dtype=torch.float64, device="cuda")
+        tol = TOL if precision == B.CFD_FP64 else 1e-6
+        for step in range(3):
+            dev.batch_step(dt_dev)
+            qs = O.rk_step_multi(cfgs, mets, dt, qs, wl.interfaces)
+            err = max(np.max(normwise(dev.host(b), qs[b])) for b in range(len(qs)))
+            print(step, err)
+            assert err < tol, (step, err)
+        cfg, persist = B.cfd_batch_tuning(dev.bt)
+        assert not any(persist)
         with pytest.raises(B.CfdError) as e:
-            B.cfd_batch_create(dev.h, dev.x, torch.cuda.current_stream())
+            B.cfd_batch_set_tuning(dev.bt, cfg, [1, 0, 0])
         assert e.value.code == B.CFD_ERR_UNSUPPORTED
     finally:
         dev.close()
+
+
+def oracle_multi_orig(wl):
+    from tests._gpu import oracle_multi
+    cfgs, mets, qs = oracle_multi(wl)
+    for c in cfgs:
+        c.scheme = O.AFWENO_ORIGINAL
+    return cfgs, mets, qs
 
 
 def test_original_and_modified_vortex_accuracy():
