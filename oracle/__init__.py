@@ -18,6 +18,7 @@ _SO = os.path.join(_HERE, "liboracle.so")
 
 XI, ETA, ZETA, INV, VIS, ALL = 1, 2, 4, 8, 16, 31
 AFWENO_MODIFIED, AFWENO_ORIGINAL = 0, 1
+VISC_REFLECT, VISC_ONE_SIDED = 0, 1
 BC_PERIODIC, BC_INTERFACE, BC_WALL, BC_FARFIELD, BC_FARFIELD_CHAR = 0, 1, 2, 3, 4
 
 
@@ -37,7 +38,7 @@ class Cfg(C.Structure):
         ("gamma", C.c_double), ("mach", C.c_double), ("reynolds", C.c_double),
         ("prandtl", C.c_double), ("suth", C.c_double), ("eps", C.c_double),
         ("viscous", C.c_int), ("linear_weights", C.c_int), ("scheme", C.c_int), ("bc", C.c_int * 6),
-        ("t_wall", C.c_double), ("qinf", C.c_double * 5),
+        ("t_wall", C.c_double), ("qinf", C.c_double * 5), ("visc_closure", C.c_int),
     ]
 
 
@@ -104,7 +105,8 @@ def _p(a: np.ndarray):
 
 def make_cfg(ni, nj, nk, gamma=1.4, mach=0.5, reynolds=1000.0, prandtl=0.71,
              suth=110.4 / 288.15, eps=1e-6, viscous=True, linear_weights=False, scheme=0,
-             bc=(0, 0, 0, 0, 0, 0), t_wall=1.0, qinf=(1.0, 0.0, 0.0, 0.0, 1.0 / (1.4 * 0.4))) -> Cfg:
+             bc=(0, 0, 0, 0, 0, 0), t_wall=1.0, qinf=(1.0, 0.0, 0.0, 0.0, 1.0 / (1.4 * 0.4)),
+             visc_closure=VISC_REFLECT) -> Cfg:
     c = Cfg()
     c.ni, c.nj, c.nk = ni, nj, nk
     c.gamma, c.mach, c.reynolds, c.prandtl, c.suth, c.eps = gamma, mach, reynolds, prandtl, suth, eps
@@ -116,13 +118,15 @@ def make_cfg(ni, nj, nk, gamma=1.4, mach=0.5, reynolds=1000.0, prandtl=0.71,
     c.t_wall = t_wall
     for n in range(5):
         c.qinf[n] = float(qinf[n])
+    c.visc_closure = int(visc_closure)
     return c
 
 
 def cfg_from_workload(wl, block=0, **over) -> Cfg:
     b = wl.blocks[block]
     kw = dict(gamma=wl.gamma, mach=wl.mach, reynolds=wl.reynolds, prandtl=wl.prandtl, suth=wl.suth,
-              eps=wl.eps, viscous=wl.viscous, bc=b.bc, t_wall=wl.t_wall, qinf=wl.qinf)
+              eps=wl.eps, viscous=wl.viscous, bc=b.bc, t_wall=wl.t_wall, qinf=wl.qinf,
+              visc_closure=getattr(wl, "visc_closure", VISC_REFLECT))
     kw.update(over)
     return make_cfg(b.ni, b.nj, b.nk, **kw)
 

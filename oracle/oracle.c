@@ -64,6 +64,49 @@ static double d6(const double* g) {
 }
 
 /* ------------------------------------------------------------------------------------ */
+/* One-sided closures of the viscous derivatives (Sec. 4.5.2 mentions one-sided         */
+/* differences near block boundaries but gives no coefficients).                        */
+/* Reading: with visc_closure = ORACLE_VISC_ONE_SIDED, along direction d a node within  */
+/* three nodes of a wall or far-field face of d takes the derivative of the degree-6    */
+/* interpolating polynomial through the seven nodes nearest that face (the boundary     */
+/* node and six inside), for the velocity and temperature gradients and for the         */
+/* derivative of the direction-d viscous flux; the viscous terms then read no ghost     */
+/* value across such a face.  Row r of OS6 gives the weights of nodes 0..6 for the      */
+/* derivative at node r (unit spacing); these are the Lagrange derivative weights,      */
+/* written as exact fractions.  A node r away from the high face uses the mirror image  */
+/* with the opposite sign.                                                              */
+/* ------------------------------------------------------------------------------------ */
+static const double OS6[3][7] = {
+    {-49.0 / 20.0, 6.0, -15.0 / 2.0, 20.0 / 3.0, -15.0 / 4.0, 6.0 / 5.0, -1.0 / 6.0},
+    {-1.0 / 6.0, -77.0 / 60.0, 5.0 / 2.0, -5.0 / 3.0, 5.0 / 6.0, -1.0 / 4.0, 1.0 / 30.0},
+    {1.0 / 30.0, -2.0 / 5.0, -7.0 / 12.0, 4.0 / 3.0, -1.0 / 2.0, 2.0 / 15.0, -1.0 / 60.0}};
+
+static int physical_face(int kind) {
+  return kind == ORACLE_BC_WALL || kind == ORACLE_BC_FARFIELD || kind == ORACLE_BC_FARFIELD_CHAR;
+}
+
+/* Viscous first derivative along dir at interior index node of a line: returns 0 for the
+ * central d6 over nodes node-3..node+3, else 1 with w[0..6] the weights of the seven nodes
+ * first..first+6 of a one-sided closure.                                                */
+static int one_sided(const oracle_cfg* c, int dir, int node, int* first, double* w) {
+  const int n = npts(c, dir);
+  int m;
+  if (c->visc_closure != ORACLE_VISC_ONE_SIDED) return 0;
+  if (node < 3 && physical_face(c->bc[2 * dir])) {
+    *first = 0;
+    for (m = 0; m < 7; ++m) w[m] = OS6[node][m];
+    return 1;
+  }
+  if (node > n - 4 && physical_face(c->bc[2 * dir + 1])) {
+    const int r = n - 1 - node;
+    *first = n - 7;
+    for (m = 0; m < 7; ++m) w[m] = -OS6[r][6 - m];
+    return 1;
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------------------ */
 /* Eq 7 / Eq 8: conservative metrics and Jacobian                                       */
 /* ------------------------------------------------------------------------------------ */
 /* derivative along dir of coordinate array X at (i,j,k) */
@@ -313,18 +356,30 @@ static void viscous_fluxes(const oracle_cfg* c, const double* met, const double*
         prim_t s0;
         int dir, n, a, b;
         for (dir = 0; dir < 3; ++dir) {
-          int di, dj, dk, st;
-          double line[4][7];
+          int di, dj, dk, st, first, os;
+          double line[4][7], w[7];
+          const int node = dir == 0 ? i : dir == 1 ? j : k;
           unit(dir, &di, &dj, &dk);
-          for (st = -3; st <= 3; ++st) {
+          /* the seven nodes of the stencil: node-3..node+3, or a one-sided window */
+          os = one_sided(c, dir, node, &first, w);
+          if (!os) first = node - 3;
+          for (st = 0; st < 7; ++st) {
             double qv[5];
             prim_t s;
-            long pp = sidx(&sd, i + st * di, j + st * dj, k + st * dk);
+            const int off = first + st - node;
+            long pp = sidx(&sd, i + off * di, j + off * dj, k + off * dk);
             for (n = 0; n < 5; ++n) qv[n] = Q[n * sd.plane + pp];
             s = primitives(qv, c->gamma);
-            line[0][st + 3] = s.u; line[1][st + 3] = s.v; line[2][st + 3] = s.w; line[3][st + 3] = s.T;
+            line[0][st] = s.u; line[1][st] = s.v; line[2][st] = s.w; line[3][st] = s.T;
           }
-          for (n = 0; n < 4; ++n) g[n][dir] = d6(line[n]);
+          for (n = 0; n < 4; ++n) {
+            if (os) {
+              g[n][dir] = 0.0;
+              for (st = 0; st < 7; ++st) g[n][dir] += w[st] * line[n][st];
+            } else {
+              g[n][dir] = d6(line[n]);
+            }
+          }
         }
         Jp = met[9 * sd.plane + p];
         for (a = 0; a < 3; ++a)
@@ -393,7 +448,9 @@ static void face_geom(const oracle_cfg* c, int f, int* axis, int* wall_idx, int*
  * is part of the interior.  Isothermal no-slip wall: after every stage the wall node gets
  * zero velocity and T = T_w at its own density (oracle_wall_reset, before any halo copy);
  * ghost m mirrors interior node m with odd velocity, the same pressure and
- * T_g = 2 T_w - T_m.  Far field: ghosts hold qinf (oracle_bc_fill).                      */
+ * T_g = max(2 T_w - T_m, T_w / 2).  Far field: ghosts hold qinf (oracle_bc_fill).
+ * Pinned by closed forms of Eq 1 next to a wall: the right-hand side of a shear mode and
+ * of a conduction mode between isothermal walls, and the decay rate of the shear mode.  */
 void oracle_wall_reset(const oracle_cfg* c, double* Q) {
   const dims_t sd = state_dims(c);
   int f;
@@ -521,7 +578,10 @@ void oracle_bc_fill_met(const oracle_cfg* c, const double* met, double* Q) {
             double Tg, rg;
             for (n = 0; n < 5; ++n) qm[n] = Q[n * sd.plane + pm];
             s = primitives(qm, c->gamma);
+            /* reflection of T - T_w; floored at T_w / 2 so that the ghost density stays
+             * positive when the mirror node is 1.5 times hotter than the wall or more */
             Tg = 2.0 * c->t_wall - s.T;
+            if (Tg < 0.5 * c->t_wall) Tg = 0.5 * c->t_wall;
             rg = c->gamma * s.p / Tg;
             Q[pg] = rg;
             Q[1 * sd.plane + pg] = -rg * s.u;
@@ -536,14 +596,17 @@ void oracle_bc_fill_met(const oracle_cfg* c, const double* met, double* Q) {
 
 /* Reading: at a wall or far-field face the ghost values of the viscous flux are the
  * odd reflection about the boundary node, F(w+out*m) = 2 F(w) - F(w-out*m), which keeps
- * linear flux profiles exact.                                                          */
+ * linear flux profiles exact (the default closure; with ORACLE_VISC_ONE_SIDED the
+ * viscous terms use no ghost value there).                                            */
 static void visc_bc_fill(const oracle_cfg* c, double* V) {
   const dims_t sd = state_dims(c);
   int f;
   for (f = 0; f < 6; ++f) {
     int axis, w, out, a, b, m, n;
     int na, nb;
-    if (c->bc[f] != ORACLE_BC_WALL && c->bc[f] != ORACLE_BC_FARFIELD && c->bc[f] != ORACLE_BC_FARFIELD_CHAR) continue;
+    if (!physical_face(c->bc[f])) continue;
+    /* one-sided closures read no viscous ghost value across the face */
+    if (c->visc_closure == ORACLE_VISC_ONE_SIDED) continue;
     face_geom(c, f, &axis, &w, &out);
     na = npts(c, (axis + 1) % 3);
     nb = npts(c, (axis + 2) % 3);
@@ -770,13 +833,22 @@ static void rhs_core(const oracle_cfg* c, const double* met, const double* Q, co
         for (v = 0; v < 5; ++v) Rt[v * sd.plane + pp] -= D[node][v];
         /* viscous part: d6 along the line of the direction-dir viscous flux */
         if ((mask & ORACLE_VIS) && c->viscous) {
+          double w[7];
+          int first;
+          const int os = one_sided(c, dir, node, &first, w);
+          if (!os) first = node - 3;
           for (v = 1; v < 5; ++v) {
-            double g[7];
+            double g[7], sum = 0.0;
             int st;
-            for (st = -3; st <= 3; ++st)
-              g[st + 3] = V[(4 * dir + v - 1) * sd.plane +
-                            sidx(&sd, base[0] + (node + st) * di, base[1] + (node + st) * dj, base[2] + (node + st) * dk)];
-            Rt[v * sd.plane + pp] += d6(g);
+            for (st = 0; st < 7; ++st)
+              g[st] = V[(4 * dir + v - 1) * sd.plane +
+                        sidx(&sd, base[0] + (first + st) * di, base[1] + (first + st) * dj, base[2] + (first + st) * dk)];
+            if (os) {
+              for (st = 0; st < 7; ++st) sum += w[st] * g[st];
+            } else {
+              sum = d6(g);
+            }
+            Rt[v * sd.plane + pp] += sum;
           }
         }
       }
@@ -797,6 +869,7 @@ static void rhs_core(const oracle_cfg* c, const double* met, const double* Q, co
 static int check_cfg(const oracle_cfg* c) {
   if (c->ni < 7 || c->nj < 7 || c->nk < 7) return -1;
   if (c->scheme != ORACLE_AFWENO_MODIFIED && c->scheme != ORACLE_AFWENO_ORIGINAL) return -1;
+  if (c->visc_closure != ORACLE_VISC_REFLECT && c->visc_closure != ORACLE_VISC_ONE_SIDED) return -1;
   return 0;
 }
 
@@ -900,8 +973,9 @@ int oracle_rk_step_local(const oracle_cfg* c, const double* met, const double* d
 double oracle_dt_cfl(const oracle_cfg* c, const double* met, const double* Q, double cfl) {
   const dims_t sd = state_dims(c);
   double smax = 0.0;
+  int bad = 0;
   int k;
-#pragma omp parallel for reduction(max : smax) schedule(static)
+#pragma omp parallel for reduction(max : smax) reduction(| : bad) schedule(static)
   for (k = 0; k < c->nk; ++k) {
     int i, j, d, n;
     for (j = 0; j < c->nj; ++j)
@@ -917,10 +991,11 @@ double oracle_dt_cfl(const oracle_cfg* c, const double* met, const double* Q, do
           double mz = Jp * met[(3 * d + 2) * sd.plane + p];
           sum += fabs(mx * s.u + my * s.v + mz * s.w) + s.c * sqrt(mx * mx + my * my + mz * mz);
         }
+        if (!(sum <= 1.7976931348623157e308)) bad = 1;  /* NaN or infinite */
         if (sum > smax) smax = sum;
       }
   }
-  return cfl / smax;
+  return bad ? NAN : cfl / smax;
 }
 
 /* Local time steps (steady runs): the same spectral radius, point by point.  Reading: the

@@ -18,11 +18,14 @@
  * Pins: every function is checked by the CPU tests against closed forms, invariants,
  * exact solutions or brute force, except where the paper fixes nothing to check against
  * ("parity unpinned"): the Sutherland constant of oracle_viscosity (only mu(1) = 1 is
- * pinned), the wall and far-field treatment of oracle_wall_reset / oracle_bc_fill (only
- * the symmetry of a symmetric channel is checked), the choice of eigenvector basis in
- * oracle_eigvec beyond L R = I and L A R = diag(lambda), and, for the original AFWENO
- * scheme, the arithmetic mean as the state of the half-point characteristic space beyond
- * its mirror symmetry (any symmetric average of the two nodes passes the pins).
+ * pinned), the choice of eigenvector basis in oracle_eigvec beyond L R = I and
+ * L A R = diag(lambda), and, for the original AFWENO scheme, the arithmetic mean as the
+ * state of the half-point characteristic space beyond its mirror symmetry (any symmetric
+ * average of the two nodes passes the pins).  The isothermal no-slip wall (ghost
+ * velocity, ghost temperature, viscous-flux reflection) and the one-sided viscous
+ * closures are pinned by closed forms of Eq 1 next to a wall (shear and conduction modes,
+ * the shear mode's decay rate, exactness on degree-6 profiles); the far-field ghost
+ * states by their Riemann invariants.
  */
 #ifndef CFD_ORACLE_H
 #define CFD_ORACLE_H
@@ -53,7 +56,15 @@ typedef struct oracle_cfg {
   int bc[6];               /* face kinds (ORACLE_BC_*)                            */
   double t_wall;           /* isothermal wall temperature                         */
   double qinf[5];          /* far-field conserved state                           */
+  int visc_closure;        /* viscous terms next to wall / far-field faces:       */
+                           /* ORACLE_VISC_REFLECT or ORACLE_VISC_ONE_SIDED         */
 } oracle_cfg;
+
+/* Viscous derivatives at the three nodes next to a wall or far-field face (Sec. 4.5.2
+ * names one-sided differences near block boundaries without giving them): central
+ * differences over reflected ghosts (the default), or one-sided seven-point differences
+ * over the boundary node and six nodes inside, exact on polynomials of degree six.      */
+enum { ORACLE_VISC_REFLECT = 0, ORACLE_VISC_ONE_SIDED = 1 };
 
 /* direction / term mask for oracle_rhs */
 #define ORACLE_XI   1u
@@ -85,11 +96,11 @@ int oracle_rk_step(const oracle_cfg* c, const double* met, double dt, double* Q)
 /* Fill the halo of nvar planes of a single periodic block by periodic wrap.             */
 void oracle_periodic_wrap(const oracle_cfg* c, double* A, int nvar);
 
-/* Wall nodes of one block: zero velocity, T = t_wall at their own density
- * (parity unpinned: the paper does not specify its boundary conditions).               */
+/* Wall nodes of one block: zero velocity, T = t_wall at their own density (a reading:
+ * the paper does not specify its boundary conditions; pinned by the wall-mode tests).  */
 void oracle_wall_reset(const oracle_cfg* c, double* Q);
-/* Ghost fill of wall / far-field faces of one block (after the halo copies; parity
- * unpinned, as above).                                                                  */
+/* Ghost fill of wall / far-field faces of one block (after the halo copies; a reading,
+ * pinned as above).                                                                     */
 void oracle_bc_fill(const oracle_cfg* c, double* Q);
 /* The same with the metrics at hand, which the characteristic far field needs for its
  * normal (faces of kind ORACLE_BC_FARFIELD_CHAR; oracle_bc_fill skips them).            */
@@ -99,7 +110,8 @@ void oracle_bc_fill_met(const oracle_cfg* c, const double* met, double* Q);
  * parity unpinned by the paper, which names no far-field treatment).                    */
 void oracle_char_farfield(const double* qb, const double* n, const double* qf, double gamma, double* qg);
 
-/* CFL time step: cfl / max over interior of sum_d (|U_d| + c |grad d|).                 */
+/* CFL time step: cfl / max over interior of sum_d (|U_d| + c |grad d|); NaN when the
+ * spectral radius of some point is not finite (a non-finite state).                     */
 double oracle_dt_cfl(const oracle_cfg* c, const double* met, const double* Q, double cfl);
 /* Local time steps for steady runs: dt_field (one plane, state layout) receives
  * cfl / sum_d (|U_d| + c |grad d|) at every interior point; halo entries untouched.       */

@@ -499,6 +499,18 @@ def test_dt_cfl_closed_form():
     assert dt == pytest.approx(ref, rel=1e-13)
 
 
+def test_dt_cfl_reports_a_non_finite_state():
+    """One non-finite interior value makes the step NaN (a maximum that skipped it would
+    return a finite step for a state that has blown up)."""
+    ni, nj, nk = 8, 10, 12
+    c = O.make_cfg(ni, nj, nk)
+    met = O.metrics(c, W.cartesian_grid(ni, nj, nk))
+    for bad in (np.nan, np.inf):
+        q = W.uniform_state((nk + 6, nj + 6, ni + 6), u=0.3)
+        q[4, 3 + 5, 3 + 4, 3 + 2] = bad
+        assert np.isnan(O.dt_cfl(c, met, q, 0.5))
+
+
 def test_rk3_amplification_polynomial():
     """Eq 20 applied to a linear operator multiplies each mode by 1 + z + z^2/2 + z^3/6."""
     stages = G.eq20()
