@@ -5,44 +5,62 @@ A step is one full TVD-RK3 step (three fused RHS + stage evaluations and the hal
 exchanges after each stage) over the whole grid.  The metric is grid-point RK3 stage
 updates per second: interior points x 3 stages x steps / wall time of the timed steps.
 
-Default workload: 256^3 periodic Taylor-Green vortex, Mach 0.1, Re 1600, on the 2 pi cube
-with a sinusoidal grid perturbation of amplitude 0.05 and seeded velocity noise, FP64.
+Default workload (the largest single-GPU configuration, the one the roofline is measured
+on): a 512 x 512 x 384 channel block, tanh wall stretching 2.5, bump 0.02, Mach 0.3,
+Re 16200, isothermal walls, periodic in x and z, FP64, single-block launches.  The same
+run adds side legs on the other throughput configurations: the channel in mixed precision,
+the 256^3 Taylor-Green case in mixed precision, and the 24-block O-grid in per-block FP64
+and batched mixed precision (the ratio of those two is the batched/mixed speed-up).
+
+The headline steps are timed with the library's per-kernel event timing switched off; a
+second pass of the same steps, with the HIP events on the kernels' own stream, gives each
+kernel's mean launch time, from which the dominant kernel's algorithmic bandwidth is
+formed (`roofline`).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-                       [--workload tgv256|vortex32|ogrid24|channel]
-                       [--precision fp64|mixed] [--form single|perblock|batched] [--no-cpu]
+                       [--workload channel|tgv256|vortex32|ogrid24]
+                       [--precision fp64|mixed] [--form single|perblock|batched]
+                       [--no-cpu] [--no-legs]
 Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
-import re
 import json
 import os
+import re
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# algorithmic HBM bytes per interior point of each kernel (compulsory reads and writes)
-# FP64 path: Q 40 B, a metric component or J 8 B, a viscous-flux component 8 B
-# compulsory HBM bytes per interior point of each kernel, by the role of a sweep in the
-# direction order (first: no partial sum in; last: the RK combination)
+# Algorithmic (compulsory) HBM bytes per interior point of each kernel of the pencil
+# design, by the role of a sweep in the direction order (first: no partial sum in; last:
+# the RK combination).  FP64 path: Q 40 B, a metric component or J 8 B, a viscous-flux
+# component 8 B.  The RK sweep reads Q^n at stages 1 and 2 only (stage 0 has Q^n = Q), so
+# per launch it moves Q^n on two of three stages.
+QN_AVG = 40.0 * 2.0 / 3.0
 ALG_BYTES_FP64 = {
-    "visc_prepass": 40 + 80 + 96,          # Q, 9 metrics + J, 12 flux planes
-    "first": 40 + 24 + 32 + 40,            # Q, 3 metrics, 4 flux planes, partial sum out
-    "middle": 40 + 24 + 32 + 40 + 40,      # + partial sum in
-    "last_rk": 40 + 24 + 32 + 40 + 8 + 40 + 40,  # Q, metrics, fluxes, partial in, J, Qn, Qout
+    "visc_prepass": 40 + 80 + 96,               # Q, 9 metrics + J, 12 flux planes
+    "first": 40 + 24 + 32 + 40,                 # Q, 3 metrics, 4 flux planes, partial sum out
+    "middle": 40 + 24 + 32 + 40 + 40,           # + partial sum in
+    "last_rk": 40 + 24 + 32 + 40 + 8 + QN_AVG + 40,  # Q, metrics, fluxes, partial in, J, Qn, Qout
 }
 ALG_BYTES_MIXED = {
-    "visc_prepass": 40 + 40 + 48,          # Q, the FP32 copy of the metrics, FP32 flux planes
+    "visc_prepass": 40 + 40 + 48,               # Q, the FP32 copy of the metrics, FP32 flux planes
     "first": 40 + 24 + 16 + 20,
     "middle": 40 + 24 + 16 + 20 + 20,
-    "last_rk": 40 + 24 + 16 + 20 + 8 + 40 + 40,
+    "last_rk": 40 + 24 + 16 + 20 + 8 + QN_AVG + 40,
 }
+# Bytes an update must move in either precision whatever the kernel design: read Q_cur,
+# the 9 metrics and J, write Q_out, and read Q^n on two of the three stages.
+COMPULSORY_B = 40 + 80 + 40 + QN_AVG
 DIR_NAMES = ("xi", "eta", "zeta")
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+VALU_PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}  # vector FP64; vector FP32 for the FP32 kernels
 
 
 def kernel_bytes(table, order):
@@ -52,9 +70,6 @@ def kernel_bytes(table, order):
     out[f"sweep_{DIR_NAMES[order[1]]}"] = table["middle"]
     out[f"sweep_{DIR_NAMES[order[2]]}_rk"] = table["last_rk"]
     return out
-
-
-HBM_PEAK_GBS = 8000.0
 
 
 def _code_only(text: str) -> str:
@@ -75,27 +90,29 @@ def source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str, workload: str, precision: str):
-    """Measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a copy
-    kernel's reading) if they were taken on the current kernel sources, else None."""
+def load_counters(kernel: str, workload: str, precision: str):
+    """Counter figures of a kernel (rocprofv3: HBM bytes per launch from FETCH_SIZE +
+    WRITE_SIZE scaled by a copy kernel's reading, VALU FLOP per launch) if they were taken
+    on the current kernel sources, else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
-        data = json.load(open(path))
+        with open(path, encoding="utf-8") as fh:
+            data = json.load(fh)
     except ValueError:
         return None
     ent = data.get(f"{workload}/{precision}/{kernel}")
     if not ent or ent.get("source_sha") != source_sha():
         return None
-    return ent.get("bytes_per_launch")
+    return ent
 
 
 WORKLOADS = {
+    "channel": "channel_512x512x384_tanh2.5_bump0.02_mach0.3_re16200",
     "tgv256": "taylor_green_256^3_wavy_2pi_mach0.1_re1600",
     "vortex32": "isentropic_vortex_32^3_wavy_unit_mach0.5_re1000",
     "ogrid24": "o_grid_24_uneven_blocks_mach0.2_vortices_wall_farfield",
-    "channel": "channel_512x512x384_tanh2.5_bump0.02_mach0.3",
 }
 
 
@@ -113,48 +130,63 @@ def build_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(wl, workload_name, scheme=0):
-    """The oracle, as it stands, timed on the host: one full RK3 step (three stages) of the
-    same workload with the same inviscid scheme."""
-    import oracle as O
-    b = wl.blocks[0]
-    c = O.cfg_from_workload(wl, scheme=scheme)
-    met = O.metrics(c, b.xyz)
-    dt = O.dt_cfl(c, met, b.q, wl.cfl)
-    t0 = time.perf_counter()
-    O.rk_step(c, met, dt, b.q)
-    el = time.perf_counter() - t0
-    return {"value": 3 * b.points / el, "unit": "updates/s", "cores": O.threads(),
-            "kind": "oracle",
-            "sample": f"one RK3 step (3 stages: RHS + update + halo wrap) of the full {workload_name} grid, "
-                      f"{el:.2f} s on {O.threads()} OpenMP threads"}
-
-
-def cpu_baseline_one_thread(workload: str, scheme=0):
-    """The oracle on one thread (the paper quotes its speed-up over one CPU core): one full
-    RK3 step of a smaller instance of the same workload (same scheme, same arithmetic per
-    point; the full-size step would take minutes on one core), as updates/s."""
-    import oracle as O
-    from paper_2006_07964_amd import workloads as W
-    small = {"tgv256": lambda: W.taylor_green_wavy(128), "vortex32": lambda: W.vortex_wavy(32),
-             "channel": lambda: W.channel(128, 128, 96)}.get(workload)
-    if small is None:
-        return None
-    wl = small()
-    b = wl.blocks[0]
-    c = O.cfg_from_workload(wl, scheme=scheme)
-    met = O.metrics(c, b.xyz)
-    dt = O.dt_cfl(c, met, b.q, wl.cfl)
-    before = O.set_threads(1)
+# ---- CPU baseline: the oracle as it stands, on a bounded sample of the workload --------
+def cpu_info():
+    model = None
     try:
+        with open("/proc/cpuinfo", encoding="utf-8") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "cpu_count": os.cpu_count(), "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+SAMPLES = {  # (all host threads, one thread) instances of each workload, same per-point work
+    "channel": ((256, 256, 96), (128, 128, 32)),
+    "tgv256": ((128, 128, 128), (64, 64, 64)),
+    "vortex32": ((32, 32, 32), (32, 32, 32)),
+}
+
+
+def _sample_workload(name, shape):
+    from paper_2006_07964_amd import workloads as W
+    if name == "channel":
+        return W.channel(*shape)
+    if name == "tgv256":
+        return W.taylor_green_wavy(shape[0])
+    return W.vortex_wavy(shape[0])
+
+
+def cpu_baseline(workload: str, scheme: int, threads: int = 0):
+    """One full RK3 step (three stages with halo fills) of a smaller instance of the same
+    workload: same scheme and boundary conditions, same arithmetic per point.  threads = 0:
+    every OpenMP thread the oracle has; 1: one thread (the paper quotes one CPU core)."""
+    import oracle as O
+    if workload not in SAMPLES:
+        return None
+    shape = SAMPLES[workload][0 if threads == 0 else 1]
+    wl = _sample_workload(workload, shape)
+    b = wl.blocks[0]
+    c = O.cfg_from_workload(wl, scheme=scheme)
+    met = O.metrics(c, b.xyz)
+    dt = O.dt_cfl(c, met, b.q, wl.cfl)
+    before = O.set_threads(threads) if threads else None
+    try:
+        used = O.threads()
         t0 = time.perf_counter()
         O.rk_step(c, met, dt, b.q)
         el = time.perf_counter() - t0
     finally:
-        O.set_threads(before)
-    return {"value": 3 * b.points / el, "unit": "updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"one RK3 step of the {b.ni}x{b.nj}x{b.nk} instance of the same workload, "
-                      f"{el:.2f} s on 1 thread"}
+        if before is not None:
+            O.set_threads(before)
+    out = {"value": 3 * b.points / el, "unit": "updates/s", "cores": used, "kind": "oracle",
+           "sample": f"one RK3 step (3 stages: RHS, update, halo fill) of the {b.ni}x{b.nj}x{b.nk} instance "
+                     f"of the {workload} workload, {el:.2f} s on {used} OpenMP thread(s)"}
+    out.update(cpu_info())
+    return out
 
 
 def copy_bandwidth(torch):
@@ -178,53 +210,27 @@ def copy_bandwidth(torch):
     return 2 * n * 8 / (ms * 1e-3) / 1e9
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="tgv256")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--form", default=None, choices=["single", "perblock", "batched"],
-                    help="single-block calls, per-block launches, or the batched graph form")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    ap.add_argument("--scheme", default="modified", choices=["modified", "original"],
-                    help="inviscid scheme: modified AFWENO (characteristic space at the nodes) or the "
-                         "original one (at the half points)")
-    ap.add_argument("--tiles", default=None,
-                    help="sweep tile shapes xi,eta,zeta of the single / per-block forms (library default if unset)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-block path runs all blocks on one device)", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    from paper_2006_07964_amd import binding as B
-
-    if not torch.cuda.is_available():
-        raise SystemExit("bench.py needs a GPU")
-    torch.cuda.set_device(0)
-    B.lib()
-    wl, wname = build_workload(args.workload)
-    prec = B.CFD_FP64 if args.precision == "fp64" else B.CFD_MIXED
+# ---- one measured configuration ------------------------------------------------------
+def run_leg(torch, B, wl, wname, precision, form, steps, warmup, scheme=0, tiles=None, profile_steps=0):
+    """Set the workload up on the device, run `warmup` untimed steps and `steps` timed ones
+    (library event timing off), then, if profile_steps > 0, that many more with the
+    per-kernel HIP events on.  Returns a dict; frees every device buffer it made."""
+    prec = B.CFD_FP64 if precision == "fp64" else B.CFD_MIXED
     stream = torch.cuda.current_stream()
     nb = len(wl.blocks)
-    form = args.form or ("single" if nb == 1 else "perblock")
+    form = form or ("single" if nb == 1 else "perblock")
     if form == "single" and nb != 1:
         raise SystemExit("--form single needs a single-block workload")
-    scheme = B.CFD_AFWENO_ORIGINAL if args.scheme == "original" else B.CFD_AFWENO_MODIFIED
-    descs, hs, qs, qas, qbs = [], [], [], [], []
+    hs, qs, qas, qbs = [], [], [], []
     for bi, blk in enumerate(wl.blocks):
         # rows padded to 16 doubles and offset so that interior rows start 128-byte lines
         desc = B.desc_from_workload(wl, bi, prec, ld_i=B.aligned_pitch(blk.ni), scheme=scheme)
         h = B.cfd_block_create(desc, stream)
-        if args.tiles:
-            B.cfd_block_set_tiles(h, [int(v) for v in args.tiles.split(",")])
+        if tiles:
+            B.cfd_block_set_tiles(h, tiles)
         xyz = torch.from_numpy(blk.xyz).cuda()
         B.cfd_metrics(h, xyz, blk.ni + 12, blk.nj + 12)
         del xyz
-        descs.append(desc)
         hs.append(h)
         qs.append(B.upload_state(desc, blk.q))
         qas.append(B.upload_state(desc, blk.q))
@@ -234,12 +240,8 @@ def main():
     dt = B.cfd_dt_cfl(hs, qs, wl.cfl)
     dt_dev = torch.tensor([dt], dtype=torch.float64, device="cuda")
     points = wl.points
-    bt = None
-    if form == "batched":
-        bt = B.cfd_batch_create(hs, x, stream)
-    h = hs[0]
-    q, qa, qb = qs[0], qas[0], qbs[0]
-    blk = wl.blocks[0]
+    bt = B.cfd_batch_create(hs, x, stream) if form == "batched" else None
+    h, q, qa, qb = hs[0], qs[0], qas[0], qbs[0]
 
     def stage(st, cur, out):
         for hb, c in zip(hs, cur):
@@ -264,73 +266,134 @@ def main():
             B.cfd_rk_stage(h, 2, dt, q, qb, q)
             B.cfd_halo_exchange(x, B.CFD_FIELDS_Q, [q])
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    profiled = form != "batched"  # a captured graph is timed as a whole
-    for hb in hs:
-        B.cfd_profile_reset(hb)
-        B.cfd_profile_enable(hb, profiled)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for n in range(args.steps):
+    for _ in range(steps):
         step()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    prof = {}
-    for hb in hs:
-        B.cfd_profile_enable(hb, False)
-        for name, (launches, ms) in B.cfd_profile_read(hb).items():
-            l0, m0 = prof.get(name, (0, 0.0))
-            prof[name] = (l0 + launches, m0 + ms)
-    for hb, qb_ in zip(hs, qs):
-        if not B.cfd_check_finite(hb, qb_):
-            raise SystemExit("non-finite state after the timed steps")
-    updates = points * 3 * args.steps
-    value = updates / el
-
-    alg = kernel_bytes(ALG_BYTES_FP64 if prec == B.CFD_FP64 else ALG_BYTES_MIXED, B.cfd_sweep_order())
-    stage_bytes = sum(alg.values()) * points
-    kernels = {}
-    for name, (launches, ms) in prof.items():
-        avg_ms = ms / max(launches, 1)
-        ent = {"launches": launches, "avg_ms": round(avg_ms, 4), "share": 0.0}
-        if name in alg:
-            # each block launches every kernel equally often
-            total_bytes = alg[name] * points * launches / nb
-            ent["alg_bytes_per_launch"] = int(total_bytes / launches)
-            ent["alg_GBps"] = round(total_bytes / (ms * 1e-3) / 1e9, 1)
-        kernels[name] = ent
-    total_ms = sum(v[1] for v in prof.values())
-    for name, ent in kernels.items():
-        ent["share"] = round(prof[name][1] / total_ms, 3)
-    if kernels:
-        dom = max((n for n in kernels if n in alg), key=lambda n: prof[n][1])
-        dk = kernels[dom]
-        achieved = dk["alg_GBps"]
-        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": load_traffic(dom, args.workload, args.precision), "kernel": dom,
-                    "alg_bytes_per_point": alg[dom], "avg_launch_ms": dk["avg_ms"]}
-    else:  # a captured graph: the whole step against its algorithmic bytes
-        achieved = round(stage_bytes * 3 * args.steps / el / 1e9, 1)
-        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "whole RK step (graph)",
-                    "alg_bytes_per_point": 3 * stage_bytes // points}
-    copy_gbs = copy_bandwidth(torch)
-
-    cfg = {"workload": wname, "blocks": nb, "points": points, "precision": args.precision, "form": form,
-           "scheme": args.scheme,
-           "cfl": wl.cfl, "dt": dt, "parallelism": "single GPU"}
+    res = {"workload": wname, "precision": precision, "form": form, "blocks": nb, "points": points,
+           "steps": steps, "warmup": warmup, "dt": dt, "cfl": wl.cfl,
+           "value": points * 3 * steps / el, "ms_per_step": el / steps * 1e3}
     if nb == 1:
-        cfg["grid"] = [blk.ni, blk.nj, blk.nk]
+        res["grid"] = [wl.blocks[0].ni, wl.blocks[0].nj, wl.blocks[0].nk]
     if bt is not None:
         tc, tp = B.cfd_batch_tuning(bt)
-        times = B.cfd_batch_tuning_times(bt)
-        cfg["tuned_tiles"] = {"cfg": tc, "persistent": tp,
-                              "candidates_ms": {f"{d}/{c}/{p}": round(v, 4) for (d, c, p), v in times.items()}}
+        res["tuned_tiles"] = {"cfg": tc, "persistent": tp}
     else:
-        cfg["tiles"] = B.cfd_block_tiles(hs[0])
+        res["tiles"] = B.cfd_block_tiles(hs[0])
+    if profile_steps > 0 and form != "batched":
+        for hb in hs:
+            B.cfd_profile_reset(hb)
+            B.cfd_profile_enable(hb, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(profile_steps):
+            step()
+        torch.cuda.synchronize()
+        elp = time.perf_counter() - t0
+        prof = {}
+        for hb in hs:
+            B.cfd_profile_enable(hb, False)
+            for name, (launches, ms) in B.cfd_profile_read(hb).items():
+                l0, m0 = prof.get(name, (0, 0.0))
+                prof[name] = (l0 + launches, m0 + ms)
+        res["prof"] = prof
+        res["profiled_value"] = points * 3 * profile_steps / elp
+        res["profile_steps"] = profile_steps
+    for hb, qb_ in zip(hs, qs):
+        if not B.cfd_check_finite(hb, qb_):
+            raise SystemExit(f"non-finite state after the timed steps of {wname} ({precision}, {form})")
+    if bt is not None:
+        B.cfd_batch_destroy(bt)
+    B.cfd_exchange_destroy(x)
+    for hb in hs:
+        B.cfd_block_destroy(hb)
+    del qs, qas, qbs, q, qa, qb, dt_dev
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return res
+
+
+def kernel_table(res, B, workload_key):
+    """Per-kernel mean launch time and algorithmic bandwidth from a profiled leg, and the
+    roofline entry of the dominant kernel (largest total time)."""
+    prec = res["precision"]
+    alg = kernel_bytes(ALG_BYTES_FP64 if prec == "fp64" else ALG_BYTES_MIXED, B.cfd_sweep_order())
+    prof, points, nb = res["prof"], res["points"], res["blocks"]
+    kernels = {}
+    total_ms = sum(v[1] for v in prof.values())
+    for name, (launches, ms) in prof.items():
+        ent = {"launches": launches, "avg_ms": round(ms / max(launches, 1), 4), "share": round(ms / total_ms, 3)}
+        if name in alg:
+            total_bytes = alg[name] * points * launches / nb  # every block launches each kernel equally often
+            ent["alg_bytes_per_launch"] = int(total_bytes / launches)
+            ent["alg_GBps"] = round(total_bytes / (ms * 1e-3) / 1e9, 1)
+            ent["alg_frac"] = round(total_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+            cnt = load_counters(name, workload_key, prec)
+            if cnt and cnt.get("flop_per_launch"):
+                tf = cnt["flop_per_launch"] * launches / (ms * 1e-3) / 1e12
+                ent["valu_TFLOPs"] = round(tf, 2)
+                ent["valu_frac"] = round(tf / VALU_PEAK_TFLOPS[prec], 4)
+        kernels[name] = ent
+    dom = max((n for n in kernels if n in alg), key=lambda n: prof[n][1])
+    dk = kernels[dom]
+    cnt = load_counters(dom, workload_key, prec)
+    roofline = {"bound": "hbm", "achieved": dk["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": dk["alg_frac"], "traffic": cnt.get("bytes_per_launch") if cnt else None,
+                "kernel": dom, "alg_bytes_per_point": round(alg[dom], 2),
+                "points_per_launch": points // nb, "avg_launch_ms": dk["avg_ms"]}
+    return kernels, roofline, alg
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="channel", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--form", default=None, choices=["single", "perblock", "batched"],
+                    help="single-block calls, per-block launches, or the batched graph form")
+    ap.add_argument("--profile-steps", type=int, default=5,
+                    help="steps of the second pass with per-kernel event timing")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-legs", action="store_true", help="skip the side legs of the default run")
+    ap.add_argument("--scheme", default="modified", choices=["modified", "original"],
+                    help="inviscid scheme: modified AFWENO (characteristic space at the nodes) or the "
+                         "original one (at the half points)")
+    ap.add_argument("--tiles", default=None,
+                    help="sweep tile shapes xi,eta,zeta of the single / per-block forms (library default if unset)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-block path runs all blocks on one device)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2006_07964_amd import binding as B
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+    B.lib()
+    scheme = B.CFD_AFWENO_ORIGINAL if args.scheme == "original" else B.CFD_AFWENO_MODIFIED
+    tiles = [int(v) for v in args.tiles.split(",")] if args.tiles else None
+    t_start = time.perf_counter()
+    wl, wname = build_workload(args.workload)
+    head = run_leg(torch, B, wl, wname, args.precision, args.form, args.steps, args.warmup, scheme, tiles,
+                   profile_steps=args.profile_steps)
+    print(f"# headline {wname} {args.precision} {head['form']}: {head['value']:.4g} updates/s "
+          f"({time.perf_counter() - t_start:.0f} s)", file=sys.stderr, flush=True)
+
+    value = head["value"]
+    cfg = {k: head[k] for k in ("workload", "blocks", "points", "precision", "form", "cfl", "dt") if k in head}
+    cfg.update({"scheme": args.scheme, "parallelism": "single GPU"})
+    for k in ("grid", "tiles", "tuned_tiles"):
+        if k in head:
+            cfg[k] = head[k]
     out = {
         # the headline metric: updates/s is `value`, the HBM GB/s and % of peak are in `roofline`
         "metric": "grid-point RK3 stage updates/s (FP64 vs mixed/batched) + HBM GB/s % of peak",
@@ -339,29 +402,73 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": el / args.steps * 1e3,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == B.CFD_FP64 else "f32+f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": cfg,
-        "roofline": roofline,
-        "kernels": kernels,
-        "copy_GBps": round(copy_gbs, 1),
-        # algorithmic bytes of whole stages over the measured time
-        "step_alg_GBps": round(stage_bytes * 3 * args.steps / el / 1e9, 1),
     }
-    if not args.no_cpu and nb == 1:
-        out["cpu_baseline"] = cpu_baseline(wl, wname, scheme)
-        one = cpu_baseline_one_thread(args.workload, scheme)
+    design_bytes = None
+    if "prof" in head:
+        kernels, roofline, alg = kernel_table(head, B, args.workload)
+        out["roofline"] = roofline
+        out["kernels"] = kernels
+        out["profiled_pass"] = {"steps": head["profile_steps"], "value": head["profiled_value"]}
+        design_bytes = sum(alg.values())
+    copy_gbs = copy_bandwidth(torch)
+    hbm = {"copy_GBps": round(copy_gbs, 1), "copy_frac": round(copy_gbs / HBM_PEAK_GBS, 4),
+           "compulsory_B_per_update": round(COMPULSORY_B, 2),
+           "compulsory_GBps": round(COMPULSORY_B * value / 1e9, 1),
+           "compulsory_frac": round(COMPULSORY_B * value / 1e9 / HBM_PEAK_GBS, 4)}
+    if design_bytes is not None:
+        # the pencil design's algorithmic bytes of whole stages over the timed steps
+        hbm["design_B_per_update"] = round(design_bytes, 2)
+        hbm["step_alg_GBps"] = round(design_bytes * value / 1e9, 1)
+        hbm["step_alg_frac"] = round(design_bytes * value / 1e9 / HBM_PEAK_GBS, 4)
+        # binding roof of the step: the larger of its HBM and VALU fractions (VALU from the
+        # counter figures of the current sources, when present)
+        k = out["kernels"]
+        if all("valu_frac" in k[n] for n in alg if n in k):
+            tot_ms = sum(k[n]["avg_ms"] * k[n]["launches"] for n in alg if n in k)
+            vf = sum(k[n]["valu_frac"] * k[n]["avg_ms"] * k[n]["launches"] for n in alg if n in k) / tot_ms
+            hbm["step_valu_frac"] = round(vf, 4)
+            hbm["binding_frac"] = round(max(vf, hbm["step_alg_frac"]), 4)
+    out["hbm"] = hbm
+
+    # ---- side legs of the default run: the other throughput configurations ------------
+    if not args.no_legs and args.workload == "channel" and args.precision == "fp64" and head["form"] == "single":
+        legs = {}
+        res = run_leg(torch, B, wl, wname, "mixed", "single", args.steps, args.warmup, scheme)
+        legs["channel_mixed_single"] = {"value": res["value"], "ms_per_step": res["ms_per_step"]}
+        del wl
+        print(f"# channel mixed: {res['value']:.4g} updates/s ({time.perf_counter() - t_start:.0f} s)",
+              file=sys.stderr, flush=True)
+        wl3, n3 = build_workload("tgv256")
+        res = run_leg(torch, B, wl3, n3, "mixed", "single", 20, 3, scheme)
+        legs["tgv256_mixed_single"] = {"workload": n3, "value": res["value"], "ms_per_step": res["ms_per_step"]}
+        del wl3
+        print(f"# tgv256 mixed: {res['value']:.4g} updates/s ({time.perf_counter() - t_start:.0f} s)",
+              file=sys.stderr, flush=True)
+        wl4, n4 = build_workload("ogrid24")
+        r64 = run_leg(torch, B, wl4, n4, "fp64", "perblock", 10, 3, scheme)
+        rmx = run_leg(torch, B, wl4, n4, "mixed", "batched", 10, 3, scheme)
+        del wl4
+        legs["ogrid24_fp64_perblock"] = {"workload": n4, "value": r64["value"], "ms_per_step": r64["ms_per_step"]}
+        legs["ogrid24_mixed_batched"] = {"workload": n4, "value": rmx["value"], "ms_per_step": rmx["ms_per_step"],
+                                         "tuned_tiles": rmx.get("tuned_tiles")}
+        legs["ogrid24_batched_mixed_over_perblock_fp64"] = round(rmx["value"] / r64["value"], 3)
+        print(f"# ogrid24: fp64 per-block {r64['value']:.4g}, mixed batched {rmx['value']:.4g} "
+              f"({time.perf_counter() - t_start:.0f} s)", file=sys.stderr, flush=True)
+        out["legs"] = legs
+
+    if not args.no_cpu and args.workload in SAMPLES:
+        out["cpu_baseline"] = cpu_baseline(args.workload, scheme, threads=0)
+        one = cpu_baseline(args.workload, scheme, threads=1)
         if one is not None:
             out["cpu_baseline_1thread"] = one
-    if bt is not None:
-        B.cfd_batch_destroy(bt)
-    B.cfd_exchange_destroy(x)
-    for hb in hs:
-        B.cfd_block_destroy(hb)
+    out["bench_wall_s"] = round(time.perf_counter() - t_start, 1)
     print(json.dumps(out), flush=True)
 
 

@@ -51,6 +51,14 @@ enum { CFD_WENO_JS = 0, CFD_WENO_LINEAR = 1 };         /* Eq 15 weights or ideal
  * the values on both sides of the node (modified AFWENO, Figs 10-11), or at the half
  * points, two WENO interpolations per half point (original AFWENO, Fig 9)              */
 enum { CFD_AFWENO_MODIFIED = 0, CFD_AFWENO_ORIGINAL = 1 };
+/* viscous derivatives at the three nodes next to a CFD_BC_WALL / CFD_BC_FARFIELD[_CHAR]
+ * face (Sec. 4.5.2 mentions one-sided differences near block boundaries): central
+ * sixth-order differences over ghost values of the velocity, temperature and viscous
+ * fluxes reflected about the boundary node (second-order accurate there), or seven-point
+ * one-sided differences over the boundary node and six nodes inside, exact on
+ * polynomials of degree six, for the gradients and the viscous-flux derivative.  The
+ * inviscid terms use the ghost states of the face either way.                          */
+enum { CFD_VISC_REFLECT = 0, CFD_VISC_ONE_SIDED = 1 };
 /* face kinds; CFD_BC_FARFIELD holds qinf in the ghosts, CFD_BC_FARFIELD_CHAR fills them
  * from locally one-dimensional Riemann invariants along the outward normal (boundary
  * node's outgoing invariant, qinf's incoming one, entropy and tangential velocity from the
@@ -74,12 +82,15 @@ typedef struct cfd_params {
   double reynolds;  /* Re_inf                                                           */
   double prandtl;   /* Pr of the heat flux (Eq 6)                                       */
   double suth;      /* Sutherland constant S/T_ref of mu(T) = T^1.5 (1+S)/(T+S)         */
-  double weno_eps;  /* epsilon of Eq 15 (paper: 1e-6)                                   */
+  double weno_eps;  /* epsilon of Eq 15 (paper: 1e-6); with WENO_JS weights at least
+                       1e-30 (FP64) or 1e-8 (CFD_MIXED), else CFD_ERR_ARG: the weights
+                       are formed over a common denominator that scales as eps^8 / eps^4
+                       where the smoothness indicators vanish                           */
   int32_t viscous;  /* 1: Navier-Stokes, 0: Euler                                       */
   int32_t weights;  /* CFD_WENO_JS or CFD_WENO_LINEAR                                   */
   int32_t scheme;   /* CFD_AFWENO_MODIFIED (default) or CFD_AFWENO_ORIGINAL; the batched
                        form runs the original one with one workgroup per tile only      */
-  int32_t reserved; /* must be 0                                                         */
+  int32_t visc_closure; /* CFD_VISC_REFLECT (default) or CFD_VISC_ONE_SIDED            */
   double t_wall;    /* isothermal wall temperature (CFD_BC_WALL faces)                  */
   double qinf[5];   /* conserved far-field state (CFD_BC_FARFIELD faces)                */
 } cfd_params;
@@ -194,11 +205,13 @@ int cfd_halo_exchange(cfd_exchange* x, int field_set, void* const* block_bufs, v
 /* ---- time step and checks ---------------------------------------------------------- */
 /* dt = cfl / max over all interior points of all blocks of
  * sum_d (|U_d| + c |grad d|), U_d the contravariant velocity with unhatted metrics
- * (the CFL-controlled global step of Sec. 4.5.3).  Q[b] device.  Synchronises.          */
+ * (the CFL-controlled global step of Sec. 4.5.3).  Q[b] device.  Synchronises.
+ * CFD_ERR_NONFINITE if that sum is not finite at some point (a NaN or Inf in a state).  */
 int cfd_dt_cfl(cfd_block* const* blocks, int nb, const double* const* Q, double cfl,
                double* dt_out);
 /* The same step written to device memory: *dt_dev (one double, device) receives the
- * value, or NaN when the spectral radius is not positive and finite.  Stream-ordered on
+ * value, or NaN when the spectral radius is not positive and finite (in particular when
+ * any point's sum is NaN or infinite).  Stream-ordered on
  * blocks[0]'s stream, after the work already enqueued on every block's stream (event
  * waits, no host synchronisation; no memset), so a time loop can recompute the step
  * every iteration and hand dt_dev to cfd_rk_stage_dev or cfd_batch_step (the reduced-
@@ -258,7 +271,9 @@ int cfd_batch_step(cfd_batch* bt, const double* dt_dev, double* const* Qn, doubl
  * shapes, persist[d] = 1 for the persistent schedule).  Before the first step these are
  * the defaults; the first cfd_batch_step times every candidate and keeps the fastest.   */
 int cfd_batch_tuning(const cfd_batch* bt, int* cfg, int* persist);
-/* Override the tiling (skips the autotuner; the next step re-captures its graph).       */
+/* Override the tiling (skips the autotuner; the next step re-captures its graph).
+ * CFD_ERR_UNSUPPORTED for a persistent schedule with the original scheme or with blocks
+ * that use the one-sided viscous closure (those run one workgroup per tile).            */
 int cfd_batch_set_tuning(cfd_batch* bt, const int* cfg, const int* persist);
 /* Milliseconds per launch that the autotuner measured for each candidate, at
  * ms[(d * cfd_tile_config_count() + cfg) * 2 + persist] for sweep direction d; -1 where

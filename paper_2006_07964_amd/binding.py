@@ -20,6 +20,7 @@ CFD_ERR_JACOBIAN, CFD_ERR_NONFINITE, CFD_ERR_UNSUPPORTED = -5, -6, -7
 CFD_FP64, CFD_MIXED = 0, 1
 CFD_WENO_JS, CFD_WENO_LINEAR = 0, 1
 CFD_AFWENO_MODIFIED, CFD_AFWENO_ORIGINAL = 0, 1
+CFD_VISC_REFLECT, CFD_VISC_ONE_SIDED = 0, 1
 CFD_BC_PERIODIC, CFD_BC_INTERFACE, CFD_BC_WALL, CFD_BC_FARFIELD, CFD_BC_FARFIELD_CHAR = 0, 1, 2, 3, 4
 CFD_FIELDS_Q, CFD_FIELDS_VISC = 0, 1
 CFD_DIR_XI, CFD_DIR_ETA, CFD_DIR_ZETA, CFD_TERM_INV, CFD_TERM_VIS, CFD_ALL = 1, 2, 4, 8, 16, 31
@@ -35,7 +36,7 @@ class cfd_params(C.Structure):
     _fields_ = [
         ("gamma", C.c_double), ("mach", C.c_double), ("reynolds", C.c_double), ("prandtl", C.c_double),
         ("suth", C.c_double), ("weno_eps", C.c_double), ("viscous", C.c_int32), ("weights", C.c_int32),
-        ("scheme", C.c_int32), ("reserved", C.c_int32), ("t_wall", C.c_double), ("qinf", C.c_double * 5),
+        ("scheme", C.c_int32), ("visc_closure", C.c_int32), ("t_wall", C.c_double), ("qinf", C.c_double * 5),
     ]
 
 
@@ -378,7 +379,7 @@ def download_state(desc: "cfd_block_desc", t):
 def make_desc(ni, nj, nk, precision=CFD_FP64, bc=(0, 0, 0, 0, 0, 0), ld_i=None, ld_j=None, gamma=1.4,
               mach=0.5, reynolds=1000.0, prandtl=0.71, suth=110.4 / 288.15, weno_eps=1e-6, viscous=True,
               weights=CFD_WENO_JS, scheme=None, t_wall=1.0,
-              qinf=(1.0, 0.0, 0.0, 0.0, 1.0 / (1.4 * 0.4))) -> cfd_block_desc:
+              qinf=(1.0, 0.0, 0.0, 0.0, 1.0 / (1.4 * 0.4)), visc_closure=CFD_VISC_REFLECT) -> cfd_block_desc:
     d = cfd_block_desc()
     d.ni, d.nj, d.nk = ni, nj, nk
     d.ld_i = ni + 6 if ld_i is None else ld_i
@@ -391,7 +392,7 @@ def make_desc(ni, nj, nk, precision=CFD_FP64, bc=(0, 0, 0, 0, 0, 0), ld_i=None, 
     p.viscous = int(bool(viscous))
     p.weights = int(weights)
     p.scheme = CFD_AFWENO_MODIFIED if scheme is None else int(scheme)
-    p.reserved = 0
+    p.visc_closure = int(visc_closure)
     p.t_wall = t_wall
     for n in range(5):
         p.qinf[n] = float(qinf[n])
@@ -402,6 +403,6 @@ def desc_from_workload(wl, block: int = 0, precision=CFD_FP64, **over) -> cfd_bl
     b = wl.blocks[block]
     kw = dict(precision=precision, bc=b.bc, gamma=wl.gamma, mach=wl.mach, reynolds=wl.reynolds,
               prandtl=wl.prandtl, suth=wl.suth, weno_eps=wl.eps, viscous=wl.viscous, t_wall=wl.t_wall,
-              qinf=wl.qinf)
+              qinf=wl.qinf, visc_closure=getattr(wl, "visc_closure", CFD_VISC_REFLECT))
     kw.update(over)
     return make_desc(b.ni, b.nj, b.nk, **kw)

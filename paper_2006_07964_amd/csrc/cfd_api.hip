@@ -116,10 +116,10 @@ struct ProfScope {
 // =====================================================================================
 // block
 // =====================================================================================
-// tile shapes of a block's own sweeps until cfd_block_set_tiles (the batched autotuner's
-// usual choice on large blocks), [FP64 / mixed][direction]: 4 lines x 58 nodes along xi,
-// 16 x 14 along eta, 8 x 26 (FP64) or 16 x 14 (mixed) along zeta, 256 threads each
-constexpr int kDefaultTiles[2][3] = {{5, 2, 4}, {5, 2, 2}};
+// tile shapes of a block's own sweeps until cfd_block_set_tiles, [FP64 / mixed][direction]
+// (measured on the 512 x 512 x 384 channel): 4 lines x 58 nodes along xi, 8 x 30 along eta
+// and zeta in FP64 (16 x 14 in mixed precision), 256 threads each
+constexpr int kDefaultTiles[2][3] = {{5, 6, 6}, {5, 2, 2}};
 
 struct cfd_block {
   cfd_block_desc d;
@@ -336,7 +336,15 @@ int validate_desc(const cfd_block_desc* d) {
     return fail(CFD_ERR_ARG, "gamma > 1, Re, Pr, Sutherland constant and WENO epsilon > 0 required");
   if (p.weights != CFD_WENO_JS && p.weights != CFD_WENO_LINEAR) return fail(CFD_ERR_ARG, "unknown WENO weights");
   if (p.scheme != CFD_AFWENO_MODIFIED && p.scheme != CFD_AFWENO_ORIGINAL) return fail(CFD_ERR_ARG, "unknown AFWENO scheme");
-  if (p.reserved != 0) return fail(CFD_ERR_ARG, "cfd_params.reserved must be 0");
+  if (p.visc_closure != CFD_VISC_REFLECT && p.visc_closure != CFD_VISC_ONE_SIDED)
+    return fail(CFD_ERR_ARG, "unknown viscous closure");
+  // Eq 15 is evaluated over a common denominator whose terms scale as weno_eps^4 (FP32)
+  // and weno_eps^8 (FP64 product of the two sides' denominators) where the smoothness
+  // indicators vanish; these floors keep them inside the normal range of the type
+  if (p.weights == CFD_WENO_JS && d->precision == CFD_MIXED && p.weno_eps < 1e-8)
+    return fail(CFD_ERR_ARG, "WENO epsilon below 1e-8 underflows the FP32 weights (mixed precision)");
+  if (p.weights == CFD_WENO_JS && p.weno_eps < 1e-30)
+    return fail(CFD_ERR_ARG, "WENO epsilon below 1e-30 underflows the FP64 weights");
   for (int f = 0; f < 6; ++f)
     if (d->bc[f] < CFD_BC_PERIODIC || d->bc[f] > CFD_BC_FARFIELD_CHAR) return fail(CFD_ERR_ARG, "unknown face kind");
   for (int ax = 0; ax < 3; ++ax)
@@ -364,6 +372,15 @@ PtrTable single_table(void* p, int64_t plane) {
   return t;
 }
 
+// faces whose viscous derivatives take the one-sided closure (bit 2*axis + side)
+int one_sided_mask(const cfd_block_desc& d) {
+  if (d.params.visc_closure != CFD_VISC_ONE_SIDED) return 0;
+  int m = 0;
+  for (int f = 0; f < 6; ++f)
+    if (is_physical(d.bc[f])) m |= 1 << f;
+  return m;
+}
+
 // viscous fluxes of one block with block-local halos (periodic wraps, physical ghosts)
 int run_visc(cfd_block* b, const double* Q) {
   ViscArgs va;
@@ -374,6 +391,7 @@ int run_visc(cfd_block* b, const double* Q) {
   va.met_r = b->met_r;
   va.vis = b->vis;
   va.ph = make_phys(b->d.params);
+  va.one_sided = one_sided_mask(b->d);
   // the prepass writes the periodic images itself (they were the only local copies)
   for (int ax = 0; ax < 3; ++ax)
     if (b->d.bc[2 * ax] == CFD_BC_PERIODIC) va.periodic |= 1 << ax;
@@ -419,6 +437,7 @@ int run_sweeps(cfd_block* b, const double* Q, unsigned mask, int out_kind, doubl
   a.b.vis = b->vis;
   a.b.qn = qn;
   a.b.dt_field = b->dt_field;
+  a.b.one_sided = one_sided_mask(b->d);
   a.c.ph = make_phys(b->d.params);
   a.c.do_inv = inv;
   a.c.do_vis = vis;
@@ -855,6 +874,7 @@ struct cfd_batch {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   int precision = CFD_FP64;
   bool viscous = true;
+  bool one_sided = false;  // some block has faces with the one-sided viscous closure
   // work lists
   TileList visc_tl{};
   TileList sweep_tl[3]{};
@@ -944,6 +964,7 @@ int batch_create(cfd_block* const* blocks, int nb, cfd_exchange* x, void* hip_st
   }
   bt->precision = blocks[0]->d.precision;
   bt->viscous = blocks[0]->d.params.viscous != 0;
+  for (int b = 0; b < nb; ++b) bt->one_sided = bt->one_sided || one_sided_mask(blocks[b]->d) != 0;
   for (int d = 0; d < 3; ++d) {
     bt->cfg[d] = kDefaultTiles[bt->precision == CFD_FP64 ? 0 : 1][d];
     for (int c = 0; c < kTileCfgs; ++c) bt->tune_ms[d][c][0] = bt->tune_ms[d][c][1] = -1.f;
@@ -1001,6 +1022,7 @@ void build_args(cfd_batch* bt, double* const* Qn, double* const* QA, double* con
       c.has_prev = n > 0;
       c.out_kind = n == 2 ? kOutRK : kOutPartial;
       c.dt_dev = dt_dev;
+      c.one_sided = bt->one_sided;
       c.ca = kRK[st][0];
       c.cb = kRK[st][1];
       c.cc = kRK[st][2];
@@ -1014,6 +1036,7 @@ void build_args(cfd_batch* bt, double* const* Qn, double* const* QA, double* con
       v.met_r = B->met_r;
       v.vis = B->vis;
       v.ph = ph;
+      v.one_sided = one_sided_mask(B->d);
       int tiles;
       visc_tiling(B->g, 0, &v.kc, &tiles);  // the batch list is long enough
       for (int d = 0; d < 3; ++d) {
@@ -1028,6 +1051,7 @@ void build_args(cfd_batch* bt, double* const* Qn, double* const* QA, double* con
         a.out = d == kSweepOrder[2] ? outp[b] : nullptr;
         a.qn = Qn[b];
         a.dt_field = B->dt_field;
+        a.one_sided = one_sided_mask(B->d);
         sweep_tiling(d, bt->cfg[d], B->g, &a.tiles_c1, &a.tiles_d, &a.tile_len);
       }
     }
@@ -1052,8 +1076,8 @@ hipError_t enqueue_stage(cfd_batch* bt, int st, double* const* outp) {
   hipError_t e = hipSuccess;
   if (bt->viscous) {
     const ViscArgs* va = bt->visc_args_dev + st * nb;
-    e = bt->precision == CFD_FP64 ? launch_visc_batch<double>(va, bt->visc_tl, bt->stream)
-                                  : launch_visc_batch<float>(va, bt->visc_tl, bt->stream);
+    e = bt->precision == CFD_FP64 ? launch_visc_batch<double>(va, bt->visc_tl, bt->one_sided, bt->stream)
+                                  : launch_visc_batch<float>(va, bt->visc_tl, bt->one_sided, bt->stream);
     if (e != hipSuccess) return e;
     PtrTable t;
     std::memset(&t, 0, sizeof t);
@@ -1111,8 +1135,8 @@ int autotune(cfd_batch* bt, double* const* Qn, double* const* QA, double* const*
     rc = upload_args(bt, Qn, QA, QB, dt_dev);
     if (rc == CFD_OK) {
       hipError_t e = bt->precision == CFD_FP64
-                         ? launch_visc_batch<double>(bt->visc_args_dev, bt->visc_tl, bt->stream)
-                         : launch_visc_batch<float>(bt->visc_args_dev, bt->visc_tl, bt->stream);
+                         ? launch_visc_batch<double>(bt->visc_args_dev, bt->visc_tl, bt->one_sided, bt->stream)
+                         : launch_visc_batch<float>(bt->visc_args_dev, bt->visc_tl, bt->one_sided, bt->stream);
       if (e != hipSuccess) rc = hip_fail(e, "tuning prepass");
     }
   }
@@ -1121,7 +1145,8 @@ int autotune(cfd_batch* bt, double* const* Qn, double* const* QA, double* const*
     int best_cfg = 0, best_p = 0;
     for (int c = 0; c < kTileCfgs && rc == CFD_OK; ++c)
       for (int p = 0; p < 2 && rc == CFD_OK; ++p) {
-        if (p == 1 && bt->blocks[0]->d.params.scheme == CFD_AFWENO_ORIGINAL) continue;  // not built
+        // not built: the persistent schedule of the original scheme or of one-sided closures
+        if (p == 1 && (bt->blocks[0]->d.params.scheme == CFD_AFWENO_ORIGINAL || bt->one_sided)) continue;
         bt->cfg[d] = c;
         bt->persist[d] = p;
         fill_tiles(bt);
@@ -1225,9 +1250,10 @@ int batch_set_tuning(cfd_batch* bt, const int* cfg, const int* persist) {
   if (!bt || !cfg || !persist) return fail(CFD_ERR_ARG, "null argument");
   for (int d = 0; d < 3; ++d)
     if (cfg[d] < 0 || cfg[d] >= kTileCfgs) return fail(CFD_ERR_ARG, "tile configuration out of range");
-  if (bt->blocks[0]->d.params.scheme == CFD_AFWENO_ORIGINAL)
+  if (bt->blocks[0]->d.params.scheme == CFD_AFWENO_ORIGINAL || bt->one_sided)
     for (int d = 0; d < 3; ++d)
-      if (persist[d]) return fail(CFD_ERR_UNSUPPORTED, "the original scheme has no persistent schedule");
+      if (persist[d])
+        return fail(CFD_ERR_UNSUPPORTED, "the original scheme and one-sided viscous closures have no persistent schedule");
   for (int d = 0; d < 3; ++d) {
     bt->cfg[d] = cfg[d];
     bt->persist[d] = persist[d] != 0;

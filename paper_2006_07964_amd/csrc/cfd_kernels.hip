@@ -146,6 +146,38 @@ __device__ __forceinline__ void primitives(GP<const double> Q, int64_t plane, ui
   out[3] = gg * (q[4] * rinv - R(0.5) * (out[0] * out[0] + out[1] * out[1] + out[2] * out[2]));
 }
 
+// One-sided closure of the viscous derivatives (Sec. 4.5.2 mentions one-sided differences
+// near block boundaries without giving them): the derivative at node r = 0, 1, 2 of a face
+// of the degree-6 polynomial through the seven nodes nearest it (node 0 on the face, node
+// m at distance m inside) is sum_m kOS6[r][m] f(m) (Lagrange derivative weights, unit
+// spacing); a node r away from the high face takes the mirror image with the opposite sign.
+__constant__ double kOS6[3][7] = {
+    {-49.0 / 20.0, 6.0, -15.0 / 2.0, 20.0 / 3.0, -15.0 / 4.0, 6.0 / 5.0, -1.0 / 6.0},
+    {-1.0 / 6.0, -77.0 / 60.0, 5.0 / 2.0, -5.0 / 3.0, 5.0 / 6.0, -1.0 / 4.0, 1.0 / 30.0},
+    {1.0 / 30.0, -2.0 / 5.0, -7.0 / 12.0, 4.0 / 3.0, -1.0 / 2.0, 2.0 / 15.0, -1.0 / 60.0}};
+
+// Window of the one-sided closure for the node at index n of an axis of nd nodes, given
+// the face mask bits of that axis (bit 0: low face one-sided, bit 1: high face): returns
+// false for a central node, else the first window node, the weight row and the sign.
+__device__ __forceinline__ bool one_sided_window(int bits, int n, int nd, int* first, int* row, int* sign) {
+  if ((bits & 1) && n < 3) {
+    *first = 0;
+    *row = n;
+    *sign = 1;
+    return true;
+  }
+  if ((bits & 2) && n > nd - 4) {
+    *first = nd - 7;
+    *row = nd - 1 - n;
+    *sign = -1;
+    return true;
+  }
+  return false;
+}
+__device__ __forceinline__ double os6_weight(int row, int sign, int m) {
+  return sign > 0 ? kOS6[row][m] : -kOS6[row][6 - m];
+}
+
 // d/dn of a field on a 7-point line, g(m) = value at offset m (sixth-order central)
 template <typename R, typename F>
 __device__ __forceinline__ R grad6(F g) {
@@ -159,7 +191,9 @@ __device__ __forceinline__ R grad6(F g) {
   return s;
 }
 
-template <typename R>
+// OS: the block may have faces with the one-sided closure (a separate instantiation, so
+// that blocks without them keep the register budget of the plain prepass)
+template <typename R, bool OS>
 __device__ __forceinline__ void visc_tile(const ViscArgs& a, int t, ViscShared<R>& sh) {
   const Geom& g = a.g;
   const int nti = (g.ni + VI - 1) / VI, ntj = (g.nj + VJ - 1) / VJ;
@@ -221,6 +255,30 @@ __device__ __forceinline__ void visc_tile(const ViscArgs& a, int t, ViscShared<R
         gr[n][2] = grad6<R>([&](int m) { return P[3 + m][n]; });
       }
       const uint32_t p = pc + (uint32_t)k * sk;
+      if constexpr (OS) {
+        // nodes next to a one-sided face of direction d: the seven-point one-sided
+        // derivative over the nodes nearest the face replaces the central one (whose
+        // ghost values it ignores); primitives of the window nodes from Q
+        const int idx[3] = {i, j, k};
+        const int nds[3] = {g.ni, g.nj, g.nk};
+        const uint32_t st[3] = {1u, (uint32_t)g.ld_i, sk};
+#pragma unroll 1
+        for (int d = 0; d < 3; ++d) {
+          int first, row, sign;
+          if (!one_sided_window((a.one_sided >> (2 * d)) & 3, idx[d], nds[d], &first, &row, &sign)) continue;
+          R acc[4] = {R(0), R(0), R(0), R(0)};
+#pragma unroll 1
+          for (int m = 0; m < 7; ++m) {
+            R pr[4];
+            primitives<R>(Q, plane, p + (uint32_t)(first + m - idx[d]) * st[d], gg, pr);
+            const R wgt = R(os6_weight(row, sign, m));
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[n] += wgt * pr[n];
+          }
+#pragma unroll
+          for (int n = 0; n < 4; ++n) gr[n][d] = acc[n];
+        }
+      }
       R mh[3][3];
 #pragma unroll
       for (int d = 0; d < 3; ++d)
@@ -276,10 +334,10 @@ __device__ __forceinline__ void visc_tile(const ViscArgs& a, int t, ViscShared<R
   }
 }
 
-template <typename R>
+template <typename R, bool OS>
 __global__ __launch_bounds__(VNT) __attribute__((amdgpu_waves_per_eu(4))) void k_visc(ViscArgs a) {
   __shared__ ViscShared<R> sh;
-  visc_tile<R>(a, xcd_remap(blockIdx.x, gridDim.x), sh);
+  visc_tile<R, OS>(a, xcd_remap(blockIdx.x, gridDim.x), sh);
 }
 
 __global__ __launch_bounds__(256) void k_round(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
@@ -307,20 +365,23 @@ void visc_tiling(const Geom& g, int min_tiles, int* kc, int* tiles) {
 }
 
 // one workgroup per tile of the concatenated list (ids remapped XCD-contiguously)
-template <typename R>
+template <typename R, bool OS>
 __global__ __launch_bounds__(VNT) __attribute__((amdgpu_waves_per_eu(4))) void k_visc_batch(const ViscArgs* __restrict__ args, TileList tl) {
   __shared__ ViscShared<R> sh;
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   int blk = 0;
   while (t >= tl.prefix[blk + 1]) ++blk;
-  visc_tile<R>(args[blk], t - tl.prefix[blk], sh);
+  visc_tile<R, OS>(args[blk], t - tl.prefix[blk], sh);
 }
 
 template <typename R>
 hipError_t launch_visc(ViscArgs a, hipStream_t s) {
   int tiles;
   visc_tiling(a.g, kViscMinTiles, &a.kc, &tiles);
-  hipLaunchKernelGGL(k_visc<R>, dim3(tiles), dim3(VNT), 0, s, a);
+  if (a.one_sided)
+    hipLaunchKernelGGL((k_visc<R, true>), dim3(tiles), dim3(VNT), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_visc<R, false>), dim3(tiles), dim3(VNT), 0, s, a);
   return hipGetLastError();
 }
 template hipError_t launch_visc<double>(ViscArgs, hipStream_t);
@@ -328,12 +389,15 @@ template hipError_t launch_visc<float>(ViscArgs, hipStream_t);
 
 // args_dev[b].kc must be the chunk length visc_tiling gives for block b
 template <typename R>
-hipError_t launch_visc_batch(const ViscArgs* args_dev, const TileList& tl, hipStream_t s) {
-  hipLaunchKernelGGL(k_visc_batch<R>, dim3(tl.prefix[tl.nblk]), dim3(VNT), 0, s, args_dev, tl);
+hipError_t launch_visc_batch(const ViscArgs* args_dev, const TileList& tl, bool one_sided, hipStream_t s) {
+  if (one_sided)
+    hipLaunchKernelGGL((k_visc_batch<R, true>), dim3(tl.prefix[tl.nblk]), dim3(VNT), 0, s, args_dev, tl);
+  else
+    hipLaunchKernelGGL((k_visc_batch<R, false>), dim3(tl.prefix[tl.nblk]), dim3(VNT), 0, s, args_dev, tl);
   return hipGetLastError();
 }
-template hipError_t launch_visc_batch<double>(const ViscArgs*, const TileList&, hipStream_t);
-template hipError_t launch_visc_batch<float>(const ViscArgs*, const TileList&, hipStream_t);
+template hipError_t launch_visc_batch<double>(const ViscArgs*, const TileList&, bool, hipStream_t);
+template hipError_t launch_visc_batch<float>(const ViscArgs*, const TileList&, bool, hipStream_t);
 
 // =====================================================================================
 // Direction sweep: modified AFWENO inviscid derivative (Sec. 4.5.1, Figs 10-11, Eq 19),
@@ -375,7 +439,9 @@ constexpr int kModified = 0, kOriginal = 1;
 
 // One tile of a direction sweep: t is the logical tile index inside the block (sweep-
 // direction tile fastest, then the cross tile c1, then the cross index c2).
-template <int DIR, typename R, int TW, int TS, int NT, int SCHEME = kModified>
+// OS: some block of the launch has faces with the one-sided viscous closure (a separate
+// instantiation keeps the register budget of the others)
+template <int DIR, typename R, int TW, int TS, int NT, int SCHEME = kModified, bool OS = false>
 __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBlock& b, int t, R* sF, StageT<R, DIR>* sFn,
                                            double* sM, R* sV) {
   constexpr int NH = SweepLds<TW, TS>::NH;
@@ -632,7 +698,19 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
     }
   }
   if (c.do_vis) {
-    if (kStageVis && c.do_inv) {
+    int first = 0, row = 0, sign = 0;
+    if (OS && one_sided_window((b.one_sided >> (2 * DIR)) & 3, d0 + s, nd, &first, &row, &sign)) {
+      // a node next to a one-sided face: seven-point one-sided derivative over the nodes
+      // nearest the face, read from memory (the tile need not hold them)
+#pragma unroll 1
+      for (int v = 1; v < 5; ++v) {
+        const GP<const R> vp = plane_ptr(vis, (v - 1) * plane);
+        R acc = R(0);
+#pragma unroll 1
+        for (int m = 0; m < 7; ++m) acc += R(os6_weight(row, sign, m)) * ldg(vp, po + (uint32_t)(first + m - d0 - s) * sd);
+        r[v] += acc;
+      }
+    } else if (kStageVis && c.do_inv) {
 #pragma unroll
       for (int v = 1; v < 5; ++v) r[v] += d6<R>([&](int m) { return sV[L::f(v - 1, w, s + 3 + m, NN)]; });
     } else {
@@ -674,24 +752,25 @@ struct SweepShared {
 };
 
 // Single block: one workgroup per tile, ids remapped XCD-contiguously.
-template <int DIR, typename R, int TW, int TS, int NT, int SCHEME>
+template <int DIR, typename R, int TW, int TS, int NT, int SCHEME, bool OS>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep(SweepArgs a) {
   __shared__ SweepShared<R, StageT<R, DIR>, TW, TS> sh;
-  sweep_tile<DIR, R, TW, TS, NT, SCHEME>(a.c, a.b, xcd_remap(blockIdx.x, gridDim.x), sh.F, sh.Fn, sh.M, sh.V);
+  sweep_tile<DIR, R, TW, TS, NT, SCHEME, OS>(a.c, a.b, xcd_remap(blockIdx.x, gridDim.x), sh.F, sh.Fn, sh.M, sh.V);
 }
 // the original scheme in FP64 holds six stencil points and the half-point basis at once:
 // three waves per SIMD give it the registers that four would make it spill
-template <int DIR, typename R, int TW, int TS, int NT>
+template <int DIR, typename R, int TW, int TS, int NT, bool OS>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_sweep_w3(SweepArgs a) {
   __shared__ SweepShared<R, StageT<R, DIR>, TW, TS> sh;
-  sweep_tile<DIR, R, TW, TS, NT, kOriginal>(a.c, a.b, xcd_remap(blockIdx.x, gridDim.x), sh.F, sh.Fn, sh.M, sh.V);
+  sweep_tile<DIR, R, TW, TS, NT, kOriginal, OS>(a.c, a.b, xcd_remap(blockIdx.x, gridDim.x), sh.F, sh.Fn, sh.M, sh.V);
 }
 
 // Batched blocks: one launch walks a work list covering the tiles of every block
 // (prefix[b] = first tile of block b).  The list is split into eight contiguous ranges, one
 // per XCD.  PERSIST: a fixed grid of workgroups strides through its XCD's range; otherwise
-// one workgroup per tile (ids remapped XCD-contiguously).
-template <int DIR, typename R, int TW, int TS, int NT, bool PERSIST>
+// one workgroup per tile (ids remapped XCD-contiguously).  Blocks with one-sided faces (OS)
+// run one workgroup per tile.
+template <int DIR, typename R, int TW, int TS, int NT, bool PERSIST, bool OS>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_batch(
     const SweepBlock* __restrict__ blocks, SweepCommon c, TileList tl) {
   __shared__ SweepShared<R, StageT<R, DIR>, TW, TS> sh;
@@ -700,9 +779,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const int t = xcd_remap(blockIdx.x, gridDim.x);
     int blk = 0;
     while (t >= tl.prefix[blk + 1]) ++blk;
-    sweep_tile<DIR, R, TW, TS, NT>(c, blocks[blk], t - tl.prefix[blk], sh.F, sh.Fn, sh.M, sh.V);
+    sweep_tile<DIR, R, TW, TS, NT, kModified, OS>(c, blocks[blk], t - tl.prefix[blk], sh.F, sh.Fn, sh.M, sh.V);
     return;
   }
+  static_assert(!(PERSIST && OS), "the persistent schedule is not built for one-sided closures");
   int start, count, lane_wg, nwg_x;
   xcd_range(total, &start, &count, &lane_wg, &nwg_x);
   int blk = 0;
@@ -716,19 +796,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 
 // Batched original-scheme sweep (one workgroup per tile).  FP64 gets three waves per SIMD
 // (see k_sweep_w3), FP32 the usual four.
-template <int DIR, typename R, int TW, int TS, int NT>
+template <int DIR, typename R, int TW, int TS, int NT, bool OS>
 __device__ __forceinline__ void batch_orig_tile(const SweepBlock* __restrict__ blocks, const SweepCommon& c,
                                                 const TileList& tl, SweepShared<R, StageT<R, DIR>, TW, TS>& sh) {
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   int blk = 0;
   while (t >= tl.prefix[blk + 1]) ++blk;
-  sweep_tile<DIR, R, TW, TS, NT, kOriginal>(c, blocks[blk], t - tl.prefix[blk], sh.F, sh.Fn, sh.M, sh.V);
+  sweep_tile<DIR, R, TW, TS, NT, kOriginal, OS>(c, blocks[blk], t - tl.prefix[blk], sh.F, sh.Fn, sh.M, sh.V);
 }
-template <int DIR, typename R, int TW, int TS, int NT>
+template <int DIR, typename R, int TW, int TS, int NT, bool OS>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 3 : 4))) void k_sweep_batch_orig(
     const SweepBlock* __restrict__ blocks, SweepCommon c, TileList tl) {
   __shared__ SweepShared<R, StageT<R, DIR>, TW, TS> sh;
-  batch_orig_tile<DIR, R, TW, TS, NT>(blocks, c, tl, sh);
+  batch_orig_tile<DIR, R, TW, TS, NT, OS>(blocks, c, tl, sh);
 }
 
 // tile configurations (lines across x nodes along the sweep x threads)
@@ -758,12 +838,23 @@ template <>
 struct TileCfg<5> {
   static constexpr int TW = 4, TS = 58, NT = 256;
 };
+// shapes whose WENO nodes (lines x (nodes + 2)) fill the 256 threads exactly
+template <>
+struct TileCfg<6> {
+  static constexpr int TW = 8, TS = 30, NT = 256;
+};
+template <>
+struct TileCfg<7> {
+  static constexpr int TW = 4, TS = 62, NT = 256;
+};
 
 void sweep_tiling(int dir, int cfg, const Geom& g, int* tiles_c1, int* tiles_d, int* tile_len) {
   static const int tw[kTileCfgs] = {TileCfg<0>::TW, TileCfg<1>::TW, TileCfg<2>::TW,
-                                    TileCfg<3>::TW, TileCfg<4>::TW, TileCfg<5>::TW};
+                                    TileCfg<3>::TW, TileCfg<4>::TW, TileCfg<5>::TW,
+                                    TileCfg<6>::TW, TileCfg<7>::TW};
   static const int tsz[kTileCfgs] = {TileCfg<0>::TS, TileCfg<1>::TS, TileCfg<2>::TS,
-                                     TileCfg<3>::TS, TileCfg<4>::TS, TileCfg<5>::TS};
+                                     TileCfg<3>::TS, TileCfg<4>::TS, TileCfg<5>::TS,
+                                     TileCfg<6>::TS, TileCfg<7>::TS};
   const int nd = dir == 0 ? g.ni : dir == 1 ? g.nj : g.nk;
   const int n1 = dir == 0 ? g.nj : g.ni;
   *tiles_c1 = (n1 + tw[cfg] - 1) / tw[cfg];
@@ -773,9 +864,11 @@ void sweep_tiling(int dir, int cfg, const Geom& g, int* tiles_c1, int* tiles_d, 
 
 void tile_shape(int cfg, int* tw, int* ts, int* nt) {
   static const int w[kTileCfgs] = {TileCfg<0>::TW, TileCfg<1>::TW, TileCfg<2>::TW,
-                                   TileCfg<3>::TW, TileCfg<4>::TW, TileCfg<5>::TW};
+                                   TileCfg<3>::TW, TileCfg<4>::TW, TileCfg<5>::TW,
+                                   TileCfg<6>::TW, TileCfg<7>::TW};
   static const int l[kTileCfgs] = {TileCfg<0>::TS, TileCfg<1>::TS, TileCfg<2>::TS,
-                                   TileCfg<3>::TS, TileCfg<4>::TS, TileCfg<5>::TS};
+                                   TileCfg<3>::TS, TileCfg<4>::TS, TileCfg<5>::TS,
+                                   TileCfg<6>::TS, TileCfg<7>::TS};
   *tw = w[cfg];
   *ts = l[cfg];
   *nt = sweep_threads(cfg);
@@ -783,36 +876,41 @@ void tile_shape(int cfg, int* tw, int* ts, int* nt) {
 
 int sweep_threads(int cfg) {
   static const int nt[kTileCfgs] = {TileCfg<0>::NT, TileCfg<1>::NT, TileCfg<2>::NT,
-                                    TileCfg<3>::NT, TileCfg<4>::NT, TileCfg<5>::NT};
+                                    TileCfg<3>::NT, TileCfg<4>::NT, TileCfg<5>::NT,
+                                    TileCfg<6>::NT, TileCfg<7>::NT};
   return nt[cfg];
 }
 
-template <typename R, int CFG, int SCHEME>
+template <typename R, int CFG, int SCHEME, bool OS>
 hipError_t launch_sweep_scheme(int dir, const SweepArgs& a, int64_t nwg, hipStream_t s) {
   using C = TileCfg<CFG>;
   dim3 grid((unsigned)nwg);
   if constexpr (SCHEME == kOriginal && sizeof(R) == 8) {
     if (dir == 0)
-      hipLaunchKernelGGL((k_sweep_w3<0, R, C::TW, C::TS, C::NT>), grid, dim3(C::NT), 0, s, a);
+      hipLaunchKernelGGL((k_sweep_w3<0, R, C::TW, C::TS, C::NT, OS>), grid, dim3(C::NT), 0, s, a);
     else if (dir == 1)
-      hipLaunchKernelGGL((k_sweep_w3<1, R, C::TW, C::TS, C::NT>), grid, dim3(C::NT), 0, s, a);
+      hipLaunchKernelGGL((k_sweep_w3<1, R, C::TW, C::TS, C::NT, OS>), grid, dim3(C::NT), 0, s, a);
     else
-      hipLaunchKernelGGL((k_sweep_w3<2, R, C::TW, C::TS, C::NT>), grid, dim3(C::NT), 0, s, a);
+      hipLaunchKernelGGL((k_sweep_w3<2, R, C::TW, C::TS, C::NT, OS>), grid, dim3(C::NT), 0, s, a);
     return hipGetLastError();
   }
   if (dir == 0)
-    hipLaunchKernelGGL((k_sweep<0, R, C::TW, C::TS, C::NT, SCHEME>), grid, dim3(C::NT), 0, s, a);
+    hipLaunchKernelGGL((k_sweep<0, R, C::TW, C::TS, C::NT, SCHEME, OS>), grid, dim3(C::NT), 0, s, a);
   else if (dir == 1)
-    hipLaunchKernelGGL((k_sweep<1, R, C::TW, C::TS, C::NT, SCHEME>), grid, dim3(C::NT), 0, s, a);
+    hipLaunchKernelGGL((k_sweep<1, R, C::TW, C::TS, C::NT, SCHEME, OS>), grid, dim3(C::NT), 0, s, a);
   else
-    hipLaunchKernelGGL((k_sweep<2, R, C::TW, C::TS, C::NT, SCHEME>), grid, dim3(C::NT), 0, s, a);
+    hipLaunchKernelGGL((k_sweep<2, R, C::TW, C::TS, C::NT, SCHEME, OS>), grid, dim3(C::NT), 0, s, a);
   return hipGetLastError();
 }
 
 template <typename R, int CFG>
 hipError_t launch_sweep_cfg(int dir, const SweepArgs& a, int64_t nwg, hipStream_t s) {
-  return a.c.ph.scheme == kOriginal ? launch_sweep_scheme<R, CFG, kOriginal>(dir, a, nwg, s)
-                                    : launch_sweep_scheme<R, CFG, kModified>(dir, a, nwg, s);
+  const bool os = a.b.one_sided != 0;
+  if (a.c.ph.scheme == kOriginal)
+    return os ? launch_sweep_scheme<R, CFG, kOriginal, true>(dir, a, nwg, s)
+              : launch_sweep_scheme<R, CFG, kOriginal, false>(dir, a, nwg, s);
+  return os ? launch_sweep_scheme<R, CFG, kModified, true>(dir, a, nwg, s)
+            : launch_sweep_scheme<R, CFG, kModified, false>(dir, a, nwg, s);
 }
 
 template <typename R>
@@ -828,35 +926,47 @@ hipError_t launch_sweep(int dir, SweepArgs a, hipStream_t s, int cfg) {
     case 3: return launch_sweep_cfg<R, 3>(dir, a, nwg, s);
     case 4: return launch_sweep_cfg<R, 4>(dir, a, nwg, s);
     case 5: return launch_sweep_cfg<R, 5>(dir, a, nwg, s);
+    case 6: return launch_sweep_cfg<R, 6>(dir, a, nwg, s);
+    case 7: return launch_sweep_cfg<R, 7>(dir, a, nwg, s);
   }
   return hipErrorInvalidValue;
 }
 template hipError_t launch_sweep<double>(int, SweepArgs, hipStream_t, int);
 template hipError_t launch_sweep<float>(int, SweepArgs, hipStream_t, int);
 
-template <typename R, int CFG, bool P>
-hipError_t launch_sweep_batch_cfg(int dir, const SweepBlock* blocks, const SweepCommon& c, const TileList& tl, int nwg,
-                                  hipStream_t s) {
+template <typename R, int CFG, bool P, bool OS>
+hipError_t launch_sweep_batch_os(int dir, const SweepBlock* blocks, const SweepCommon& c, const TileList& tl, int nwg,
+                                 hipStream_t s) {
   using C = TileCfg<CFG>;
   if (c.ph.scheme == kOriginal) {
     // the original scheme runs one workgroup per tile (the persistent schedule is not built
     // for it); in FP64 at three waves per SIMD like its single-block kernels
     if (P) return hipErrorInvalidValue;
     if (dir == 0)
-      hipLaunchKernelGGL((k_sweep_batch_orig<0, R, C::TW, C::TS, C::NT>), dim3(nwg), dim3(C::NT), 0, s, blocks, c, tl);
+      hipLaunchKernelGGL((k_sweep_batch_orig<0, R, C::TW, C::TS, C::NT, OS>), dim3(nwg), dim3(C::NT), 0, s, blocks, c, tl);
     else if (dir == 1)
-      hipLaunchKernelGGL((k_sweep_batch_orig<1, R, C::TW, C::TS, C::NT>), dim3(nwg), dim3(C::NT), 0, s, blocks, c, tl);
+      hipLaunchKernelGGL((k_sweep_batch_orig<1, R, C::TW, C::TS, C::NT, OS>), dim3(nwg), dim3(C::NT), 0, s, blocks, c, tl);
     else
-      hipLaunchKernelGGL((k_sweep_batch_orig<2, R, C::TW, C::TS, C::NT>), dim3(nwg), dim3(C::NT), 0, s, blocks, c, tl);
+      hipLaunchKernelGGL((k_sweep_batch_orig<2, R, C::TW, C::TS, C::NT, OS>), dim3(nwg), dim3(C::NT), 0, s, blocks, c, tl);
     return hipGetLastError();
   }
-  if (dir == 0)
-    hipLaunchKernelGGL((k_sweep_batch<0, R, C::TW, C::TS, C::NT, P>), dim3(nwg), dim3(C::NT), 0, s, blocks, c, tl);
-  else if (dir == 1)
-    hipLaunchKernelGGL((k_sweep_batch<1, R, C::TW, C::TS, C::NT, P>), dim3(nwg), dim3(C::NT), 0, s, blocks, c, tl);
-  else
-    hipLaunchKernelGGL((k_sweep_batch<2, R, C::TW, C::TS, C::NT, P>), dim3(nwg), dim3(C::NT), 0, s, blocks, c, tl);
-  return hipGetLastError();
+  if constexpr (P && OS) {
+    return hipErrorInvalidValue;
+  } else {
+    if (dir == 0)
+      hipLaunchKernelGGL((k_sweep_batch<0, R, C::TW, C::TS, C::NT, P, OS>), dim3(nwg), dim3(C::NT), 0, s, blocks, c, tl);
+    else if (dir == 1)
+      hipLaunchKernelGGL((k_sweep_batch<1, R, C::TW, C::TS, C::NT, P, OS>), dim3(nwg), dim3(C::NT), 0, s, blocks, c, tl);
+    else
+      hipLaunchKernelGGL((k_sweep_batch<2, R, C::TW, C::TS, C::NT, P, OS>), dim3(nwg), dim3(C::NT), 0, s, blocks, c, tl);
+    return hipGetLastError();
+  }
+}
+template <typename R, int CFG, bool P>
+hipError_t launch_sweep_batch_cfg(int dir, const SweepBlock* blocks, const SweepCommon& c, const TileList& tl, int nwg,
+                                  hipStream_t s) {
+  return c.one_sided ? launch_sweep_batch_os<R, CFG, P, true>(dir, blocks, c, tl, nwg, s)
+                     : launch_sweep_batch_os<R, CFG, P, false>(dir, blocks, c, tl, nwg, s);
 }
 
 // persist: nwg workgroups stride through the list; otherwise nwg must equal the tile count
@@ -871,6 +981,8 @@ hipError_t launch_sweep_batch(int dir, int cfg, bool persist, const SweepBlock* 
       case 3: return launch_sweep_batch_cfg<R, 3, true>(dir, blocks, c, tl, nwg, s);
       case 4: return launch_sweep_batch_cfg<R, 4, true>(dir, blocks, c, tl, nwg, s);
       case 5: return launch_sweep_batch_cfg<R, 5, true>(dir, blocks, c, tl, nwg, s);
+      case 6: return launch_sweep_batch_cfg<R, 6, true>(dir, blocks, c, tl, nwg, s);
+      case 7: return launch_sweep_batch_cfg<R, 7, true>(dir, blocks, c, tl, nwg, s);
     }
   } else {
     switch (cfg) {
@@ -880,6 +992,8 @@ hipError_t launch_sweep_batch(int dir, int cfg, bool persist, const SweepBlock* 
       case 3: return launch_sweep_batch_cfg<R, 3, false>(dir, blocks, c, tl, nwg, s);
       case 4: return launch_sweep_batch_cfg<R, 4, false>(dir, blocks, c, tl, nwg, s);
       case 5: return launch_sweep_batch_cfg<R, 5, false>(dir, blocks, c, tl, nwg, s);
+      case 6: return launch_sweep_batch_cfg<R, 6, false>(dir, blocks, c, tl, nwg, s);
+      case 7: return launch_sweep_batch_cfg<R, 7, false>(dir, blocks, c, tl, nwg, s);
     }
   }
   return hipErrorInvalidValue;
@@ -1017,7 +1131,8 @@ __global__ __launch_bounds__(256) void k_ghost_fill(const BcSeg* segs, BcArgs A)
       const double ke = 0.5 * (u * u + v * v + w * w);
       const double p = gm1 * (Q[4 * pl + pm] - rho * ke);
       const double T = A.gamma * p * rinv;
-      const double Tg = 2.0 * A.t_wall - T;
+      // reflection of T - T_w, floored at T_w / 2 (positive ghost density)
+      const double Tg = fmax(2.0 * A.t_wall - T, 0.5 * A.t_wall);
       const double rg = A.gamma * p / Tg;
       Q[pg] = rg;
       Q[pl + pg] = -rg * u;
@@ -1078,8 +1193,8 @@ template hipError_t launch_visc_ghost<float>(const BcSeg*, int, int, const PtrTa
 // =====================================================================================
 __global__ __launch_bounds__(256) void k_dt_max(Geom g, const double* q, const double* met, double gamma,
                                                 unsigned long long* acc) {
-  __shared__ double red[256];
-  double best = 0.0;
+  __shared__ uint64_t red[256];
+  uint64_t best = 0;  // bit pattern of the largest spectral radius (+0.0 to start)
   const int64_t total = (int64_t)g.ni * g.nj * g.nk;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
     const int i = (int)(e % g.ni);
@@ -1097,16 +1212,19 @@ __global__ __launch_bounds__(256) void k_dt_max(Geom g, const double* q, const d
                    az = J * met[(3 * d + 2) * g.plane + p];
       sum += fabs(ax * u + ay * v + az * w) + c * sqrt(ax * ax + ay * ay + az * az);
     }
-    best = fmax(best, sum);
+    // a non-finite point (NaN or infinite spectral radius) becomes the quiet-NaN pattern,
+    // which orders above +inf as an unsigned integer, so the maximum keeps it
+    const uint64_t bits = sum <= 1.7976931348623157e308 ? (uint64_t)__double_as_longlong(sum) : 0x7ff8000000000000ull;
+    best = best > bits ? best : bits;
   }
   red[threadIdx.x] = best;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+    if ((int)threadIdx.x < h) red[threadIdx.x] = red[threadIdx.x] > red[threadIdx.x + h] ? red[threadIdx.x] : red[threadIdx.x + h];
     __syncthreads();
   }
   // non-negative doubles order like their bit patterns
-  if (threadIdx.x == 0) atomicMax(acc, (unsigned long long)__double_as_longlong(red[0]));
+  if (threadIdx.x == 0) atomicMax(acc, (unsigned long long)red[0]);
 }
 
 hipError_t launch_dt_max(const Geom& g, const double* q, const double* met, double gamma, unsigned long long* acc,

@@ -38,14 +38,18 @@ struct ViscArgs {
   int kc;     // planes per tile (set by visc_tiling)
   int periodic;  // bit d: the block is periodic with itself along d, the kernel fills
                  // the direction-d flux halos across the d-faces
+  int one_sided;  // bit 2*axis + side (side 1: high face): a physical face whose viscous
+                  // derivatives use the one-sided closure (the gradients at the three
+                  // nodes next to it)
 };
 template <typename R>
 hipError_t launch_visc(ViscArgs a, hipStream_t s);
 // dst[e] = float(src[e]) for e < n
 hipError_t launch_round(const double* src, float* dst, int64_t n, hipStream_t s);
-// batched viscous prepass over the tiles (64 x 8 columns, a chunk of k planes) of every block
+// batched viscous prepass over the tiles (64 x 16 columns, a chunk of k planes) of every
+// block; one_sided: some block has faces with the one-sided closure
 template <typename R>
-hipError_t launch_visc_batch(const ViscArgs* args_dev, const TileList& tl, hipStream_t s);
+hipError_t launch_visc_batch(const ViscArgs* args_dev, const TileList& tl, bool one_sided, hipStream_t s);
 void visc_tiling(const Geom& g, int min_tiles, int* kc, int* tiles);
 
 // ---- direction sweep ----------------------------------------------------------------
@@ -62,6 +66,8 @@ struct SweepBlock {
   const double* qn;   // RK base state (kOutRK)
   const double* dt_field;  // a time step per point (one plane) in place of the scalar one, or null
   int tiles_c1, tiles_d, tile_len;  // filled by the launcher
+  int one_sided;  // faces with the one-sided viscous closure (bit 2*axis + side): the
+                  // viscous derivative at the three nodes next to them
 };
 // part shared by every block of a launch
 struct SweepCommon {
@@ -70,6 +76,8 @@ struct SweepCommon {
   double ca, cb, cc;     // Qout = ca Qn + cb Q + cc dt J Rtilde
   Phys ph;
   int do_inv, do_vis, has_prev, out_kind;
+  int one_sided;  // some block of the launch has faces with the one-sided viscous closure
+                  // (selects the kernels that evaluate it; batched launches only)
 };
 struct SweepArgs {
   SweepCommon c;
@@ -79,7 +87,7 @@ struct SweepArgs {
 // sweep carries the output (R or the RK combination); its extra loads are cheapest along
 // xi, whose stencils stay within rows.
 constexpr int kSweepOrder[3] = {2, 1, 0};
-constexpr int kTileCfgs = 6;
+constexpr int kTileCfgs = 8;
 // shape of tile configuration cfg (lines across, nodes along the sweep, threads)
 void tile_shape(int cfg, int* tw, int* ts, int* nt);  // sweep tile configurations (see TileCfg in cfd_kernels.hip)
 // tiles of one block for direction dir under configuration cfg

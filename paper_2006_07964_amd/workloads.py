@@ -78,6 +78,7 @@ class Workload:
     t_wall: float = 1.0
     qinf: Tuple[float, float, float, float, float] = (1.0, 0.0, 0.0, 0.0, 1.0 / (GAMMA * (GAMMA - 1.0)))
     description: str = ""
+    visc_closure: int = 0  # viscous terms at wall / far-field faces: 0 reflected ghosts, 1 one-sided
 
     @property
     def points(self) -> int:

@@ -65,8 +65,12 @@ int main(void) {
 
 
 def test_argument_errors_without_gpu(lib):
+    # WENO epsilon floors of Eq 15's common-denominator form: below 1e-8 in mixed
+    # precision (eps^4 leaves the normal FP32 range), below 1e-30 in FP64 (eps^8 leaves it)
     for bad in (dict(ni=5), dict(ld_i=10), dict(precision=7), dict(weights=3), dict(gamma=1.0),
-                dict(bc=(0, 2, 0, 0, 0, 0)), dict(scheme=2)):
+                dict(bc=(0, 2, 0, 0, 0, 0)), dict(scheme=2), dict(visc_closure=2), dict(visc_closure=-1),
+                dict(weno_eps=1e-12, precision=B.CFD_MIXED), dict(weno_eps=9.9e-9, precision=B.CFD_MIXED),
+                dict(weno_eps=1e-40), dict(weno_eps=9.9e-31)):
         kw = dict(ni=16, nj=16, nk=16)
         kw.update(bad)
         ni = kw.pop("ni")

@@ -2,14 +2,17 @@
 
 Bar: states after every RK step within a normwise relative 1e-12 per conserved quantity
 (density, momentum vector, energy; see tests/_gpu.normwise); the metrics
-within 1e-13.  Right-hand sides are compared over the whole vector: within 1e-12 with the
-ideal (linear) weights (rounding of O(1) fluxes whose differences are O(1e-2), measured
-~1e-13), and within 1e-10 with the WENO-JS weights of Eq 15, whose
-normalisation divides by (eps + beta)^2 with eps = 1e-6 and so amplifies last-bit
-differences in beta by up to ~2/eps relative: a weight moves by ~2e-10 where beta << eps,
-the interpolated value by that times the spread of the sub-stencil values (<~ 0.1), i.e.
-~2e-11 of the flux scale or ~5e-11 of max|R|; one RK stage multiplies that by
-dt*|R|/|Q| ~ 1e-2, well inside the 1e-12 state bar.
+within 1e-13.  Right-hand sides are compared per conserved quantity (normwise): within
+1e-12 with the ideal (linear) weights (rounding of O(1) fluxes whose differences are
+O(1e-2), measured ~1e-13), and within 5e-11 with the WENO-JS weights of Eq 15.  The
+oracle evaluates the smoothness indicators in the expanded quadratic form printed as
+Eq 17, whose rounding is absolute, about 30 * 1.1e-16 * |V|^2 (the GPU forms the same
+beta from squared differences, with a relative rounding).  Where beta << eps = 1e-6 the
+weights are set by eps + beta, so that difference moves a weight by ~2 * 3.3e-15 |V|^2 /
+eps ~ 7e-9 |V|^2 relative, and the interpolated value by that times the spread of the
+sub-stencil values, which is below ~1e-3 |V| wherever beta < eps: ~1e-11 of the flux scale
+for |V| ~ 1 to 2 (measured 2e-11 on the vortex case).  One RK stage multiplies an RHS
+error by dt*|R|/|Q| ~ 1e-2, well inside the 1e-12 state bar.
 """
 import numpy as np
 import pytest
@@ -22,8 +25,8 @@ from tests._gpu import DevBlock, normwise, per_component, vector_norm_err
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-12        # states after an RK step, per field
-TOL_RHS_JS = 1e-10  # right-hand side with WENO-JS weights, whole vector
-TOL_RHS_LIN = 1e-12  # right-hand side with ideal weights, whole vector
+TOL_RHS_JS = 5e-11  # right-hand side with WENO-JS weights, per conserved quantity
+TOL_RHS_LIN = 1e-12  # right-hand side with ideal weights, per conserved quantity
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -73,8 +76,9 @@ def test_rhs(size, mask):
     try:
         got = dev.rhs(mask)
         ref = O.rhs(c, met, wl.blocks[0].q, mask)
-        print(size, mask, vector_norm_err(got, ref), normwise(got, ref))
-        assert vector_norm_err(got, ref) < TOL_RHS_JS
+        err = normwise(got, ref)
+        print(size, mask, "whole vector", vector_norm_err(got, ref), "per quantity", err)
+        assert np.all(err < TOL_RHS_JS), err
     finally:
         dev.close()
 
@@ -86,9 +90,9 @@ def test_rhs_weights_and_euler(weights):
     try:
         got = dev.rhs()
         ref = O.rhs(c, met, wl.blocks[0].q)
-        err = vector_norm_err(got, ref)
-        print(weights, err)
-        assert err < (TOL_RHS_LIN if weights == B.CFD_WENO_LINEAR else TOL_RHS_JS)
+        err = normwise(got, ref)
+        print(weights, "whole vector", vector_norm_err(got, ref), "per quantity", err)
+        assert np.all(err < (TOL_RHS_LIN if weights == B.CFD_WENO_LINEAR else TOL_RHS_JS)), err
     finally:
         dev.close()
 
