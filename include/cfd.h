@@ -246,6 +246,16 @@ int cfd_block_set_local_dt(cfd_block* b, const double* dt_field);
  * CFD_ERR_NONFINITE (a norm is not finite).                                             */
 int cfd_residual(cfd_block* const* blocks, int nb, const double* const* A, const double* const* B,
                  double scale, double* out);
+/* cfd_residual for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight time loops, harnesses that forbid allocation): the same norms, the same
+ * kernels and summation order (bitwise the same result), but the partial rows live in a
+ * fixed scratch array of the library (1.31 MB per device: 64 blocks x 256 rows x 10
+ * doubles + 10), found once per device at the first call; no hipMalloc or hipFree, ever.
+ * Every call on one GPU shares that array: calls that overlap on one device (different
+ * host threads, or streams not ordered with each other) race and must not be made.
+ * Arguments, ordering and synchronisation as cfd_residual; nb above 64 gives CFD_ERR_ARG.  */
+int cfd_residual_noalloc(cfd_block* const* blocks, int nb, const double* const* A, const double* const* B,
+                         double scale, double* out);
 /* *ok = 1 if every interior value of Q is finite, else 0 (and CFD_ERR_NONFINITE).
  * Synchronises.                                                                        */
 int cfd_check_finite(cfd_block* b, const double* Q, int* ok);

@@ -89,6 +89,8 @@ def lib():
         "cfd_dt_local": ([C.POINTER(_VP), C.c_int, C.POINTER(_VP), C.c_double, C.POINTER(_VP)], C.c_int),
         "cfd_block_set_local_dt": ([_VP, _VP], C.c_int),
         "cfd_residual": ([C.POINTER(_VP), C.c_int, C.POINTER(_VP), C.POINTER(_VP), C.c_double, _DP], C.c_int),
+        "cfd_residual_noalloc": ([C.POINTER(_VP), C.c_int, C.POINTER(_VP), C.POINTER(_VP), C.c_double, _DP],
+                                 C.c_int),
         "cfd_check_finite": ([_VP, _VP, C.POINTER(C.c_int)], C.c_int),
         "cfd_sync": ([_VP], C.c_int),
         "cfd_batch_create": ([C.POINTER(_VP), C.c_int, _VP, _VP, C.POINTER(_VP)], C.c_int),
@@ -247,6 +249,15 @@ def cfd_residual(blocks: Sequence[int], a: Sequence, b: Optional[Sequence] = Non
     arr = (_VP * len(blocks))(*blocks)
     out = (C.c_double * 10)()
     _check(lib().cfd_residual(arr, len(blocks), _vp_array(a), None if b is None else _vp_array(b), scale, out))
+    return list(out[:5]), list(out[5:])
+
+
+def cfd_residual_noalloc(blocks: Sequence[int], a: Sequence, b: Optional[Sequence] = None, scale: float = 1.0):
+    """cfd_residual through the library's fixed scratch (no device allocation)."""
+    arr = (_VP * len(blocks))(*blocks)
+    out = (C.c_double * 10)()
+    _check(lib().cfd_residual_noalloc(arr, len(blocks), _vp_array(a), None if b is None else _vp_array(b), scale,
+                                      out))
     return list(out[:5]), list(out[5:])
 
 

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -489,6 +490,34 @@ int check_rk_args(cfd_block* b, int stage, const double* Qn, const double* Qcur,
   return CFD_OK;
 }
 
+// Residual scratch of cfd_residual_noalloc: kResGroups partial rows of up to kMaxBlocks
+// blocks and the 10 results, in a file-scope device array (1.31 MB per device, held until
+// the process ends).  Host code never uses the array's name as an address: the device
+// address of each GPU's copy comes from hipGetSymbolAddress, taken once per device with
+// that device current.
+constexpr size_t kResScratch = (size_t)kMaxBlocks * kResGroups * 10 + 10;
+static __device__ __align__(256) double scratch[kResScratch];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+int residual_scratch(int device, double** ptr) {
+  if (device < 0 || device >= kMaxDevices) return fail(CFD_ERR_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur), "hipGetDevice");
+    if (cur != device) HIP_TRY(hipSetDevice(device), "hipSetDevice");
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(residual scratch)");
+    g_scratch_ptr[device] = static_cast<double*>(p);
+  }
+  *ptr = g_scratch_ptr[device];
+  return CFD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -802,6 +831,36 @@ int cfd_residual(cfd_block* const* blocks, int nb, const double* const* A, const
             "residual launch");
   double* res_out = b0->res_dev + (int64_t)kMaxBlocks * kResGroups * 10;
   HIP_TRY(launch_res_final(b0->res_dev, nb * kResGroups, 1.0 / (double)npts, res_out, b0->stream), "residual launch");
+  HIP_TRY(hipMemcpyAsync(out, res_out, 10 * sizeof(double), hipMemcpyDeviceToHost, b0->stream), "copy residual");
+  HIP_TRY(hipStreamSynchronize(b0->stream), "stream synchronize");
+  for (int v = 0; v < 10; ++v)
+    if (!std::isfinite(out[v])) return fail(CFD_ERR_NONFINITE, "non-finite residual");
+  return CFD_OK;
+}
+
+int cfd_residual_noalloc(cfd_block* const* blocks, int nb, const double* const* A, const double* const* Bm,
+                         double scale, double* out) {
+  if (!blocks || nb <= 0 || nb > kMaxBlocks || !A || !out) return fail(CFD_ERR_ARG, "need 1..64 blocks, A and out");
+  int64_t npts = 0;
+  for (int n = 0; n < nb; ++n) {
+    if (!blocks[n] || !A[n]) return fail(CFD_ERR_ARG, "null block or array");
+    npts += (int64_t)blocks[n]->g.ni * blocks[n]->g.nj * blocks[n]->g.nk;
+  }
+  if (!std::isfinite(scale)) return fail(CFD_ERR_ARG, "scale must be finite");
+  cfd_block* b0 = blocks[0];
+  double* part = nullptr;
+  int rc = residual_scratch(b0->device, &part);
+  if (rc != CFD_OK) return rc;
+  rc = order_on_first(blocks, nb);
+  if (rc != CFD_OK) return rc;
+  // every partial row of the nb blocks is written before the final reduction reads it, so
+  // the scratch needs no clearing
+  for (int n = 0; n < nb; ++n)
+    HIP_TRY(launch_res_partial(blocks[n]->g, A[n], Bm ? Bm[n] : nullptr, scale, part + (int64_t)n * kResGroups * 10,
+                               b0->stream),
+            "residual launch");
+  double* res_out = part + (int64_t)kMaxBlocks * kResGroups * 10;
+  HIP_TRY(launch_res_final(part, nb * kResGroups, 1.0 / (double)npts, res_out, b0->stream), "residual launch");
   HIP_TRY(hipMemcpyAsync(out, res_out, 10 * sizeof(double), hipMemcpyDeviceToHost, b0->stream), "copy residual");
   HIP_TRY(hipStreamSynchronize(b0->stream), "stream synchronize");
   for (int v = 0; v < 10; ++v)
