@@ -118,9 +118,10 @@ struct ProfScope {
 // block
 // =====================================================================================
 // tile shapes of a block's own sweeps until cfd_block_set_tiles, [FP64 / mixed][direction]
-// (measured on the 512 x 512 x 384 channel): 4 lines x 58 nodes along xi, 8 x 30 along eta
-// and zeta in FP64 (16 x 14 in mixed precision), 256 threads each
-constexpr int kDefaultTiles[2][3] = {{5, 6, 6}, {5, 2, 2}};
+// (measured on the 512 x 512 x 384 channel): 4 lines x 58 nodes along xi; 8 x 30 along eta
+// and zeta in FP64; 16 x 14 along eta and 16 x 30 (512 threads) along zeta in mixed
+// precision
+constexpr int kDefaultTiles[2][3] = {{5, 6, 6}, {5, 2, 0}};
 
 struct cfd_block {
   cfd_block_desc d;
