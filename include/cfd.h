@@ -118,6 +118,24 @@ typedef struct cfd_interface {
   int32_t orient;               /* 0..7 as above                                       */
 } cfd_interface;
 
+/* A patch of a block connection (Sec. 3: the domain may be split arbitrarily, without the
+ * limitation of one-to-one block connection, and connecting and physical faces may be
+ * defined anywhere on a block's faces).  The rectangle of face_a of block_a that starts at
+ * node (a_lo[0], a_lo[1]) and spans (n[0], n[1]) nodes along a's tangential axes t1 < t2
+ * is joined node to node with the rectangle of face_b of block_b that starts at
+ * (b_lo[0], b_lo[1]) along b's tangential axes t1 < t2.  orient is that of cfd_interface
+ * applied inside the two rectangles: with a reversal bit set, index p along a's axis
+ * (counted from a_lo) lands on the partner axis at the rectangle's far end minus p.  Ghost
+ * layer m (1..3) beyond a's rectangle is interior layer m-1 inside b's, and the other way
+ * round.  A cfd_interface is the patch with zero corners and the whole face.             */
+typedef struct cfd_patch {
+  int32_t block_a, face_a;
+  int32_t a_lo[2], n[2];        /* corner and extents on face_a (along a's t1, t2)       */
+  int32_t block_b, face_b;
+  int32_t b_lo[2];              /* corner on face_b (along b's t1, t2)                   */
+  int32_t orient;               /* 0..7 as for cfd_interface                             */
+} cfd_patch;
+
 typedef struct cfd_block cfd_block;
 typedef struct cfd_exchange cfd_exchange;
 typedef struct cfd_batch cfd_batch;
@@ -192,6 +210,19 @@ int cfd_rk_sweeps(cfd_block* b, int stage, double dt, const double* Qn, const do
  * reverses handedness, or a face used twice.                                          */
 int cfd_exchange_create(cfd_block* const* blocks, int nb, const cfd_interface* ifc, int nifc,
                         cfd_exchange** out);
+/* The same for blocks joined by patches (np >= 0; p may be NULL when np is 0).  A face of
+ * kind CFD_BC_INTERFACE must be covered by patches completely; a CFD_BC_WALL /
+ * CFD_BC_FARFIELD / CFD_BC_FARFIELD_CHAR face may be covered in part: its covered nodes
+ * take the connected block's values, the others keep the wall reset, the ghost fill and
+ * the reflected viscous ghosts; CFD_BC_PERIODIC faces take no patch.  Blocks with a patch
+ * on a physical face use the split form (cfd_viscous_fluxes, the viscous exchange, the
+ * sweeps) or the batched form, like blocks with interface faces.
+ * Errors: CFD_ERR_ARG on an index or a rectangle out of range, a node covered twice, an
+ * interface face left partly uncovered, a patch on a periodic face, orient outside 0..7 or
+ * a map that reverses handedness; CFD_ERR_UNSUPPORTED for a patch on a physical face of a
+ * block with the one-sided viscous closure (it treats the whole face as physical).       */
+int cfd_exchange_create_patched(cfd_block* const* blocks, int nb, const cfd_patch* p, int np,
+                                cfd_exchange** out);
 int cfd_exchange_destroy(cfd_exchange* x);
 /* Refill halos by on-device copies (Sec. 4.2: blocks of one process exchange on the
  * device).  field_set CFD_FIELDS_Q: block_bufs[b] is block b's caller-owned Q (5 planes);

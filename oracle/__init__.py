@@ -47,6 +47,13 @@ class Iface(C.Structure):
                 ("orient", C.c_int)]
 
 
+class Patch(C.Structure):
+    """A rectangle of face_a of block_a joined node to node to a rectangle of face_b of
+    block_b (see oracle_patch in oracle.h)."""
+    _fields_ = [("block_a", C.c_int), ("face_a", C.c_int), ("a_lo", C.c_int * 2), ("n", C.c_int * 2),
+                ("block_b", C.c_int), ("face_b", C.c_int), ("b_lo", C.c_int * 2), ("orient", C.c_int)]
+
+
 _lib = None
 
 
@@ -94,6 +101,9 @@ def lib():
         L.oracle_exchange.argtypes = [cp, C.c_int, PP, C.c_int, C.POINTER(Iface), C.c_int]
         L.oracle_rhs_multi.argtypes = [cp, C.c_int, PP, PP, PP, C.c_uint, C.POINTER(Iface), C.c_int]
         L.oracle_rk_step_multi.argtypes = [cp, C.c_int, PP, C.c_double, PP, C.POINTER(Iface), C.c_int]
+        L.oracle_halo_patched.argtypes = [cp, C.c_int, PP, PP, C.POINTER(Patch), C.c_int]
+        L.oracle_rhs_patched.argtypes = [cp, C.c_int, PP, PP, PP, C.c_uint, C.POINTER(Patch), C.c_int]
+        L.oracle_rk_step_patched.argtypes = [cp, C.c_int, PP, C.c_double, PP, C.POINTER(Patch), C.c_int]
         _lib = L
     return _lib
 
@@ -319,4 +329,48 @@ def rk_step_multi(cfgs, mets, dt, qs, ifc):
     rc = lib().oracle_rk_step_multi(cs, len(cfgs), _ptr_array(mets), dt, _ptr_array(out), _ifaces(ifc), len(ifc))
     if rc != 0:
         raise ValueError("oracle_rk_step_multi failed")
+    return out
+
+
+def _patches(patches):
+    arr = (Patch * max(1, len(patches)))()
+    for k, p in enumerate(patches):
+        arr[k].block_a, arr[k].face_a = p.block_a, p.face_a
+        arr[k].a_lo[0], arr[k].a_lo[1] = p.a_lo
+        arr[k].n[0], arr[k].n[1] = p.n
+        arr[k].block_b, arr[k].face_b = p.block_b, p.face_b
+        arr[k].b_lo[0], arr[k].b_lo[1] = p.b_lo
+        arr[k].orient = p.orient
+    return arr
+
+
+def halo_patched(cfgs, mets, qs, patches):
+    """Halos of all blocks as after a stage (wall reset, periodic wraps, patch copies,
+    ghost fills), on copies of qs."""
+    cs = (Cfg * len(cfgs))(*cfgs)
+    out = [np.array(q, dtype=np.float64, copy=True) for q in qs]
+    mp = _ptr_array(mets) if mets is not None else None
+    rc = lib().oracle_halo_patched(cs, len(cfgs), mp, _ptr_array(out), _patches(patches), len(patches))
+    if rc != 0:
+        raise ValueError("oracle_halo_patched: the patches break a rule")
+    return out
+
+
+def rhs_patched(cfgs, mets, qs, patches, mask=ALL):
+    cs = (Cfg * len(cfgs))(*cfgs)
+    rs = [np.zeros(state_shape(c)) for c in cfgs]
+    rc = lib().oracle_rhs_patched(cs, len(cfgs), _ptr_array(mets), _ptr_array(qs), _ptr_array(rs), mask,
+                                  _patches(patches), len(patches))
+    if rc != 0:
+        raise ValueError("oracle_rhs_patched failed")
+    return rs
+
+
+def rk_step_patched(cfgs, mets, dt, qs, patches):
+    cs = (Cfg * len(cfgs))(*cfgs)
+    out = [np.array(q, copy=True) for q in qs]
+    rc = lib().oracle_rk_step_patched(cs, len(cfgs), _ptr_array(mets), dt, _ptr_array(out), _patches(patches),
+                                      len(patches))
+    if rc != 0:
+        raise ValueError("oracle_rk_step_patched failed")
     return out

@@ -444,6 +444,18 @@ static void face_geom(const oracle_cfg* c, int f, int* axis, int* wall_idx, int*
   *wall_idx = (f % 2) ? npts(c, *axis) - 1 : 0;
 }
 
+/* Nodes of face f that a patched connection covers (the multi-block driver's map per
+ * face, indexed p1 + n1 * p2 with p1, p2 the node's indices along the face's tangential
+ * axes t1 < t2); cov == NULL or cov[f] == NULL: none.  Covered nodes take the values of
+ * the connected block instead of the physical treatment.                               */
+static int face_covered(const oracle_cfg* c, const unsigned char* const* cov, int f, const int* idx) {
+  int t1, t2;
+  if (!cov || !cov[f]) return 0;
+  t1 = f / 2 == 0 ? 1 : 0;
+  t2 = f / 2 == 2 ? 1 : 2;
+  return cov[f][idx[t1] + (long)npts(c, t1) * idx[t2]] != 0;
+}
+
 /* Reading (physical boundaries, not specified by the paper): the boundary node itself
  * is part of the interior.  Isothermal no-slip wall: after every stage the wall node gets
  * zero velocity and T = T_w at its own density (oracle_wall_reset, before any halo copy);
@@ -451,7 +463,7 @@ static void face_geom(const oracle_cfg* c, int f, int* axis, int* wall_idx, int*
  * T_g = max(2 T_w - T_m, T_w / 2).  Far field: ghosts hold qinf (oracle_bc_fill).
  * Pinned by closed forms of Eq 1 next to a wall: the right-hand side of a shear mode and
  * of a conduction mode between isothermal walls, and the decay rate of the shear mode.  */
-void oracle_wall_reset(const oracle_cfg* c, double* Q) {
+static void wall_reset_cov(const oracle_cfg* c, double* Q, const unsigned char* const* cov) {
   const dims_t sd = state_dims(c);
   int f;
   for (f = 0; f < 6; ++f) {
@@ -467,6 +479,7 @@ void oracle_wall_reset(const oracle_cfg* c, double* Q) {
         idx[(axis + 1) % 3] = a;
         idx[(axis + 2) % 3] = b;
         idx[axis] = w;
+        if (face_covered(c, cov, f, idx)) continue;
         pw = sidx(&sd, idx[0], idx[1], idx[2]);
         Q[1 * sd.plane + pw] = 0.0;
         Q[2 * sd.plane + pw] = 0.0;
@@ -475,6 +488,8 @@ void oracle_wall_reset(const oracle_cfg* c, double* Q) {
       }
   }
 }
+
+void oracle_wall_reset(const oracle_cfg* c, double* Q) { wall_reset_cov(c, Q, NULL); }
 
 /* Characteristic far field (reading; the paper names no far-field treatment): locally
  * one-dimensional Riemann invariants along the outward unit normal n.  From the boundary
@@ -519,9 +534,7 @@ void oracle_char_farfield(const double* qb, const double* n, const double* qf, d
   qg[4] = p / (gamma - 1.0) + 0.5 * rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
 }
 
-void oracle_bc_fill(const oracle_cfg* c, double* Q) { oracle_bc_fill_met(c, NULL, Q); }
-
-void oracle_bc_fill_met(const oracle_cfg* c, const double* met, double* Q) {
+static void bc_fill_cov(const oracle_cfg* c, const double* met, double* Q, const unsigned char* const* cov) {
   const dims_t sd = state_dims(c);
   int f;
   for (f = 0; f < 6; ++f) {
@@ -542,6 +555,7 @@ void oracle_bc_fill_met(const oracle_cfg* c, const double* met, double* Q) {
           idx[(axis + 1) % 3] = a;
           idx[(axis + 2) % 3] = b;
           idx[axis] = w;
+          if (face_covered(c, cov, f, idx)) continue;
           pw = sidx(&sd, idx[0], idx[1], idx[2]);
           for (n = 0; n < 5; ++n) qb[n] = Q[n * sd.plane + pw];
           for (n = 0; n < 3; ++n) nv[n] = met[(3 * axis + n) * sd.plane + pw];
@@ -564,6 +578,8 @@ void oracle_bc_fill_met(const oracle_cfg* c, const double* met, double* Q) {
         int idx[3];
         idx[(axis + 1) % 3] = a;
         idx[(axis + 2) % 3] = b;
+        idx[axis] = w;
+        if (face_covered(c, cov, f, idx)) continue;
         for (m = 1; m <= HS; ++m) {
           long pg, pm;
           idx[axis] = w + out * m;
@@ -593,6 +609,10 @@ void oracle_bc_fill_met(const oracle_cfg* c, const double* met, double* Q) {
       }
   }
 }
+
+void oracle_bc_fill(const oracle_cfg* c, double* Q) { bc_fill_cov(c, NULL, Q, NULL); }
+
+void oracle_bc_fill_met(const oracle_cfg* c, const double* met, double* Q) { bc_fill_cov(c, met, Q, NULL); }
 
 /* Reading: at a wall or far-field face the ghost values of the viscous flux are the
  * odd reflection about the boundary node, F(w+out*m) = 2 F(w) - F(w-out*m), which keeps
@@ -1047,31 +1067,39 @@ static void face_dirs(int fa, int fb, int orient, int* dir, int* sgn) {
   }
 }
 
-/* Ghost layers beyond face fa of block A from the interior layers inside face fb of
- * block B.  visc = 0: nvar planes copied as they are.  visc = 1: the 12 viscous-flux
- * planes, 4 per index direction (Eqs 5-6 through that direction's hatted metric): A's
- * direction d is B's direction dir[d], so A's planes of d take B's planes of dir[d],
- * with the sign of sgn[d] (a reversed index reverses the hatted metric and the flux).   */
-static void copy_face(const oracle_cfg* ca, double* A, int fa, const oracle_cfg* cb, const double* B,
-                      int fb, int orient, int nvar, int visc) {
+/* Ghost layers beyond the rectangle of face fa of block A that starts at alo and spans n
+ * nodes along A's tangential axes t1 < t2, from the interior layers inside the partner
+ * rectangle of face fb of block B, which starts at blo along B's t1 < t2 (see
+ * oracle_patch).  visc = 0: nvar planes copied as they are.  visc = 1: the 12
+ * viscous-flux planes, 4 per index direction (Eqs 5-6 through that direction's hatted
+ * metric): A's direction d is B's direction dir[d], so A's planes of d take B's planes of
+ * dir[d], with the sign of sgn[d] (a reversed index reverses the hatted metric and the
+ * flux).                                                                               */
+static void copy_patch(const oracle_cfg* ca, double* A, int fa, const int* alo, const int* n,
+                       const oracle_cfg* cb, const double* B, int fb, const int* blo, int orient, int nvar,
+                       int visc) {
   const dims_t da = state_dims(ca), db = state_dims(cb);
   int axa = fa / 2, axb = fb / 2, outa = (fa % 2) ? +1 : -1, outb = (fb % 2) ? +1 : -1;
   int wa = (fa % 2) ? npts(ca, axa) - 1 : 0;
   int wb = (fb % 2) ? npts(cb, axb) - 1 : 0;
   int ta0 = axa == 0 ? 1 : 0, ta1 = axa == 2 ? 1 : 2;
+  int tb0 = axb == 0 ? 1 : 0;
   int dir[3], sgn[3];
+  int lo0, lo1;  /* B's rectangle corner along the axes that A's t1 and t2 run along */
   int a, b, m, v, d;
   face_dirs(fa, fb, orient, dir, sgn);
-  for (b = 0; b < npts(ca, ta1); ++b)
-    for (a = 0; a < npts(ca, ta0); ++a)
+  lo0 = dir[ta0] == tb0 ? blo[0] : blo[1];
+  lo1 = dir[ta1] == tb0 ? blo[0] : blo[1];
+  for (b = 0; b < n[1]; ++b)
+    for (a = 0; a < n[0]; ++a)
       for (m = 1; m <= HS; ++m) {
         int ia[3], ib[3];
         long pa, pb;
-        ia[ta0] = a; ia[ta1] = b; ia[axa] = wa + outa * m;
+        ia[ta0] = alo[0] + a; ia[ta1] = alo[1] + b; ia[axa] = wa + outa * m;
         /* ghost m beyond face fa is interior layer m-1 inside face fb */
         ib[axb] = wb - outb * (m - 1);
-        ib[dir[ta0]] = sgn[ta0] > 0 ? a : npts(cb, dir[ta0]) - 1 - a;
-        ib[dir[ta1]] = sgn[ta1] > 0 ? b : npts(cb, dir[ta1]) - 1 - b;
+        ib[dir[ta0]] = sgn[ta0] > 0 ? lo0 + a : lo0 + n[0] - 1 - a;
+        ib[dir[ta1]] = sgn[ta1] > 0 ? lo1 + b : lo1 + n[1] - 1 - b;
         pa = sidx(&da, ia[0], ia[1], ia[2]);
         pb = sidx(&db, ib[0], ib[1], ib[2]);
         if (!visc) {
@@ -1081,6 +1109,14 @@ static void copy_face(const oracle_cfg* ca, double* A, int fa, const oracle_cfg*
             for (v = 0; v < 4; ++v) A[(4 * d + v) * da.plane + pa] = sgn[d] * B[(4 * dir[d] + v) * db.plane + pb];
         }
       }
+}
+
+/* The whole face fa of A from the whole face fb of B. */
+static void copy_face(const oracle_cfg* ca, double* A, int fa, const oracle_cfg* cb, const double* B,
+                      int fb, int orient, int nvar, int visc) {
+  const int axa = fa / 2, zero[2] = {0, 0};
+  const int n[2] = {npts(ca, axa == 0 ? 1 : 0), npts(ca, axa == 2 ? 1 : 2)};
+  copy_patch(ca, A, fa, zero, n, cb, B, fb, zero, orient, nvar, visc);
 }
 
 static int exchange(const oracle_cfg* cfgs, int nb, double* const* arrays, int nvar, int visc,
@@ -1161,6 +1197,199 @@ int oracle_rk_step_multi(const oracle_cfg* cfgs, int nb, const double* const* me
   for (b = 0; b < nb && !rc; ++b) memcpy(Q[b], A[b], (size_t)5 * state_dims(&cfgs[b]).plane * sizeof(double));
   for (b = 0; b < nb; ++b) { free(A[b]); free(Bq[b]); free(R[b]); }
   free(Qn); free(A); free(Bq); free(R);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Multi-block with patched connections (Sec. 3: arbitrary splits, connecting and        */
+/* physical faces defined anywhere on a block's faces).                                  */
+/* ------------------------------------------------------------------------------------ */
+/* The same patch seen from block_b: the corners trade places, the extents follow b's
+ * axes, and the orientation is inverted (the swap stays, the reversals follow their axes). */
+static oracle_patch patch_from_b(const oracle_patch* p) {
+  oracle_patch q;
+  const int r1 = (p->orient >> 1) & 1, r2 = (p->orient >> 2) & 1;
+  q.block_a = p->block_b;
+  q.face_a = p->face_b;
+  q.block_b = p->block_a;
+  q.face_b = p->face_a;
+  q.a_lo[0] = p->b_lo[0];
+  q.a_lo[1] = p->b_lo[1];
+  q.b_lo[0] = p->a_lo[0];
+  q.b_lo[1] = p->a_lo[1];
+  if (p->orient & 1) {
+    q.n[0] = p->n[1];
+    q.n[1] = p->n[0];
+    q.orient = 1 | (r2 << 1) | (r1 << 2);
+  } else {
+    q.n[0] = p->n[0];
+    q.n[1] = p->n[1];
+    q.orient = p->orient;
+  }
+  return q;
+}
+
+typedef struct {
+  unsigned char* cov[6];  /* per face: 1 at the nodes a patch covers (see face_covered) */
+} block_cover;
+
+static void free_cover(block_cover* cv, int nb) {
+  int b, f;
+  for (b = 0; b < nb; ++b)
+    for (f = 0; f < 6; ++f) free(cv[b].cov[f]);
+  free(cv);
+}
+
+/* Check the patches against the rules of oracle_patch and mark the nodes they cover on
+ * both sides.  Returns NULL on a violation.                                            */
+static block_cover* cover_patches(const oracle_cfg* cfgs, int nb, const oracle_patch* p, int np) {
+  block_cover* cv = (block_cover*)calloc((size_t)nb, sizeof(block_cover));
+  int k, side, b, f;
+  for (k = 0; k < np; ++k)
+    for (side = 0; side < 2; ++side) {
+      const oracle_patch q = side ? patch_from_b(&p[k]) : p[k];
+      const oracle_cfg *ca, *cb;
+      int t1a, t2a, t1b, t2b, e0, e1, x, y, n1;
+      if (q.block_a < 0 || q.block_a >= nb || q.block_b < 0 || q.block_b >= nb || q.face_a < 0 || q.face_a > 5 ||
+          q.face_b < 0 || q.face_b > 5 || q.orient < 0 || q.orient > 7 ||
+          (q.block_a == q.block_b && q.face_a == q.face_b))
+        goto bad;
+      ca = &cfgs[q.block_a];
+      cb = &cfgs[q.block_b];
+      t1a = q.face_a / 2 == 0 ? 1 : 0;
+      t2a = q.face_a / 2 == 2 ? 1 : 2;
+      t1b = q.face_b / 2 == 0 ? 1 : 0;
+      t2b = q.face_b / 2 == 2 ? 1 : 2;
+      e0 = (q.orient & 1) ? q.n[1] : q.n[0]; /* extents along b's t1, t2 */
+      e1 = (q.orient & 1) ? q.n[0] : q.n[1];
+      if (q.n[0] < 1 || q.n[1] < 1 || q.a_lo[0] < 0 || q.a_lo[1] < 0 || q.a_lo[0] + q.n[0] > npts(ca, t1a) ||
+          q.a_lo[1] + q.n[1] > npts(ca, t2a) || q.b_lo[0] < 0 || q.b_lo[1] < 0 || q.b_lo[0] + e0 > npts(cb, t1b) ||
+          q.b_lo[1] + e1 > npts(cb, t2b))
+        goto bad;
+      if (ca->bc[q.face_a] == ORACLE_BC_PERIODIC) goto bad;
+      if (physical_face(ca->bc[q.face_a]) && ca->visc_closure == ORACLE_VISC_ONE_SIDED) goto bad;
+      n1 = npts(ca, t1a);
+      if (!cv[q.block_a].cov[q.face_a]) cv[q.block_a].cov[q.face_a] = (unsigned char*)calloc((size_t)n1 * npts(ca, t2a), 1);
+      for (y = 0; y < q.n[1]; ++y)
+        for (x = 0; x < q.n[0]; ++x) {
+          unsigned char* c = &cv[q.block_a].cov[q.face_a][(q.a_lo[0] + x) + (long)n1 * (q.a_lo[1] + y)];
+          if (*c) goto bad; /* a node covered twice */
+          *c = 1;
+        }
+    }
+  for (b = 0; b < nb; ++b)
+    for (f = 0; f < 6; ++f)
+      if (cfgs[b].bc[f] == ORACLE_BC_INTERFACE) {
+        const int t1 = f / 2 == 0 ? 1 : 0, t2 = f / 2 == 2 ? 1 : 2;
+        long e, ne = (long)npts(&cfgs[b], t1) * npts(&cfgs[b], t2);
+        if (!cv[b].cov[f]) goto bad;
+        for (e = 0; e < ne; ++e)
+          if (!cv[b].cov[f][e]) goto bad; /* an interface face with a node left open */
+      }
+  return cv;
+bad:
+  free_cover(cv, nb);
+  return NULL;
+}
+
+static void exchange_patched(const oracle_cfg* cfgs, double* const* arrays, int nvar, int visc, const oracle_patch* p,
+                             int np) {
+  int k, side;
+  for (k = 0; k < np; ++k)
+    for (side = 0; side < 2; ++side) {
+      const oracle_patch q = side ? patch_from_b(&p[k]) : p[k];
+      copy_patch(&cfgs[q.block_a], arrays[q.block_a], q.face_a, q.a_lo, q.n, &cfgs[q.block_b], arrays[q.block_b],
+                 q.face_b, q.b_lo, q.orient, nvar, visc);
+    }
+}
+
+static void halo_cov(const oracle_cfg* cfgs, int nb, const double* const* met, double* const* Q, const oracle_patch* p,
+                     int np, const block_cover* cv) {
+  int b;
+  for (b = 0; b < nb; ++b) wall_reset_cov(&cfgs[b], Q[b], (const unsigned char* const*)cv[b].cov);
+  for (b = 0; b < nb; ++b) oracle_periodic_wrap(&cfgs[b], Q[b], 5);
+  exchange_patched(cfgs, Q, 5, 0, p, np);
+  for (b = 0; b < nb; ++b) bc_fill_cov(&cfgs[b], met ? met[b] : NULL, Q[b], (const unsigned char* const*)cv[b].cov);
+}
+
+int oracle_halo_patched(const oracle_cfg* cfgs, int nb, const double* const* met, double* const* Q,
+                        const oracle_patch* p, int np) {
+  block_cover* cv = cover_patches(cfgs, nb, p, np);
+  if (!cv) return -1;
+  halo_cov(cfgs, nb, met, Q, p, np, cv);
+  free_cover(cv, nb);
+  return 0;
+}
+
+static int rhs_patched(const oracle_cfg* cfgs, int nb, const double* const* met, const double* const* Q,
+                       double* const* R, unsigned mask, const oracle_patch* p, int np) {
+  double** V = (double**)calloc((size_t)nb, sizeof(double*));
+  int b, rc = 0;
+  for (b = 0; b < nb; ++b)
+    if (check_cfg(&cfgs[b])) rc = -1;
+  if (!rc && (mask & ORACLE_VIS)) {
+    for (b = 0; b < nb; ++b)
+      if (cfgs[b].viscous) V[b] = visc_planes(&cfgs[b], met[b], Q[b]);
+      else V[b] = (double*)calloc((size_t)12 * state_dims(&cfgs[b]).plane, sizeof(double));
+    /* the covered nodes of partly physical faces get the connected block's fluxes over
+     * the reflected ghosts visc_planes put there */
+    exchange_patched(cfgs, V, 12, 1, p, np);
+  }
+  if (!rc)
+    for (b = 0; b < nb; ++b) rhs_core(&cfgs[b], met[b], Q[b], V[b], R[b], mask, 0, cfgs[b].nk);
+  for (b = 0; b < nb; ++b) free(V[b]);
+  free(V);
+  return rc;
+}
+
+int oracle_rhs_patched(const oracle_cfg* cfgs, int nb, const double* const* met, const double* const* Q,
+                       double* const* R, unsigned mask, const oracle_patch* p, int np) {
+  block_cover* cv = cover_patches(cfgs, nb, p, np);
+  int rc;
+  if (!cv) return -1;
+  rc = rhs_patched(cfgs, nb, met, Q, R, mask, p, np);
+  free_cover(cv, nb);
+  return rc;
+}
+
+int oracle_rk_step_patched(const oracle_cfg* cfgs, int nb, const double* const* met, double dt,
+                           double* const* Q, const oracle_patch* p, int np) {
+  block_cover* cv = cover_patches(cfgs, nb, p, np);
+  double **Qn, **A, **Bq, **R;
+  int b, stage, rc = 0;
+  if (!cv) return -1;
+  Qn = malloc(sizeof(double*) * nb);
+  A = malloc(sizeof(double*) * nb);
+  Bq = malloc(sizeof(double*) * nb);
+  R = malloc(sizeof(double*) * nb);
+  for (b = 0; b < nb; ++b) {
+    size_t bytes = (size_t)5 * state_dims(&cfgs[b]).plane * sizeof(double);
+    Qn[b] = Q[b];
+    A[b] = malloc(bytes);
+    Bq[b] = malloc(bytes);
+    R[b] = calloc(1, bytes);
+    memcpy(A[b], Q[b], bytes);
+    memcpy(Bq[b], Q[b], bytes);
+  }
+  for (stage = 0; stage < 3 && !rc; ++stage) {
+    double** cur = stage == 0 ? Qn : stage == 1 ? A : Bq;
+    double** out = stage == 0 ? A : stage == 1 ? Bq : A;
+    rc = rhs_patched(cfgs, nb, met, (const double* const*)cur, R, ORACLE_ALL, p, np);
+    if (rc) break;
+    for (b = 0; b < nb; ++b) rk_combine(&cfgs[b], stage, dt, Qn[b], cur[b], R[b], out[b]);
+    halo_cov(cfgs, nb, met, out, p, np, cv);
+  }
+  for (b = 0; b < nb && !rc; ++b) memcpy(Q[b], A[b], (size_t)5 * state_dims(&cfgs[b]).plane * sizeof(double));
+  for (b = 0; b < nb; ++b) {
+    free(A[b]);
+    free(Bq[b]);
+    free(R[b]);
+  }
+  free(Qn);
+  free(A);
+  free(Bq);
+  free(R);
+  free_cover(cv, nb);
   return rc;
 }
 

@@ -162,6 +162,42 @@ int oracle_rhs_multi(const oracle_cfg* cfgs, int nb, const double* const* met,
 int oracle_rk_step_multi(const oracle_cfg* cfgs, int nb, const double* const* met,
                          double dt, double* const* Q, const oracle_iface* ifc, int nifc);
 
+/* ---- multi-block with patched connections (Sec. 3: the domain may be split arbitrarily,
+ * without the limitation of one-to-one block connection, and connecting and physical
+ * faces may be defined anywhere on a block's faces) ----------------------------------- */
+/* A patch joins a rectangle of face_a of block_a to an equal rectangle of face_b of
+ * block_b, node to node.  The rectangle on face_a starts at (a_lo[0], a_lo[1]) and spans
+ * (n[0], n[1]) nodes along a's two tangential axes t1 < t2; the one on face_b starts at
+ * (b_lo[0], b_lo[1]) along b's t1 < t2.  orient is that of oracle_iface inside the two
+ * rectangles: the swap bit pairs a's t1 with b's t2, a reversal bit sends index p (counted
+ * from a's low corner) to the far end minus p of the partner rectangle's axis.  Ghost layer
+ * m (1..3) beyond face_a takes interior layer m-1 inside face_b, and the other way round.
+ * Rules (violations give -1): no node of a face is covered twice; a face of kind
+ * ORACLE_BC_INTERFACE is covered completely; a face of kind ORACLE_BC_PERIODIC takes no
+ * patch; a wall or far-field face may be covered in part, its uncovered nodes keeping the
+ * physical treatment (wall reset, ghost fill, reflected viscous ghosts), but not with
+ * ORACLE_VISC_ONE_SIDED.  A whole-face oracle_iface is the patch with zero corners and
+ * the face's extents.                                                                   */
+typedef struct oracle_patch {
+  int block_a, face_a;
+  int a_lo[2], n[2];
+  int block_b, face_b;
+  int b_lo[2];
+  int orient;
+} oracle_patch;
+
+/* Halos of all blocks as the solver refills them after a stage: wall reset on the
+ * uncovered wall nodes, periodic wraps, copies across the patches (both sides), ghost
+ * fill of the uncovered wall and far-field nodes.  Returns -1 on a rule violation.        */
+int oracle_halo_patched(const oracle_cfg* cfgs, int nb, const double* const* met, double* const* Q,
+                        const oracle_patch* p, int np);
+/* R_Q for all blocks, the viscous flux planes exchanged across the patches.             */
+int oracle_rhs_patched(const oracle_cfg* cfgs, int nb, const double* const* met, const double* const* Q,
+                       double* const* R, unsigned mask, const oracle_patch* p, int np);
+/* One RK3 step of all blocks in place (oracle_halo_patched after every stage).          */
+int oracle_rk_step_patched(const oracle_cfg* cfgs, int nb, const double* const* met, double dt,
+                           double* const* Q, const oracle_patch* p, int np);
+
 /* Number of OpenMP threads the oracle's parallel loops use.                             */
 int oracle_threads(void);
 /* Use n threads from now on (n > 0); returns the previous count.  Results do not depend

@@ -53,6 +53,11 @@ class cfd_interface(C.Structure):
                 ("orient", C.c_int32)]
 
 
+class cfd_patch(C.Structure):
+    _fields_ = [("block_a", C.c_int32), ("face_a", C.c_int32), ("a_lo", C.c_int32 * 2), ("n", C.c_int32 * 2),
+                ("block_b", C.c_int32), ("face_b", C.c_int32), ("b_lo", C.c_int32 * 2), ("orient", C.c_int32)]
+
+
 _lib = None
 _VP = C.c_void_p
 _DP = C.POINTER(C.c_double)
@@ -82,6 +87,8 @@ def lib():
         "cfd_rhs_sweeps": ([_VP, _VP, _VP, C.c_uint], C.c_int),
         "cfd_rk_sweeps": ([_VP, C.c_int, C.c_double, _VP, _VP, _VP], C.c_int),
         "cfd_exchange_create": ([C.POINTER(_VP), C.c_int, C.POINTER(cfd_interface), C.c_int, C.POINTER(_VP)], C.c_int),
+        "cfd_exchange_create_patched": ([C.POINTER(_VP), C.c_int, C.POINTER(cfd_patch), C.c_int, C.POINTER(_VP)],
+                                        C.c_int),
         "cfd_exchange_destroy": ([_VP], C.c_int),
         "cfd_halo_exchange": ([_VP, C.c_int, C.POINTER(_VP), _VP], C.c_int),
         "cfd_dt_cfl": ([C.POINTER(_VP), C.c_int, C.POINTER(_VP), C.c_double, _DP], C.c_int),
@@ -211,6 +218,23 @@ def cfd_exchange_create(blocks: Sequence[int], interfaces: Sequence) -> int:
         ifc[k].orient = getattr(f, "orient", 0)
     h = _VP()
     _check(lib().cfd_exchange_create(arr, len(blocks), ifc, n, C.byref(h)))
+    return h.value
+
+
+def cfd_exchange_create_patched(blocks: Sequence[int], patches: Sequence) -> int:
+    """patches: objects with block_a, face_a, a_lo, n, block_b, face_b, b_lo, orient."""
+    arr = (_VP * len(blocks))(*blocks)
+    n = len(patches)
+    ps = (cfd_patch * max(1, n))()
+    for k, p in enumerate(patches):
+        ps[k].block_a, ps[k].face_a = p.block_a, p.face_a
+        ps[k].a_lo[0], ps[k].a_lo[1] = p.a_lo
+        ps[k].n[0], ps[k].n[1] = p.n
+        ps[k].block_b, ps[k].face_b = p.block_b, p.face_b
+        ps[k].b_lo[0], ps[k].b_lo[1] = p.b_lo
+        ps[k].orient = getattr(p, "orient", 0)
+    h = _VP()
+    _check(lib().cfd_exchange_create_patched(arr, len(blocks), ps, n, C.byref(h)))
     return h.value
 
 

@@ -145,6 +145,7 @@ struct cfd_block {
   BcSeg* local_bc_dev = nullptr;
   int n_local_bc = 0, max_local_bc = 0;
   bool has_interface = false;
+  int patched = 0;  // exchanges that connect part of one of its physical faces to a block
   int cfg[3] = {0, 0, 0};  // sweep tile shape per direction (set at creation)
   // small device scratch for reductions
   unsigned long long* red_dev = nullptr;
@@ -248,11 +249,22 @@ int inverse_orient(int orient) {
   return (orient & 1) ? (1 | (r2 << 1) | (r1 << 2)) : orient;
 }
 
-// halo copy of face fa of block A (index ia) from face fb of block B (index ib) under the
-// tangential map orient: ghost layer m (1..3) beyond fa <- interior layer m-1 inside fb.
-// Planes plane0.. of A receive planes src_plane0.. of B, negated if negate.
-CopySeg make_copy(const Geom& A, int ia, int fa, const Geom& B, int ib, int fb, int plane0, int nplanes,
-                  int orient = 0, int src_plane0 = -1, int negate = 0) {
+// A rectangle of a face: corner and extents along the face's tangential axes t1 < t2
+struct FaceRect {
+  int lo[2], n[2];
+};
+FaceRect whole_face(const Geom& g, int f) {
+  int ta, tb;
+  tangential(f / 2, &ta, &tb);
+  return FaceRect{{0, 0}, {npts(g, ta), npts(g, tb)}};
+}
+
+// halo copy of the rectangle ra of face fa of block A (index ia) from face fb of block B
+// (index ib) under the tangential map orient: ghost layer m (1..3) beyond fa <- interior
+// layer m-1 inside fb, B's rectangle starting at blo (along B's t1, t2).  Planes plane0..
+// of A receive planes src_plane0.. of B, negated if negate.
+CopySeg make_copy_rect(const Geom& A, int ia, int fa, const FaceRect& ra, const Geom& B, int ib, int fb,
+                       const int* blo, int plane0, int nplanes, int orient, int src_plane0, int negate) {
   int axis, wa, outa, wb, outb;
   face_geom(A, fa, &axis, &wa, &outa);
   int axis_b;
@@ -263,16 +275,20 @@ CopySeg make_copy(const Geom& A, int ia, int fa, const Geom& B, int ib, int fb, 
   s.layer_fast = axis == 0;  // on i faces the three halo layers are the contiguous run
   s.dst = ia;
   s.src = ib;
-  s.na = npts(A, m.ta[0]);
-  s.nb = npts(A, m.ta[1]);
+  s.na = ra.n[0];
+  s.nb = ra.n[1];
   s.plane0 = plane0;
-  s.src_plane0 = src_plane0 < 0 ? plane0 : src_plane0;
+  s.src_plane0 = src_plane0;
   s.negate = negate;
   s.nplanes = nplanes;
   int ida[3] = {0, 0, 0}, idb[3] = {0, 0, 0};
   ida[axis] = wa + outa;  // ghost layer 1
   idb[axis_b] = wb;       // interior layer 0
-  for (int q = 0; q < 2; ++q) idb[m.map_axis[q]] = m.map_rev[q] ? npts(B, m.map_axis[q]) - 1 : 0;
+  for (int q = 0; q < 2; ++q) {
+    ida[m.ta[q]] = ra.lo[q];
+    const int lo = m.map_axis[q] == m.tb[0] ? blo[0] : blo[1];  // B's corner along that axis
+    idb[m.map_axis[q]] = m.map_rev[q] ? lo + ra.n[q] - 1 : lo;
+  }
   s.dst_off = at_h(A, ida[0], ida[1], ida[2]);
   s.src_off = at_h(B, idb[0], idb[1], idb[2]);
   s.dst_sa = stride(A, m.ta[0]);
@@ -284,7 +300,16 @@ CopySeg make_copy(const Geom& A, int ia, int fa, const Geom& B, int ib, int fb, 
   return s;
 }
 
-BcSeg make_bc(const Geom& G, int blk, int f, int kind) {
+// the whole face fa of A from the whole face fb of B
+CopySeg make_copy(const Geom& A, int ia, int fa, const Geom& B, int ib, int fb, int plane0, int nplanes,
+                  int orient = 0, int src_plane0 = -1, int negate = 0) {
+  const int zero[2] = {0, 0};
+  return make_copy_rect(A, ia, fa, whole_face(A, fa), B, ib, fb, zero, plane0, nplanes, orient,
+                        src_plane0 < 0 ? plane0 : src_plane0, negate);
+}
+
+// wall / far-field treatment of the rectangle r of face f
+BcSeg make_bc_rect(const Geom& G, int blk, int f, int kind, const FaceRect& r) {
   int axis, w, out;
   face_geom(G, f, &axis, &w, &out);
   int ta, tb;
@@ -292,9 +317,11 @@ BcSeg make_bc(const Geom& G, int blk, int f, int kind) {
   BcSeg s;
   s.blk = blk;
   s.kind = kind;
-  s.na = npts(G, ta);
-  s.nb = npts(G, tb);
+  s.na = r.n[0];
+  s.nb = r.n[1];
   int id[3] = {0, 0, 0};
+  id[ta] = r.lo[0];
+  id[tb] = r.lo[1];
   id[axis] = w;
   s.wall_off = at_h(G, id[0], id[1], id[2]);
   s.sa = stride(G, ta);
@@ -303,6 +330,7 @@ BcSeg make_bc(const Geom& G, int blk, int f, int kind) {
   s.axis = axis;
   return s;
 }
+BcSeg make_bc(const Geom& G, int blk, int f, int kind) { return make_bc_rect(G, blk, f, kind, whole_face(G, f)); }
 
 // Allocate nplanes planes of esize-byte elements.  The base is shifted so that the first
 // interior point of every row, element ((k+3)*ld_j + j+3)*ld_i + 3, starts a 128-byte cache
@@ -664,7 +692,7 @@ int cfd_rhs_sweeps(cfd_block* b, const double* Q, double* R, unsigned mask) {
 
 int cfd_rhs(cfd_block* b, const double* Q, double* R, unsigned mask) {
   if (!b || !Q || !R) return fail(CFD_ERR_ARG, "null argument");
-  if (b->has_interface)
+  if (b->has_interface || b->patched)
     return fail(CFD_ERR_STATE, "block has interface faces: use cfd_viscous_fluxes, cfd_halo_exchange(VISC), cfd_rhs_sweeps");
   if ((mask & CFD_TERM_VIS) && b->d.params.viscous) {
     int rc = cfd_viscous_fluxes(b, Q);
@@ -689,7 +717,7 @@ int cfd_rk_stage(cfd_block* b, int stage, double dt, const double* Qn, const dou
   int rc = check_rk_args(b, stage, Qn, Qcur, Qout);
   if (rc) return rc;
   if (!std::isfinite(dt)) return fail(CFD_ERR_ARG, "dt must be finite");
-  if (b->has_interface)
+  if (b->has_interface || b->patched)
     return fail(CFD_ERR_STATE, "block has interface faces: use cfd_viscous_fluxes, cfd_halo_exchange(VISC), cfd_rk_sweeps");
   if (b->d.params.viscous) {
     rc = run_visc(b, Qcur);
@@ -703,7 +731,7 @@ int cfd_rk_stage_dev(cfd_block* b, int stage, const double* dt_dev, const double
   int rc = check_rk_args(b, stage, Qn, Qcur, Qout);
   if (rc) return rc;
   if (!dt_dev) return fail(CFD_ERR_ARG, "null dt_dev");
-  if (b->has_interface)
+  if (b->has_interface || b->patched)
     return fail(CFD_ERR_STATE, "block has interface faces: use cfd_viscous_fluxes, cfd_halo_exchange(VISC), cfd_rk_sweeps");
   if (b->d.params.viscous) {
     rc = run_visc(b, Qcur);
@@ -920,6 +948,7 @@ struct cfd_exchange {
   int precision = CFD_FP64;
   std::vector<CopySeg> qs_host, vs_host;  // host copies of the segment tables
   std::vector<BcSeg> bc_host;
+  std::vector<cfd_block*> patched;  // blocks with a partly connected physical face
 };
 
 
@@ -1041,9 +1070,10 @@ int batch_create(cfd_block* const* blocks, int nb, cfd_exchange* x, void* hip_st
         vc.push_back(make_copy(B->g, b, 2 * ax, B->g, b, 2 * ax + 1, 4 * ax, 4));
         vc.push_back(make_copy(B->g, b, 2 * ax + 1, B->g, b, 2 * ax, 4 * ax, 4));
       }
-    for (int f = 0; f < 6; ++f)
-      if (is_physical(B->d.bc[f])) vb.push_back(make_bc(B->g, b, f, B->d.bc[f]));
   }
+  // wall / far-field rectangles of the exchange (the parts of physical faces no patch
+  // covers): the viscous ghosts run after the copies and must not overwrite them
+  vb = x->bc_host;
   for (auto& c : vc) bt->maxvcopy = std::max(bt->maxvcopy, c.na * c.nb * kHalo * c.nplanes);
   for (auto& c : vb) bt->maxvbc = std::max(bt->maxvbc, c.na * c.nb);
   if (upload(vc, &bt->vcopy_dev) || upload(vb, &bt->vbc_dev)) {
@@ -1328,56 +1358,134 @@ int batch_set_tuning(cfd_batch* bt, const int* cfg, const int* persist) {
 
 extern "C" {
 
-int cfd_exchange_create(cfd_block* const* blocks, int nb, const cfd_interface* ifc, int nifc, cfd_exchange** out) {
+namespace {
+
+// the same patch seen from block_b: corners trade places, the extents follow b's axes and
+// the orientation is inverted
+cfd_patch patch_seen_from_b(const cfd_patch& p) {
+  cfd_patch q;
+  q.block_a = p.block_b;
+  q.face_a = p.face_b;
+  q.block_b = p.block_a;
+  q.face_b = p.face_a;
+  q.a_lo[0] = p.b_lo[0];
+  q.a_lo[1] = p.b_lo[1];
+  q.b_lo[0] = p.a_lo[0];
+  q.b_lo[1] = p.a_lo[1];
+  const bool swap = p.orient & 1;
+  q.n[0] = swap ? p.n[1] : p.n[0];
+  q.n[1] = swap ? p.n[0] : p.n[1];
+  q.orient = inverse_orient(p.orient);
+  return q;
+}
+
+// Uncovered parts of a face as rectangles: the face is cut at every patch edge along each
+// tangential axis, and every cell of that grid is uniformly covered or not.
+std::vector<FaceRect> uncovered_rects(const std::vector<uint8_t>& cov, int n0, int n1,
+                                      const std::vector<FaceRect>& patches) {
+  std::vector<int> c0{0, n0}, c1{0, n1};
+  for (const FaceRect& r : patches) {
+    c0.push_back(r.lo[0]);
+    c0.push_back(r.lo[0] + r.n[0]);
+    c1.push_back(r.lo[1]);
+    c1.push_back(r.lo[1] + r.n[1]);
+  }
+  std::sort(c0.begin(), c0.end());
+  c0.erase(std::unique(c0.begin(), c0.end()), c0.end());
+  std::sort(c1.begin(), c1.end());
+  c1.erase(std::unique(c1.begin(), c1.end()), c1.end());
+  std::vector<FaceRect> out;
+  const size_t nc0 = c0.size() - 1, nc1 = c1.size() - 1;  // cells along t1, t2
+  for (size_t y = 0; y < nc1; ++y)
+    for (size_t x = 0; x < nc0; ++x) {
+      if (cov[(size_t)c1[y] * n0 + c0[x]]) continue;
+      size_t e = x + 1;  // run of uncovered cells along t1: cells x .. e-1
+      while (e < nc0 && !cov[(size_t)c1[y] * n0 + c0[e]]) ++e;
+      out.push_back(FaceRect{{c0[x], c1[y]}, {c0[e] - c0[x], c1[y + 1] - c1[y]}});
+      x = e;  // cell e is covered (or past the end)
+    }
+  return out;
+}
+
+int build_exchange(cfd_block* const* blocks, int nb, const std::vector<cfd_patch>& patches, cfd_exchange** out) {
   if (!out) return fail(CFD_ERR_ARG, "null output handle");
   *out = nullptr;
   if (!blocks || nb <= 0 || nb > kMaxBlocks) return fail(CFD_ERR_ARG, "need 1..64 blocks");
-  if (nifc < 0 || (nifc > 0 && !ifc)) return fail(CFD_ERR_ARG, "bad interface list");
   for (int n = 0; n < nb; ++n)
     if (!blocks[n]) return fail(CFD_ERR_ARG, "null block");
   const int prec = blocks[0]->d.precision;
   for (int n = 0; n < nb; ++n)
     if (blocks[n]->d.precision != prec) return fail(CFD_ERR_ARG, "all blocks of an exchange share one precision");
-  std::vector<int> used(6 * nb, 0);
+  std::vector<std::vector<uint8_t>> cov(6 * nb);          // covered nodes per face (t1 fastest)
+  std::vector<std::vector<FaceRect>> rects(6 * nb);        // patch rectangles per face
   std::vector<CopySeg> qs, vs;
   std::vector<BcSeg> bs;
-  for (int n = 0; n < nifc; ++n) {
-    const cfd_interface& f = ifc[n];
-    if (f.block_a < 0 || f.block_a >= nb || f.block_b < 0 || f.block_b >= nb || f.face_a < 0 || f.face_a > 5 ||
-        f.face_b < 0 || f.face_b > 5)
-      return fail(CFD_ERR_ARG, "interface index out of range");
-    if (f.block_a == f.block_b && f.face_a == f.face_b) return fail(CFD_ERR_ARG, "an interface joins two faces");
-    if (f.orient < 0 || f.orient > 7) return fail(CFD_ERR_ARG, "interface orient must be 0..7");
-    const cfd_block* A = blocks[f.block_a];
-    const cfd_block* B = blocks[f.block_b];
-    if (A->d.bc[f.face_a] != CFD_BC_INTERFACE || B->d.bc[f.face_b] != CFD_BC_INTERFACE)
-      return fail(CFD_ERR_ARG, "interface faces must have kind CFD_BC_INTERFACE");
-    const FaceMap m = face_map(f.face_a, f.face_b, f.orient);
-    for (int q = 0; q < 2; ++q)
-      if (npts(A->g, m.ta[q]) != npts(B->g, m.map_axis[q])) return fail(CFD_ERR_ARG, "interface face sizes differ");
-    if (face_map_det(m) != 1) return fail(CFD_ERR_ARG, "interface orientation reverses handedness");
-    if (used[6 * f.block_a + f.face_a]++ || used[6 * f.block_b + f.face_b]++)
-      return fail(CFD_ERR_ARG, "a face appears in more than one interface");
-    const int inv = inverse_orient(f.orient);
-    const int neg = m.normal_sign < 0;
-    qs.push_back(make_copy(A->g, f.block_a, f.face_a, B->g, f.block_b, f.face_b, 0, 5, f.orient));
-    qs.push_back(make_copy(B->g, f.block_b, f.face_b, A->g, f.block_a, f.face_a, 0, 5, inv));
-    // the face-normal direction's viscous flux: a's direction axis_a is b's axis_b
-    vs.push_back(make_copy(A->g, f.block_a, f.face_a, B->g, f.block_b, f.face_b, 4 * m.axis_a, 4, f.orient,
-                           4 * m.axis_b, neg));
-    vs.push_back(make_copy(B->g, f.block_b, f.face_b, A->g, f.block_a, f.face_a, 4 * m.axis_b, 4, inv,
-                           4 * m.axis_a, neg));
+  for (const cfd_patch& p : patches) {
+    if (p.block_a < 0 || p.block_a >= nb || p.block_b < 0 || p.block_b >= nb || p.face_a < 0 || p.face_a > 5 ||
+        p.face_b < 0 || p.face_b > 5)
+      return fail(CFD_ERR_ARG, "patch index out of range");
+    if (p.block_a == p.block_b && p.face_a == p.face_b) return fail(CFD_ERR_ARG, "a patch joins two faces");
+    if (p.orient < 0 || p.orient > 7) return fail(CFD_ERR_ARG, "patch orient must be 0..7");
+    if (face_map_det(face_map(p.face_a, p.face_b, p.orient)) != 1)
+      return fail(CFD_ERR_ARG, "patch orientation reverses handedness");
+    for (int side = 0; side < 2; ++side) {
+      const cfd_patch q = side ? patch_seen_from_b(p) : p;
+      const cfd_block* A = blocks[q.block_a];
+      const cfd_block* B = blocks[q.block_b];
+      int ta, tb, ua, ub;
+      tangential(q.face_a / 2, &ta, &tb);
+      tangential(q.face_b / 2, &ua, &ub);
+      const bool swap = q.orient & 1;
+      const int eb0 = swap ? q.n[1] : q.n[0], eb1 = swap ? q.n[0] : q.n[1];  // extents along b's t1, t2
+      if (q.n[0] < 1 || q.n[1] < 1 || q.a_lo[0] < 0 || q.a_lo[1] < 0 || q.a_lo[0] + q.n[0] > npts(A->g, ta) ||
+          q.a_lo[1] + q.n[1] > npts(A->g, tb) || q.b_lo[0] < 0 || q.b_lo[1] < 0 || q.b_lo[0] + eb0 > npts(B->g, ua) ||
+          q.b_lo[1] + eb1 > npts(B->g, ub))
+        return fail(CFD_ERR_ARG, "patch rectangle outside its face");
+      const int kind = A->d.bc[q.face_a];
+      if (kind == CFD_BC_PERIODIC) return fail(CFD_ERR_ARG, "a periodic face takes no patch");
+      if (is_physical(kind) && A->d.params.visc_closure == CFD_VISC_ONE_SIDED)
+        return fail(CFD_ERR_UNSUPPORTED, "a patch on a physical face of a block with the one-sided viscous closure");
+      const int fi = 6 * q.block_a + q.face_a;
+      const int n0 = npts(A->g, ta);
+      if (cov[fi].empty()) cov[fi].assign((size_t)n0 * npts(A->g, tb), 0);
+      for (int y = 0; y < q.n[1]; ++y)
+        for (int x = 0; x < q.n[0]; ++x) {
+          uint8_t& c = cov[fi][(size_t)(q.a_lo[1] + y) * n0 + q.a_lo[0] + x];
+          if (c) return fail(CFD_ERR_ARG, "a face node is covered by two patches");
+          c = 1;
+        }
+      const FaceRect ra{{q.a_lo[0], q.a_lo[1]}, {q.n[0], q.n[1]}};
+      rects[fi].push_back(ra);
+      const FaceMap m = face_map(q.face_a, q.face_b, q.orient);
+      qs.push_back(make_copy_rect(A->g, q.block_a, q.face_a, ra, B->g, q.block_b, q.face_b, q.b_lo, 0, 5, q.orient, 0, 0));
+      // the face-normal direction's viscous flux: a's direction axis_a is b's axis_b
+      vs.push_back(make_copy_rect(A->g, q.block_a, q.face_a, ra, B->g, q.block_b, q.face_b, q.b_lo, 4 * m.axis_a, 4,
+                                  q.orient, 4 * m.axis_b, m.normal_sign < 0));
+    }
   }
   for (int n = 0; n < nb; ++n) {
     const cfd_block* B = blocks[n];
     for (int f = 0; f < 6; ++f) {
       const int k = B->d.bc[f];
-      if (k == CFD_BC_INTERFACE && !used[6 * n + f]) return fail(CFD_ERR_ARG, "an interface face has no partner");
+      const int fi = 6 * n + f;
+      if (k == CFD_BC_INTERFACE) {
+        if (cov[fi].empty() || std::find(cov[fi].begin(), cov[fi].end(), 0) != cov[fi].end())
+          return fail(CFD_ERR_ARG, "an interface face is not covered completely");
+      }
       if (k == CFD_BC_PERIODIC && (f % 2) == 0) {
         qs.push_back(make_copy(B->g, n, f, B->g, n, f + 1, 0, 5));
         qs.push_back(make_copy(B->g, n, f + 1, B->g, n, f, 0, 5));
       }
-      if (is_physical(k)) bs.push_back(make_bc(B->g, n, f, k));
+      if (is_physical(k)) {
+        if (cov[fi].empty()) {
+          bs.push_back(make_bc(B->g, n, f, k));
+        } else {
+          int ta, tb;
+          tangential(f / 2, &ta, &tb);
+          for (const FaceRect& r : uncovered_rects(cov[fi], npts(B->g, ta), npts(B->g, tb), rects[fi]))
+            bs.push_back(make_bc_rect(B->g, n, f, k, r));
+        }
+      }
     }
   }
   cfd_exchange* x = new cfd_exchange();
@@ -1396,12 +1504,67 @@ int cfd_exchange_create(cfd_block* const* blocks, int nb, const cfd_interface* i
   x->qs_host = qs;
   x->vs_host = vs;
   x->bc_host = bs;
+  // blocks whose physical faces are partly connected need the split form from now on
+  for (int n = 0; n < nb; ++n)
+    for (int f = 0; f < 6; ++f)
+      if (is_physical(blocks[n]->d.bc[f]) && !cov[6 * n + f].empty()) {
+        x->patched.push_back(blocks[n]);
+        ++blocks[n]->patched;
+        break;
+      }
   *out = x;
   return CFD_OK;
 }
 
+}  // namespace
+
+int cfd_exchange_create(cfd_block* const* blocks, int nb, const cfd_interface* ifc, int nifc, cfd_exchange** out) {
+  if (!out) return fail(CFD_ERR_ARG, "null output handle");
+  *out = nullptr;
+  if (!blocks || nb <= 0 || nb > kMaxBlocks) return fail(CFD_ERR_ARG, "need 1..64 blocks");
+  if (nifc < 0 || (nifc > 0 && !ifc)) return fail(CFD_ERR_ARG, "bad interface list");
+  for (int n = 0; n < nb; ++n)
+    if (!blocks[n]) return fail(CFD_ERR_ARG, "null block");
+  std::vector<cfd_patch> ps;
+  for (int n = 0; n < nifc; ++n) {
+    const cfd_interface& f = ifc[n];
+    if (f.block_a < 0 || f.block_a >= nb || f.block_b < 0 || f.block_b >= nb || f.face_a < 0 || f.face_a > 5 ||
+        f.face_b < 0 || f.face_b > 5)
+      return fail(CFD_ERR_ARG, "interface index out of range");
+    if (f.orient < 0 || f.orient > 7) return fail(CFD_ERR_ARG, "interface orient must be 0..7");
+    const cfd_block* A = blocks[f.block_a];
+    const cfd_block* B = blocks[f.block_b];
+    if (A->d.bc[f.face_a] != CFD_BC_INTERFACE || B->d.bc[f.face_b] != CFD_BC_INTERFACE)
+      return fail(CFD_ERR_ARG, "interface faces must have kind CFD_BC_INTERFACE");
+    const FaceMap m = face_map(f.face_a, f.face_b, f.orient);
+    for (int q = 0; q < 2; ++q)
+      if (npts(A->g, m.ta[q]) != npts(B->g, m.map_axis[q])) return fail(CFD_ERR_ARG, "interface face sizes differ");
+    const FaceRect r = whole_face(A->g, f.face_a);
+    cfd_patch p;
+    p.block_a = f.block_a;
+    p.face_a = f.face_a;
+    p.a_lo[0] = p.a_lo[1] = 0;
+    p.n[0] = r.n[0];
+    p.n[1] = r.n[1];
+    p.block_b = f.block_b;
+    p.face_b = f.face_b;
+    p.b_lo[0] = p.b_lo[1] = 0;
+    p.orient = f.orient;
+    ps.push_back(p);
+  }
+  return build_exchange(blocks, nb, ps, out);
+}
+
+int cfd_exchange_create_patched(cfd_block* const* blocks, int nb, const cfd_patch* p, int np, cfd_exchange** out) {
+  if (!out) return fail(CFD_ERR_ARG, "null output handle");
+  *out = nullptr;
+  if (np < 0 || (np > 0 && !p)) return fail(CFD_ERR_ARG, "bad patch list");
+  return build_exchange(blocks, nb, std::vector<cfd_patch>(p, p + np), out);
+}
+
 int cfd_exchange_destroy(cfd_exchange* x) {
   if (!x) return CFD_OK;
+  for (cfd_block* b : x->patched) --b->patched;
   (void)hipFree(x->q_dev);
   (void)hipFree(x->v_dev);
   (void)hipFree(x->bc_dev);

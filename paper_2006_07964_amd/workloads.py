@@ -62,6 +62,23 @@ class Interface:
 
 
 @dataclasses.dataclass
+class Patch:
+    """A rectangle of face_a of block_a joined node to node with a rectangle of face_b of
+    block_b: a's rectangle starts at a_lo and spans n nodes along a's tangential axes
+    t1 < t2; b's starts at b_lo along b's t1 < t2; orient as for Interface, inside the
+    rectangles."""
+
+    block_a: int
+    face_a: int
+    a_lo: Tuple[int, int]
+    n: Tuple[int, int]
+    block_b: int
+    face_b: int
+    b_lo: Tuple[int, int]
+    orient: int = 0
+
+
+@dataclasses.dataclass
 class Workload:
     name: str
     blocks: List[Block]
@@ -79,6 +96,7 @@ class Workload:
     qinf: Tuple[float, float, float, float, float] = (1.0, 0.0, 0.0, 0.0, 1.0 / (GAMMA * (GAMMA - 1.0)))
     description: str = ""
     visc_closure: int = 0  # viscous terms at wall / far-field faces: 0 reflected ghosts, 1 one-sided
+    patches: List[Patch] = dataclasses.field(default_factory=list)  # patched connections (no interfaces then)
 
     @property
     def points(self) -> int:
@@ -384,6 +402,100 @@ def split_block(wl_single: Workload, sizes, periodic=(True, True, True)) -> Work
                 blocks.append(Block(ni, nj, nk, xyz, q, (BC_INTERFACE,) * 6))
     out = dataclasses.replace(wl_single, name=wl_single.name + f"_{na}x{nb}x{nc}blocks", blocks=blocks,
                               interfaces=structured_interfaces(na, nb, nc, periodic))
+    return out
+
+
+def _tangential(axis):
+    return (1, 2) if axis == 0 else (0, 2) if axis == 1 else (0, 1)
+
+
+def split_boxes(wl_single: Workload, boxes, name: str) -> Workload:
+    """Blocks cut from a single-block workload as index boxes (i0, i1, j0, j1, k0, k1) of
+    its interior; the boxes need not fill it (what they leave out is solid).  Two boxes
+    whose faces lie on one index plane, or on the two sides of a periodic seam, are joined
+    by a patch over the overlap of the faces.  A box spanning a periodic direction wraps
+    onto itself there.  A face covered completely is an interface; the rest of a face
+    keeps the single block's kind where it lies on the domain's boundary and becomes an
+    isothermal wall where it borders the solid.  Coordinates and states are sliced from the
+    single block, whose halos hold the periodic images and the wall mirrors."""
+    b = wl_single.blocks[0]
+    N = (b.ni, b.nj, b.nk)
+    per = [b.bc[2 * d] == BC_PERIODIC for d in range(3)]
+    blocks, patches = [], []
+    for (i0, i1, j0, j1, k0, k1) in boxes:
+        assert 0 <= i0 < i1 <= N[0] and 0 <= j0 < j1 <= N[1] and 0 <= k0 < k1 <= N[2]
+    lo = [(bx[0], bx[2], bx[4]) for bx in boxes]
+    hi = [(bx[1], bx[3], bx[5]) for bx in boxes]
+    covered = [[np.zeros(0, bool)] * 6 for _ in boxes]
+    for a in range(len(boxes)):
+        for d in range(3):
+            t = _tangential(d)
+            ext = (hi[a][t[0]] - lo[a][t[0]], hi[a][t[1]] - lo[a][t[1]])
+            for side in (0, 1):
+                covered[a][2 * d + side] = np.zeros(ext[::-1], bool)  # [t2][t1]
+    for a in range(len(boxes)):
+        for d in range(3):
+            if per[d] and lo[a][d] == 0 and hi[a][d] == N[d]:
+                continue  # wraps onto itself
+            t = _tangential(d)
+            for c in range(len(boxes)):
+                # a's high face against c's low face, directly or across the periodic seam
+                if not (hi[a][d] == lo[c][d] or (per[d] and hi[a][d] == N[d] and lo[c][d] == 0)):
+                    continue
+                if per[d] and lo[c][d] == 0 and hi[c][d] == N[d]:
+                    continue
+                ov = [(max(lo[a][x], lo[c][x]), min(hi[a][x], hi[c][x])) for x in t]
+                if ov[0][0] >= ov[0][1] or ov[1][0] >= ov[1][1]:
+                    continue
+                n = (ov[0][1] - ov[0][0], ov[1][1] - ov[1][0])
+                a_lo = (ov[0][0] - lo[a][t[0]], ov[1][0] - lo[a][t[1]])
+                c_lo = (ov[0][0] - lo[c][t[0]], ov[1][0] - lo[c][t[1]])
+                patches.append(Patch(a, 2 * d + 1, a_lo, n, c, 2 * d, c_lo))
+                covered[a][2 * d + 1][a_lo[1]:a_lo[1] + n[1], a_lo[0]:a_lo[0] + n[0]] = True
+                covered[c][2 * d][c_lo[1]:c_lo[1] + n[1], c_lo[0]:c_lo[0] + n[0]] = True
+    for a, (i0, i1, j0, j1, k0, k1) in enumerate(boxes):
+        bc = []
+        for d in range(3):
+            if per[d] and lo[a][d] == 0 and hi[a][d] == N[d]:
+                bc += [BC_PERIODIC, BC_PERIODIC]
+                continue
+            for side in (0, 1):
+                f = 2 * d + side
+                if covered[a][f].all():
+                    bc.append(BC_INTERFACE)
+                elif (side == 0 and lo[a][d] == 0 or side == 1 and hi[a][d] == N[d]) and not per[d]:
+                    bc.append(b.bc[f])
+                else:
+                    bc.append(BC_WALL)
+        xyz = np.ascontiguousarray(b.xyz[:, k0:k1 + 12, j0:j1 + 12, i0:i1 + 12])
+        q = np.ascontiguousarray(b.q[:, k0:k1 + 6, j0:j1 + 6, i0:i1 + 6])
+        blocks.append(Block(i1 - i0, j1 - j0, k1 - k0, xyz, q, tuple(bc)))
+    return dataclasses.replace(wl_single, name=name, blocks=blocks, interfaces=[], patches=patches)
+
+
+def patched_vortex(n: int = 32, cut_i: int = 13, cut_j: int = 11, cut_k: int = 9, viscous: bool = True,
+                   steps: int = 5) -> Workload:
+    """The periodic wavy vortex box in four blocks whose faces meet several blocks each:
+    A = [0, cut_i) x all x all; B = [cut_i, n) x [0, cut_j) x all; C1, C2 = [cut_i, n) x
+    [cut_j, n) x ([0, cut_k), [cut_k, n)).  A's i faces meet B, C1 and C2 (directly and across
+    the periodic seam), B's j faces meet C1 and C2."""
+    wl = vortex_wavy(n, viscous=viscous, steps=steps)
+    boxes = [(0, cut_i, 0, n, 0, n), (cut_i, n, 0, cut_j, 0, n), (cut_i, n, cut_j, n, 0, cut_k),
+             (cut_i, n, cut_j, n, cut_k, n)]
+    return split_boxes(wl, boxes, f"vortex_wavy_{n}_patched_4blocks")
+
+
+def periodic_step(ni: int = 48, nj: int = 32, nk: int = 16, step_i: int = 20, step_j: int = 10, seed: int = 5,
+                  mach: float = 0.3, reynolds: float = 1000.0, steps: int = 5) -> Workload:
+    """A periodic row of backward-facing steps cut from the channel: the channel's
+    [0, step_i) x [0, step_j) corner is solid.  Block A = [0, step_i) x [step_j, nj) sits
+    above the step, block B = [step_i, ni) x [0, nj) behind it.  B's i faces are walls (the
+    step's face and, across the periodic seam, its back) below step_j and patches to A
+    above it; A's lower face is the step's top wall."""
+    wl = channel(ni, nj, nk, seed=seed, mach=mach, reynolds=reynolds, steps=steps)
+    boxes = [(0, step_i, step_j, nj, 0, nk), (step_i, ni, 0, nj, 0, nk)]
+    out = split_boxes(wl, boxes, f"periodic_step_{ni}x{nj}x{nk}")
+    out.description = f"{ni}x{nj}x{nk} channel with a {step_i}x{step_j} solid step, Mach {mach}, Re {reynolds}"
     return out
 
 

@@ -147,7 +147,13 @@ class DevMulti:
             self.q.append(B.upload_state(d, b.q))
             self.qa.append(B.upload_state(d, b.q))
             self.qb.append(B.upload_state(d, b.q))
-        self.x = B.cfd_exchange_create(self.h, wl.interfaces)
+        try:
+            self.x = (B.cfd_exchange_create_patched(self.h, wl.patches) if getattr(wl, "patches", None)
+                      else B.cfd_exchange_create(self.h, wl.interfaces))
+        except Exception:
+            for h in self.h:
+                B.cfd_block_destroy(h)
+            raise
         self.bt = None
         self.halo(self.q)  # initial wall reset, copies and ghost fills
 
@@ -189,6 +195,8 @@ def oracle_multi(wl, linear=False):
     import oracle as O
     cfgs = [O.cfg_from_workload(wl, bi, linear_weights=linear) for bi in range(len(wl.blocks))]
     mets = [O.metrics(c, b.xyz) for c, b in zip(cfgs, wl.blocks)]
+    if getattr(wl, "patches", None):
+        return cfgs, mets, O.halo_patched(cfgs, mets, [b.q for b in wl.blocks], wl.patches)
     qs = [O.wall_reset(c, b.q) for c, b in zip(cfgs, wl.blocks)]
     qs = [O.periodic_wrap(c, q) for c, q in zip(cfgs, qs)]
     O.exchange(cfgs, qs, wl.interfaces)
