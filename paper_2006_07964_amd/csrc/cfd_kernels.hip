@@ -126,7 +126,7 @@ hipError_t launch_metrics(const MetricArgs& a, hipStream_t s) {
 // read once per column.
 // =====================================================================================
 constexpr int VI = 64, VJ = 16, VNT = VI * VJ;
-constexpr int kViscChunk = 64;     // most planes per workgroup (fewer when nk is smaller)
+constexpr int kViscChunk = 128;    // most planes per workgroup (fewer when nk is smaller)
 constexpr int kViscMinTiles = 256;  // workgroups a single-block launch aims for (one per CU)
 
 template <typename R>

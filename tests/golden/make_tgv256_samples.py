@@ -1,5 +1,8 @@
-"""Write tgv256_samples.json: the oracle's state of the 256^3 Taylor-Green case (FP64,
-WENO-JS, viscous) after 1, 10 and 100 RK3 steps, at a lattice of sample nodes.
+"""Write the oracle's state of the 256^3 Taylor-Green case (FP64, WENO-JS, viscous):
+
+* tgv256_samples.json -- after 1, 10 and 100 RK3 steps at a 12^3 lattice of nodes;
+* tgv256_lattice32.npz -- after 100 steps at every 8th node along each axis (32^3 nodes),
+  for the per-field L2 / Linf report of mixed precision.
 
 The GPU tests compare their own 256^3 runs (FP64 and mixed) at these nodes.  Runs only the
 CPU oracle (and the seeded input generator); about an hour on 8 cores.
@@ -22,6 +25,8 @@ N = 256
 SAVE = (1, 10, 100)
 # 12 sample indices per axis, spread over the block and off the grid's symmetry planes
 IDX = [int(v) for v in (5 + 21 * np.arange(12))]
+# every 8th node, off the block's faces
+IDX32 = [int(v) for v in (3 + 8 * np.arange(32))]
 
 
 def main():
@@ -45,6 +50,11 @@ def main():
             out["values"][str(s)] = [[[[float(v) for v in row] for row in plane] for plane in f] for f in sub]
             with open(os.path.join(HERE, "tgv256_samples.json"), "w") as fh:
                 json.dump(out, fh)
+    i32 = np.array(IDX32) + 3
+    np.savez(os.path.join(HERE, "tgv256_lattice32.npz"), index=np.array(IDX32), dt=np.float64(dt), step=np.int64(max(SAVE)),
+             values=np.ascontiguousarray(q[:, i32][:, :, i32][:, :, :, i32]),
+             layout=np.array("values[field][k][j][i] at the interior nodes (index[k], index[j], index[i])"),
+             made_by=np.array("tests/golden/make_tgv256_samples.py (CPU oracle only)"))
     print("done", time.time() - t0)
 
 
