@@ -333,8 +333,10 @@ int cfd_sweep_order(int* dirs);
 int cfd_tile_config_count(void);
 int cfd_tile_config(int cfg, int* lines, int* nodes, int* threads);
 /* Tile shape per direction (cfg[0..2] for xi, eta, zeta) of a block's own launches
- * (cfd_rhs, cfd_rk_stage, cfd_rhs_sweeps, cfd_rk_sweeps).  Every shape gives the same
- * bits; the default is the library's choice for large blocks.                           */
+ * (cfd_rhs, cfd_rk_stage, cfd_rhs_sweeps, cfd_rk_sweeps).  Every shape does the same
+ * arithmetic per node; each is a separately compiled kernel whose multiply-add
+ * contraction may differ, so shapes agree to round-off.  The default is the library's
+ * choice for large blocks.                                                               */
 int cfd_block_set_tiles(cfd_block* b, const int* cfg);
 int cfd_block_tiles(const cfd_block* b, int* cfg);
 
