@@ -70,6 +70,18 @@ def test_periodic_step_per_block_and_batched():
     _run(wl, 3, batch=True)
 
 
+def test_wall_face_with_a_connected_slot():
+    """A 12-node tall slot [0, 20) x [10, 22) in front of the block [20, 48) x all of the
+    48 x 32 x 16 channel: that block's i faces are wall below and above the slot and
+    connected in between (their uncovered parts are two rectangles each), the slot's
+    j faces are walls.  3 RK3 steps per block and batched."""
+    wl = W.split_boxes(W.channel(48, 32, 16, mach=0.3, reynolds=1000.0), [(0, 20, 10, 22, 0, 16), (20, 48, 0, 32, 0, 16)],
+                       "channel_slot_48x32x16")
+    assert wl.blocks[1].bc[:2] == (B.CFD_BC_WALL, B.CFD_BC_WALL) and wl.blocks[0].bc[2:4] == (B.CFD_BC_WALL,) * 2
+    _run(wl, 3)
+    _run(wl, 3, batch=True)
+
+
 def test_periodic_step_mixed_batched():
     """Mixed precision, batched: normwise within 1e-5 of the FP64 oracle after 3 steps."""
     _run(W.periodic_step(), 3, batch=True, precision=B.CFD_MIXED, tol=1e-5)
