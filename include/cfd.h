@@ -223,6 +223,8 @@ int cfd_exchange_create(cfd_block* const* blocks, int nb, const cfd_interface* i
  * block with the one-sided viscous closure (it treats the whole face as physical).       */
 int cfd_exchange_create_patched(cfd_block* const* blocks, int nb, const cfd_patch* p, int np,
                                 cfd_exchange** out);
+/* Free a plan (NULL is a no-op).  A plan refers to its blocks: destroy it (and any batch
+ * made with it) before them.                                                             */
 int cfd_exchange_destroy(cfd_exchange* x);
 /* Refill halos by on-device copies (Sec. 4.2: blocks of one process exchange on the
  * device).  field_set CFD_FIELDS_Q: block_bufs[b] is block b's caller-owned Q (5 planes);
