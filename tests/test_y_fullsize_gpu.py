@@ -225,6 +225,17 @@ def _tgv256_samples():
     return gold["dt"], ix, ref
 
 
+GOLD_TGV256_32 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "tgv256_lattice32.npz")
+
+
+def _tgv256_lattice32():
+    """The oracle's state after 100 steps at every 8th node (32^3 nodes)."""
+    if not os.path.exists(GOLD_TGV256_32):
+        pytest.skip("tests/golden/tgv256_lattice32.npz not generated")
+    with np.load(GOLD_TGV256_32) as z:
+        return int(z["step"]), float(z["dt"]), np.array(z["index"]) + 3, np.array(z["values"])
+
+
 def _sample(a, ix):
     return a[:, ix][:, :, ix][:, :, :, ix]
 
@@ -241,39 +252,57 @@ def test_taylor_green_256_fp64_steps_1_10_100():
     calls and tiles, against the oracle's states after 1, 10 and 100 steps (stored at a
     12^3 lattice of nodes by tests/golden/make_tgv256_samples.py).  Independent runs whose
     per-step round-off (~1e-15 per step) accumulates: 1e-12 at every saved step (measured
-    6.6e-13 after 100 steps)."""
+    6.6e-13 after 100 steps).  After 100 steps also at the 32^3 lattice of every 8th node."""
     dt, ix, ref = _tgv256_samples()
+    s32, dt32, ix32, ref32 = _tgv256_lattice32()
+    assert dt32 == dt and s32 == max(ref)
     wl = W.taylor_green_wavy(256)
     dev = DevBlock(wl, pitched=True)
     try:
         for s in range(1, max(ref) + 1):
             dev.step(dt)
             if s in ref:
-                got = _sample(dev.host(dev.q), ix)
-                err = _sample_normwise(got, ref[s])
+                q = dev.host(dev.q)
+                err = _sample_normwise(_sample(q, ix), ref[s])
                 print(f"step {s}: normwise (rho, momentum, e) {err}", flush=True)
                 assert np.all(err < TOL), (s, err)
+                if s == s32:
+                    err = _sample_normwise(_sample(q, ix32), ref32)
+                    print(f"step {s}, 32^3 lattice: normwise (rho, momentum, e) {err}", flush=True)
+                    assert np.all(err < TOL), (s, err)
     finally:
         dev.close()
 
 
+def _report_fields(label, got, ref):
+    for f, name in enumerate(("rho", "rho u", "rho v", "rho w", "E")):
+        d = got[f] - ref[f]
+        print(f"{label} {name}: L2 {np.sqrt(np.mean(d * d)):.3e} Linf {np.max(np.abs(d)):.3e}")
+
+
 def test_taylor_green_256_mixed_100_steps_vs_oracle():
-    """The same case in mixed precision: per-field L2 and Linf over the sample nodes against
-    the FP64 oracle after 1, 10 and 100 steps (reported), normwise error bounded by 2e-5
-    as at 64^3."""
+    """The same case in mixed precision: per-field L2 and Linf against the FP64 oracle
+    after 1, 10 and 100 steps over the 12^3 sample nodes, and after 100 steps over the
+    32^3 lattice of every 8th node (reported); normwise error bounded by 2e-5 as at 64^3."""
     dt, ix, ref = _tgv256_samples()
+    s32, _, ix32, ref32 = _tgv256_lattice32()
     wl = W.taylor_green_wavy(256)
     dev = DevBlock(wl, precision=B.CFD_MIXED, pitched=True)
     try:
         for s in range(1, max(ref) + 1):
             dev.step(dt)
             if s in ref:
-                got = _sample(dev.host(dev.q), ix)
-                for f, name in enumerate(("rho", "rho u", "rho v", "rho w", "E")):
-                    d = got[f] - ref[s][f]
-                    print(f"step {s} {name}: L2 {np.sqrt(np.mean(d * d)):.3e} Linf {np.max(np.abs(d)):.3e}")
+                q = dev.host(dev.q)
+                got = _sample(q, ix)
+                _report_fields(f"step {s}", got, ref[s])
                 err = _sample_normwise(got, ref[s])
                 print(f"step {s}: normwise (rho, momentum, e) {err}", flush=True)
                 assert np.all(err < 2e-5)
+                if s == s32:
+                    got = _sample(q, ix32)
+                    _report_fields(f"step {s}, 32^3 lattice", got, ref32)
+                    err = _sample_normwise(got, ref32)
+                    print(f"step {s}, 32^3 lattice: normwise (rho, momentum, e) {err}", flush=True)
+                    assert np.all(err < 2e-5)
     finally:
         dev.close()
