@@ -120,3 +120,53 @@ def test_patched_exchange_errors():
     with pytest.raises(B.CfdError) as e:
         DevMulti(os_step)
     assert e.value.code == B.CFD_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("orient", range(8))
+def test_oriented_patches_match_the_oracle(orient):
+    """Block A's i+ face (9 x 11 nodes along j, k) against block B's k- face under each
+    tangential orientation, the faces joined by four patches of a 2 x 2 cut: the GPU's halo
+    refill (copies and far-field ghosts) equals the oracle's on random states.  The partner
+    rectangles follow from the orientation's definition; orientations that reverse the
+    handedness are refused."""
+    import torch
+    from tests.test_patched_oracle import _two_blocks
+    rng = np.random.default_rng(orient)
+    ca, cb, qa, qb, (n1, n2) = _two_blocks(orient, rng)
+    cuts1, cuts2 = (0, 4, n1), (0, 6, n2)
+    patches = []
+    for x in range(2):
+        for y in range(2):
+            lo = (cuts1[x], cuts2[y])
+            n = (cuts1[x + 1] - cuts1[x], cuts2[y + 1] - cuts2[y])
+            N = (n1, n2)
+            rng_b = [(N[q] - lo[q] - n[q]) if (orient >> (1 + q)) & 1 else lo[q] for q in range(2)]
+            b_lo = (rng_b[1], rng_b[0]) if orient & 1 else (rng_b[0], rng_b[1])
+            patches.append(W.Patch(0, 1, lo, n, 1, 4, b_lo, orient))
+    s = torch.cuda.current_stream()
+    descs = [B.make_desc(c.ni, c.nj, c.nk, bc=tuple(c.bc), viscous=False) for c in (ca, cb)]
+    hs = [B.cfd_block_create(d, s) for d in descs]
+    try:
+        try:
+            x = B.cfd_exchange_create_patched(hs, patches)
+        except B.CfdError as e:
+            # a map that reverses handedness: the oracle (which does not check it) is not consulted
+            assert e.code == B.CFD_ERR_ARG and "handedness" in str(e)
+            return
+        try:
+            bufs = [B.upload_state(d, q) for d, q in zip(descs, (qa, qb))]
+            B.cfd_halo_exchange(x, B.CFD_FIELDS_Q, bufs)
+            got = [B.download_state(d, t) for d, t in zip(descs, bufs)]
+        finally:
+            B.cfd_exchange_destroy(x)
+        ref = O.halo_patched([ca, cb], None, [qa, qb], patches)
+        for g_, r_ in zip(got, ref):
+            np.testing.assert_array_equal(g_[:, 3:-3, 3:-3, 3:-3], r_[:, 3:-3, 3:-3, 3:-3])
+        np.testing.assert_array_equal(got[0][:, 3:-3, 3:-3, -3:], ref[0][:, 3:-3, 3:-3, -3:])
+        np.testing.assert_array_equal(got[1][:, :3, 3:-3, 3:-3], ref[1][:, :3, 3:-3, 3:-3])
+        # the far-field faces' ghosts
+        np.testing.assert_array_equal(got[0][:, 3:-3, 3:-3, :3], ref[0][:, 3:-3, 3:-3, :3])
+        np.testing.assert_array_equal(got[1][:, -3:, 3:-3, 3:-3], ref[1][:, -3:, 3:-3, 3:-3])
+    finally:
+        for h in hs:
+            B.cfd_block_destroy(h)
