@@ -1354,12 +1354,6 @@ int batch_set_tuning(cfd_batch* bt, const int* cfg, const int* persist) {
   return CFD_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-namespace {
-
 // the same patch seen from block_b: corners trade places, the extents follow b's axes and
 // the orientation is inverted
 cfd_patch patch_seen_from_b(const cfd_patch& p) {
@@ -1517,6 +1511,8 @@ int build_exchange(cfd_block* const* blocks, int nb, const std::vector<cfd_patch
 }
 
 }  // namespace
+
+extern "C" {
 
 int cfd_exchange_create(cfd_block* const* blocks, int nb, const cfd_interface* ifc, int nifc, cfd_exchange** out) {
   if (!out) return fail(CFD_ERR_ARG, "null output handle");
