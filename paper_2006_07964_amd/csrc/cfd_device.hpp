@@ -86,25 +86,20 @@ struct Gas {
 // e = 1 - x y^2, 1/sqrt(x) = y (1 + e/2 + 3 e^2/8 + ...).  Keeping the terms through e^2
 // leaves an error of order e^3; the FP64 estimates are good to about 5e-8, so that is
 // ~1e-22, below the rounding of the result, in fewer operations than two Newton steps.
-// One Newton step for float.
+// Float takes the hardware estimates as they are (within 1 ulp): a refinement step would
+// cost the FP32 sweeps, whose VALU issue is their bound, about 5% of their instructions.
 __device__ __forceinline__ double rcp(double x) {
   const double r = __builtin_amdgcn_rcp(x);
   const double e = fma(-x, r, 1.0);
   return fma(r, fma(e, e, e), r);
 }
-__device__ __forceinline__ float rcp(float x) {
-  float r = __builtin_amdgcn_rcpf(x);
-  return fmaf(r, fmaf(-x, r, 1.0f), r);
-}
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double rsq(double x) {
   const double y = __builtin_amdgcn_rsq(x);
   const double e = fma(-x * y, y, 1.0);
   return fma(y, e * fma(0.375, e, 0.5), y);
 }
-__device__ __forceinline__ float rsq(float x) {
-  float y = __builtin_amdgcn_rsqf(x);
-  return fmaf(0.5f * y, fmaf(-x * y, y, 1.0f), y);
-}
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
 // ---- sixth-order central difference (Sec. 2 after Eq 8), unit spacing ---------------
 // g(m) returns the value at offset m in [-3, 3] (the centre is not used).
@@ -139,17 +134,20 @@ __device__ __forceinline__ void phys_flux(const R q[5], R mx, R my, R mz, const 
 // lambda^{+-} = (lambda +- |lambda|)/2 and
 // F = rho/(2 gamma) [2 (gamma-1) l1 (1,u,v,w,|u|^2/2) + l4 (1, u + c k, H + c theta)
 //                    + l5 (1, u - c k, H - c theta)].
+// minv = 1/|m| (from metric_rsq, which an interface's two sides may share)
+template <typename R>
+__device__ __forceinline__ R metric_rsq(R mx, R my, R mz) {
+  return rsq(mx * mx + my * my + mz * mz);
+}
 template <int SIGN, typename R>
-__device__ __forceinline__ void sw_flux(const R q[5], R mx, R my, R mz, const Gas<R>& G, R F[5]) {
+__device__ __forceinline__ void sw_flux(const R q[5], R mx, R my, R mz, R minv, const Gas<R>& G, R F[5]) {
   const R rinv = rcp(q[0]);
   const R u = q[1] * rinv, v = q[2] * rinv, w = q[3] * rinv;
   const R ke = R(0.5) * (u * u + v * v + w * w);
   const R p = G.gm1 * (q[4] - q[0] * ke);
   const R c2 = G.gamma * p * rinv;
   const R c = c2 * rsq(c2);
-  const R m2 = mx * mx + my * my + mz * mz;
-  const R minv = rsq(m2);
-  const R mag = m2 * minv;
+  const R mag = (mx * mx + my * my + mz * mz) * minv;
   const R mu = mx * u + my * v + mz * w;  // |m| theta
   const R H = (q[4] + p) * rinv;
   const R l1 = mu, l4 = mu + mag * c, l5 = mu - mag * c;

@@ -437,13 +437,35 @@ struct SweepLds {
 // AFWENO, Figs 10-11) or at the half points (original AFWENO, Fig 9).
 constexpr int kModified = 0, kOriginal = 1;
 
+// Half-point metrics of the modified scheme in FP32: formed once per interface, by the
+// thread of the node left of it, and read from LDS by the thread of the node right of it.
+// FP64 forms them on both sides: the LDS they would take costs its sweeps a workgroup per
+// CU, while FP32 issue is the bound of the mixed-precision sweeps.
+template <typename R>
+constexpr bool kHalfLds = sizeof(R) == 4;
+
+// LDS of one workgroup for the largest tile configuration in use.
+template <typename R, typename S, int TW, int TS>
+struct SweepShared {
+  R F[5 * TW * SweepLds<TW, TS>::NH];   // interface fluxes f(n+1/2)
+  S Fn[5 * TW * SweepLds<TW, TS>::NN];  // staged Q, then nodal fluxes
+  double M[3 * TW * SweepLds<TW, TS>::NN];  // node metrics of the sweep direction
+  R V[(sizeof(R) == 8 || sizeof(S) == sizeof(R)) ? 4 * TW * SweepLds<TW, TS>::NN : 1];  // viscous fluxes
+  R H[kHalfLds<R> ? 4 * TW * SweepLds<TW, TS>::NH : 1];  // half-point metric and 1/|m| (FP32)
+};
+
 // One tile of a direction sweep: t is the logical tile index inside the block (sweep-
 // direction tile fastest, then the cross tile c1, then the cross index c2).
 // OS: some block of the launch has faces with the one-sided viscous closure (a separate
 // instantiation keeps the register budget of the others)
 template <int DIR, typename R, int TW, int TS, int NT, int SCHEME = kModified, bool OS = false>
-__device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBlock& b, int t, R* sF, StageT<R, DIR>* sFn,
-                                           double* sM, R* sV) {
+__device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBlock& b, int t,
+                                           SweepShared<R, StageT<R, DIR>, TW, TS>& sh) {
+  R* const sF = sh.F;
+  StageT<R, DIR>* const sFn = sh.Fn;
+  double* const sM = sh.M;
+  R* const sV = sh.V;
+  R* const sH = sh.H;
   constexpr int NH = SweepLds<TW, TS>::NH;
   constexpr int NN = SweepLds<TW, TS>::NN;
   constexpr int NW = SweepLds<TW, TS>::NW;
@@ -618,18 +640,30 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
           const R hx = R(half_metric([&](int m) { return sM[L::f(0, w, sc + m, NN)]; }));
           const R hy = R(half_metric([&](int m) { return sM[L::f(1, w, sc + m, NN)]; }));
           const R hz = R(half_metric([&](int m) { return sM[L::f(2, w, sc + m, NN)]; }));
-          sw_flux<+1>(ul, hx, hy, hz, G, F);
+          const R hinv = metric_rsq(hx, hy, hz);
+          if constexpr (kHalfLds<R>) {  // for the F- of the node right of n+1/2
+            sH[L::f(0, w, s, NH)] = hx;
+            sH[L::f(1, w, s, NH)] = hy;
+            sH[L::f(2, w, s, NH)] = hz;
+            sH[L::f(3, w, s, NH)] = hinv;
+          }
+          sw_flux<+1>(ul, hx, hy, hz, hinv, G, F);
 #pragma unroll
           for (int v = 0; v < 5; ++v) sF[L::f(v, w, s, NH)] = F[v];
         }
         if (need_m) {
-          R ur[5];
-          unproject(B, G, vr, ur);
-          // half point n-1/2 = (n-1)+1/2, centred on staged index sc-1
-          const R hx = R(half_metric([&](int m) { return sM[L::f(0, w, sc - 1 + m, NN)]; }));
-          const R hy = R(half_metric([&](int m) { return sM[L::f(1, w, sc - 1 + m, NN)]; }));
-          const R hz = R(half_metric([&](int m) { return sM[L::f(2, w, sc - 1 + m, NN)]; }));
-          sw_flux<-1>(ur, hx, hy, hz, G, Fkeep);
+          if constexpr (kHalfLds<R>) {
+            // the state right of n-1/2; its F- waits for the half-point metric in LDS
+            unproject(B, G, vr, Fkeep);
+          } else {
+            R ur[5];
+            unproject(B, G, vr, ur);
+            // half point n-1/2 = (n-1)+1/2, centred on staged index sc-1
+            const R hx = R(half_metric([&](int m) { return sM[L::f(0, w, sc - 1 + m, NN)]; }));
+            const R hy = R(half_metric([&](int m) { return sM[L::f(1, w, sc - 1 + m, NN)]; }));
+            const R hz = R(half_metric([&](int m) { return sM[L::f(2, w, sc - 1 + m, NN)]; }));
+            sw_flux<-1>(ur, hx, hy, hz, metric_rsq(hx, hy, hz), G, Fkeep);
+          }
         }
       }
     } else {
@@ -669,11 +703,11 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
         for (int f = 0; f < 5; ++f) vr[f] = weno_left(V[0][f], V[4][f], V[3][f], V[2][f], V[1][f], eps, linear);
         // this thread alone writes slot s: F+ goes to LDS, F- is added to it
         unproject(B, G, vl, uh);
-        sw_flux<+1>(uh, hm(0), hm(1), hm(2), G, F);
+        sw_flux<+1>(uh, hm(0), hm(1), hm(2), metric_rsq(hm(0), hm(1), hm(2)), G, F);
 #pragma unroll
         for (int v = 0; v < 5; ++v) sF[L::f(v, w, s, NH)] = F[v];
         unproject(B, G, vr, uh);
-        sw_flux<-1>(uh, hm(0), hm(1), hm(2), G, F);
+        sw_flux<-1>(uh, hm(0), hm(1), hm(2), metric_rsq(hm(0), hm(1), hm(2)), G, F);
 #pragma unroll
         for (int v = 0; v < 5; ++v) sF[L::f(v, w, s, NH)] += F[v];
       }
@@ -686,6 +720,15 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
     }
     __syncthreads();
     if (need_m) {  // each interface receives exactly one F-
+      if constexpr (SCHEME == kModified && kHalfLds<R>) {
+        // Fkeep holds the state; the thread of node n-1 stored the metric of n-1/2
+        const int hs = sw_ - 1;
+        R F[5];
+        sw_flux<-1>(Fkeep, sH[L::f(0, ww, hs, NH)], sH[L::f(1, ww, hs, NH)], sH[L::f(2, ww, hs, NH)],
+                    sH[L::f(3, ww, hs, NH)], G, F);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Fkeep[v] = F[v];
+      }
 #pragma unroll
       for (int v = 0; v < 5; ++v) sF[L::f(v, ww, sw_ - 1, NH)] += Fkeep[v];
     }
@@ -770,27 +813,18 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
   }
 }
 
-// LDS of one workgroup for the largest tile configuration in use.
-template <typename R, typename S, int TW, int TS>
-struct SweepShared {
-  R F[5 * TW * SweepLds<TW, TS>::NH];   // interface fluxes f(n+1/2)
-  S Fn[5 * TW * SweepLds<TW, TS>::NN];  // staged Q, then nodal fluxes
-  double M[3 * TW * SweepLds<TW, TS>::NN];  // node metrics of the sweep direction
-  R V[(sizeof(R) == 8 || sizeof(S) == sizeof(R)) ? 4 * TW * SweepLds<TW, TS>::NN : 1];  // viscous fluxes
-};
-
 // Single block: one workgroup per tile, ids remapped XCD-contiguously.
 template <int DIR, typename R, int TW, int TS, int NT, int SCHEME, bool OS>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep(SweepArgs a) {
   __shared__ SweepShared<R, StageT<R, DIR>, TW, TS> sh;
-  sweep_tile<DIR, R, TW, TS, NT, SCHEME, OS>(a.c, a.b, xcd_remap(blockIdx.x, gridDim.x), sh.F, sh.Fn, sh.M, sh.V);
+  sweep_tile<DIR, R, TW, TS, NT, SCHEME, OS>(a.c, a.b, xcd_remap(blockIdx.x, gridDim.x), sh);
 }
 // the original scheme in FP64 holds six stencil points and the half-point basis at once:
 // three waves per SIMD give it the registers that four would make it spill
 template <int DIR, typename R, int TW, int TS, int NT, bool OS>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_sweep_w3(SweepArgs a) {
   __shared__ SweepShared<R, StageT<R, DIR>, TW, TS> sh;
-  sweep_tile<DIR, R, TW, TS, NT, kOriginal, OS>(a.c, a.b, xcd_remap(blockIdx.x, gridDim.x), sh.F, sh.Fn, sh.M, sh.V);
+  sweep_tile<DIR, R, TW, TS, NT, kOriginal, OS>(a.c, a.b, xcd_remap(blockIdx.x, gridDim.x), sh);
 }
 
 // Batched blocks: one launch walks a work list covering the tiles of every block
@@ -807,7 +841,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(PERSIST && s
     const int t = xcd_remap(blockIdx.x, gridDim.x);
     int blk = 0;
     while (t >= tl.prefix[blk + 1]) ++blk;
-    sweep_tile<DIR, R, TW, TS, NT, kModified, OS>(c, blocks[blk], t - tl.prefix[blk], sh.F, sh.Fn, sh.M, sh.V);
+    sweep_tile<DIR, R, TW, TS, NT, kModified, OS>(c, blocks[blk], t - tl.prefix[blk], sh);
     return;
   }
   static_assert(!(PERSIST && OS), "the persistent schedule is not built for one-sided closures");
@@ -817,7 +851,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(PERSIST && s
   for (int u = lane_wg; u < count; u += nwg_x) {
     const int t = start + u;
     while (t >= tl.prefix[blk + 1]) ++blk;  // t only grows, so the scan resumes
-    sweep_tile<DIR, R, TW, TS, NT>(c, blocks[blk], t - tl.prefix[blk], sh.F, sh.Fn, sh.M, sh.V);
+    sweep_tile<DIR, R, TW, TS, NT>(c, blocks[blk], t - tl.prefix[blk], sh);
     __syncthreads();  // the next tile overwrites the LDS this one read
   }
 }
@@ -830,7 +864,7 @@ __device__ __forceinline__ void batch_orig_tile(const SweepBlock* __restrict__ b
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   int blk = 0;
   while (t >= tl.prefix[blk + 1]) ++blk;
-  sweep_tile<DIR, R, TW, TS, NT, kOriginal, OS>(c, blocks[blk], t - tl.prefix[blk], sh.F, sh.Fn, sh.M, sh.V);
+  sweep_tile<DIR, R, TW, TS, NT, kOriginal, OS>(c, blocks[blk], t - tl.prefix[blk], sh);
 }
 template <int DIR, typename R, int TW, int TS, int NT, bool OS>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 3 : 4))) void k_sweep_batch_orig(
