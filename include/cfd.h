@@ -149,7 +149,9 @@ const char* cfd_last_error(void);
 /* Create a block: validates d, allocates the 10 metric planes (Sec. 2, Eqs 7-8) and the
  * scratch of the RHS (12 viscous-flux planes, Eqs 5-6, and 5 partial-sum planes, in the
  * compute type; a CFD_MIXED block also keeps the metric planes rounded to FP32 for its
- * FP32 viscous terms) on the current device.  hip_stream (hipStream_t, may be NULL =
+ * FP32 arithmetic, and the metrics of the half points between nodes, which Sec. 4.5
+ * interpolates from the node values where they are used, interpolated once in FP64 and
+ * rounded) on the current device.  hip_stream (hipStream_t, may be NULL =
  * default stream) is the stream later calls enqueue on.  Errors: CFD_ERR_ARG,
  * CFD_ERR_ALLOC, CFD_ERR_UNSUPPORTED (a plane of 2^29 points or more).                   */
 int cfd_block_create(const cfd_block_desc* d, void* hip_stream, cfd_block** out);

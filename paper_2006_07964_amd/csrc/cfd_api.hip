@@ -131,7 +131,9 @@ struct cfd_block {
   double* met = nullptr;  // 10 planes FP64
   void* vis = nullptr;    // 12 planes (compute type)
   void* rt = nullptr;     // 5 planes (compute type)
-  void* met_r = nullptr;  // metrics in the compute type: met itself (FP64) or a rounded copy (mixed)
+  // metrics in the compute type: met itself (FP64), or (mixed) a rounded copy followed by
+  // the 9 half-point metric planes of the sweeps
+  void* met_r = nullptr;
   void* met_raw = nullptr;  // allocations behind met, met_r, vis, rt (see aligned_planes)
   void* met_r_raw = nullptr;
   void* vis_raw = nullptr;
@@ -464,6 +466,7 @@ int run_sweeps(cfd_block* b, const double* Q, unsigned mask, int out_kind, doubl
   a.b.g = b->g;
   a.b.q = Q;
   a.b.met = b->met;
+  a.b.met_r = b->esize == sizeof(double) ? nullptr : static_cast<const float*>(b->met_r);
   a.b.vis = b->vis;
   a.b.qn = qn;
   a.b.dt_field = b->dt_field;
@@ -579,7 +582,8 @@ int cfd_block_create(const cfd_block_desc* d, void* hip_stream, cfd_block** out)
   if (aligned_planes(plane, 10, sizeof(double), &b->met_raw, &mbase)) return cleanup(CFD_ERR_ALLOC, "metrics allocation");
   b->met = static_cast<double*>(mbase);
   b->met_r = b->met;
-  if (b->esize != sizeof(double) && aligned_planes(plane, 10, b->esize, &b->met_r_raw, &b->met_r))
+  // mixed precision: the metric planes rounded to FP32 and the 9 half-point metric planes
+  if (b->esize != sizeof(double) && aligned_planes(plane, 10 + 9, b->esize, &b->met_r_raw, &b->met_r))
     return cleanup(CFD_ERR_ALLOC, "metrics allocation");
   if (aligned_planes(plane, 12, b->esize, &b->vis_raw, &b->vis)) return cleanup(CFD_ERR_ALLOC, "viscous scratch allocation");
   if (aligned_planes(plane, 5, b->esize, &b->rt_raw, &b->rt)) return cleanup(CFD_ERR_ALLOC, "partial-sum allocation");
@@ -587,7 +591,7 @@ int cfd_block_create(const cfd_block_desc* d, void* hip_stream, cfd_block** out)
       hipMalloc((void**)&b->flag_dev, sizeof(int)) != hipSuccess)
     return cleanup(CFD_ERR_ALLOC, "reduction scratch");
   if (hipEventCreateWithFlags(&b->ev, hipEventDisableTiming) != hipSuccess) return cleanup(CFD_ERR_HIP, "block event");
-  b->bytes = (int64_t)plane * (10 * 8 + (b->esize == sizeof(double) ? 17 : 27) * (int64_t)b->esize);
+  b->bytes = (int64_t)plane * (10 * 8 + (b->esize == sizeof(double) ? 17 : 36) * (int64_t)b->esize);
   // block-local viscous halo work
   std::vector<CopySeg> cs;
   std::vector<BcSeg> bs;
@@ -657,9 +661,12 @@ int cfd_metrics(cfd_block* b, const double* xyz, int64_t cld_i, int64_t cld_j) {
   int rc = CFD_OK;
   hipError_t e = hipMemsetAsync(b->flag_dev, 0, sizeof(int), b->stream);
   if (e == hipSuccess) e = launch_metrics(a, b->stream);
-  // the FP32 consumers of a mixed block read the metrics rounded once here
+  // the FP32 consumers of a mixed block read the metrics rounded once here, and its sweeps
+  // the half-point metrics interpolated once in FP64 and rounded
   if (e == hipSuccess && b->met_r != b->met)
     e = launch_round(b->met, static_cast<float*>(b->met_r), (int64_t)10 * b->g.plane, b->stream);
+  if (e == hipSuccess && b->met_r != b->met)
+    e = launch_half_metrics(b->g, b->met, static_cast<float*>(b->met_r) + 10 * b->g.plane, b->stream);
   int bad = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&bad, b->flag_dev, sizeof(int), hipMemcpyDeviceToHost, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
@@ -1135,6 +1142,7 @@ void build_args(cfd_batch* bt, double* const* Qn, double* const* QA, double* con
         a.g = B->g;
         a.q = cur[b];
         a.met = B->met;
+        a.met_r = B->esize == sizeof(double) ? nullptr : static_cast<const float*>(B->met_r);
         a.vis = B->vis;
         a.rt_in = B->rt;
         a.rt_out = B->rt;

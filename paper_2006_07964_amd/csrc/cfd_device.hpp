@@ -134,20 +134,17 @@ __device__ __forceinline__ void phys_flux(const R q[5], R mx, R my, R mz, const 
 // lambda^{+-} = (lambda +- |lambda|)/2 and
 // F = rho/(2 gamma) [2 (gamma-1) l1 (1,u,v,w,|u|^2/2) + l4 (1, u + c k, H + c theta)
 //                    + l5 (1, u - c k, H - c theta)].
-// minv = 1/|m| (from metric_rsq, which an interface's two sides may share)
-template <typename R>
-__device__ __forceinline__ R metric_rsq(R mx, R my, R mz) {
-  return rsq(mx * mx + my * my + mz * mz);
-}
 template <int SIGN, typename R>
-__device__ __forceinline__ void sw_flux(const R q[5], R mx, R my, R mz, R minv, const Gas<R>& G, R F[5]) {
+__device__ __forceinline__ void sw_flux(const R q[5], R mx, R my, R mz, const Gas<R>& G, R F[5]) {
   const R rinv = rcp(q[0]);
   const R u = q[1] * rinv, v = q[2] * rinv, w = q[3] * rinv;
   const R ke = R(0.5) * (u * u + v * v + w * w);
   const R p = G.gm1 * (q[4] - q[0] * ke);
   const R c2 = G.gamma * p * rinv;
   const R c = c2 * rsq(c2);
-  const R mag = (mx * mx + my * my + mz * mz) * minv;
+  const R m2 = mx * mx + my * my + mz * mz;
+  const R minv = rsq(m2);
+  const R mag = m2 * minv;
   const R mu = mx * u + my * v + mz * w;  // |m| theta
   const R H = (q[4] + p) * rinv;
   const R l1 = mu, l4 = mu + mag * c, l5 = mu - mag * c;

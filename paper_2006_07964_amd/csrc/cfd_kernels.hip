@@ -351,6 +351,33 @@ hipError_t launch_round(const double* src, float* dst, int64_t n, hipStream_t s)
   return hipGetLastError();
 }
 
+// Half-point metrics of a mixed-precision block (one thread per stored node and direction).
+__global__ __launch_bounds__(256) void k_half_metric(Geom g, const double* __restrict__ met, float* __restrict__ hm) {
+  const int64_t pl = g.plane;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < 3 * pl; e += (int64_t)gridDim.x * 256) {
+    const int d = (int)(e / pl);
+    const int64_t p = e - d * pl;
+    const int64_t ij = g.ld_i * g.ld_j;
+    const int idx = d == 0 ? (int)(p % g.ld_i) - kHalo
+                  : d == 1 ? (int)((p / g.ld_i) % g.ld_j) - kHalo
+                           : (int)(p / ij) - kHalo;
+    const int nd = d == 0 ? g.ni : d == 1 ? g.nj : g.nk;
+    if (idx < -1 || idx > nd - 1) continue;  // the stencil idx-2 .. idx+3 stays in the halo
+    const int64_t st = d == 0 ? 1 : d == 1 ? g.ld_i : ij;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double* m = met + (3 * d + c) * pl + p;
+      hm[(3 * d + c) * pl + p] = float(half_metric([&](int o) { return m[o * st]; }));
+    }
+  }
+}
+
+hipError_t launch_half_metrics(const Geom& g, const double* met, float* hm, hipStream_t s) {
+  const int64_t nwg = (3 * g.plane + 255) / 256;
+  hipLaunchKernelGGL(k_half_metric, dim3((unsigned)(nwg < 65536 ? nwg : 65536)), dim3(256), 0, s, g, met, hm);
+  return hipGetLastError();
+}
+
 // chunk length and tile count of one block (i-tile fastest, then j-tile, then k-chunk):
 // at most kViscChunk planes per tile, that bound halved (down to 8) while the block would
 // give fewer than min_tiles workgroups, and nk split into the fewest chunks of equal length
@@ -437,21 +464,24 @@ struct SweepLds {
 // AFWENO, Figs 10-11) or at the half points (original AFWENO, Fig 9).
 constexpr int kModified = 0, kOriginal = 1;
 
-// Half-point metrics of the modified scheme in FP32: formed once per interface, by the
-// thread of the node left of it, and read from LDS by the thread of the node right of it.
-// FP64 forms them on both sides: the LDS they would take costs its sweeps a workgroup per
-// CU, while FP32 issue is the bound of the mixed-precision sweeps.
+// Metrics of a sweep in mixed precision: the node metrics are staged from their FP32
+// copy (every use rounds them to FP32) and the half-point metrics from the planes that
+// cfd_metrics interpolated once in FP64 and rounded (the values an FP64 interpolation in
+// the sweep would give, without its FP64 arithmetic in the FP32 sweeps, whose VALU issue
+// is their bound).  FP64 sweeps stage the FP64 node metrics and interpolate.
 template <typename R>
-constexpr bool kHalfLds = sizeof(R) == 4;
+constexpr bool kHalfPre = sizeof(R) == 4;
+template <typename R>
+using StageM = typename std::conditional<kHalfPre<R>, R, double>::type;
 
 // LDS of one workgroup for the largest tile configuration in use.
 template <typename R, typename S, int TW, int TS>
 struct SweepShared {
   R F[5 * TW * SweepLds<TW, TS>::NH];   // interface fluxes f(n+1/2)
   S Fn[5 * TW * SweepLds<TW, TS>::NN];  // staged Q, then nodal fluxes
-  double M[3 * TW * SweepLds<TW, TS>::NN];  // node metrics of the sweep direction
+  StageM<R> M[3 * TW * SweepLds<TW, TS>::NN];  // node metrics of the sweep direction
   R V[(sizeof(R) == 8 || sizeof(S) == sizeof(R)) ? 4 * TW * SweepLds<TW, TS>::NN : 1];  // viscous fluxes
-  R H[kHalfLds<R> ? 4 * TW * SweepLds<TW, TS>::NH : 1];  // half-point metric and 1/|m| (FP32)
+  R H[kHalfPre<R> ? 3 * TW * SweepLds<TW, TS>::NH : 1];  // half-point metrics (mixed precision)
 };
 
 // One tile of a direction sweep: t is the logical tile index inside the block (sweep-
@@ -463,7 +493,7 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
                                            SweepShared<R, StageT<R, DIR>, TW, TS>& sh) {
   R* const sF = sh.F;
   StageT<R, DIR>* const sFn = sh.Fn;
-  double* const sM = sh.M;
+  StageM<R>* const sM = sh.M;
   R* const sV = sh.V;
   R* const sH = sh.H;
   constexpr int NH = SweepLds<TW, TS>::NH;
@@ -502,9 +532,14 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
   const Gas<R> G(c.ph);
   const R eps = R(c.ph.eps);
   const bool linear = c.ph.linear != 0;
-  const GP<const double> mx = plane_ptr(met, (3 * DIR + 0) * plane);
-  const GP<const double> my = plane_ptr(met, (3 * DIR + 1) * plane);
-  const GP<const double> mz = plane_ptr(met, (3 * DIR + 2) * plane);
+  using MT = StageM<R>;
+  // node metrics of the direction (FP64, or their FP32 copy), half-point metrics (mixed)
+  const GP<const MT> mbase =
+      kHalfPre<R> ? (GP<const MT>)to_global(b.met_r) : (GP<const MT>)to_global(b.met);
+  const GP<const MT> mx = plane_ptr(mbase, (3 * DIR + 0) * plane);
+  const GP<const MT> my = plane_ptr(mbase, (3 * DIR + 1) * plane);
+  const GP<const MT> mz = plane_ptr(mbase, (3 * DIR + 2) * plane);
+  const GP<const float> hbase = kHalfPre<R> ? to_global(b.met_r) + (10 + 3 * DIR) * plane : nullptr;
 
   // ---- the output node of this thread (at most one per thread) and its global operands,
   // requested before the last barrier so that their latency overlaps the nodal-flux phase
@@ -561,9 +596,10 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
     // store, so the tile waits for one memory round trip rather than one per item.
     {
       constexpr int ITEMS = (TW * NN + NT - 1) / NT;
-      double ld[ITEMS][12];
-      bool ok[ITEMS];
-      int li[ITEMS];
+      double ld[ITEMS][12];  // Q, then (FP64) node metrics and viscous fluxes
+      R lr[ITEMS][10];       // mixed precision: node metrics, viscous fluxes, half-point metrics
+      bool ok[ITEMS], okh[ITEMS];
+      int li[ITEMS], lhi[ITEMS];
 #pragma unroll
       for (int it = 0; it < ITEMS; ++it) {
         const int e = threadIdx.x + it * NT;
@@ -577,26 +613,56 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
           const uint32_t p = origin + (uint32_t)c1 * s1 + (uint32_t)n * sd;
 #pragma unroll
           for (int v = 0; v < 5; ++v) ld[it][v] = ldg(plane_ptr(Q, v * plane), p);
-          ld[it][5] = ldg(mx, p);
-          ld[it][6] = ldg(my, p);
-          ld[it][7] = ldg(mz, p);
-          if (kStageVis && c.do_vis) {
+          if constexpr (kHalfPre<R>) {
+            lr[it][0] = ldg(mx, p);
+            lr[it][1] = ldg(my, p);
+            lr[it][2] = ldg(mz, p);
+            if (kStageVis && c.do_vis) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) ld[it][8 + v] = double(ldg(plane_ptr(vis, v * plane), p));
+              for (int v = 0; v < 4; ++v) lr[it][3 + v] = ldg(plane_ptr(vis, v * plane), p);
+            }
+            // the half point n+1/2 is interface slot s-2 (slots 0 .. ts, n <= nd-1)
+            okh[it] = s >= 2 && s <= ts + 2 && n <= nd - 1;
+            lhi[it] = L::f(0, w, s - 2, NH);
+            if (okh[it]) {
+#pragma unroll
+              for (int v = 0; v < 3; ++v) lr[it][7 + v] = ldg(plane_ptr(hbase, v * plane), p);
+            }
+          } else {
+            ld[it][5] = ldg(mx, p);
+            ld[it][6] = ldg(my, p);
+            ld[it][7] = ldg(mz, p);
+            if (kStageVis && c.do_vis) {
+#pragma unroll
+              for (int v = 0; v < 4; ++v) ld[it][8 + v] = double(ldg(plane_ptr(vis, v * plane), p));
+            }
           }
         }
       }
-      // plane v of an LDS array starts TW*NN entries after plane v-1 (both layouts)
+      // plane v of an LDS array starts TW*NN (TW*NH) entries after plane v-1 (both layouts)
 #pragma unroll
       for (int it = 0; it < ITEMS; ++it) {
         if (!ok[it]) continue;
 #pragma unroll
         for (int v = 0; v < 5; ++v) sFn[li[it] + v * TW * NN] = S(R(ld[it][v]));
+        if constexpr (kHalfPre<R>) {
 #pragma unroll
-        for (int v = 0; v < 3; ++v) sM[li[it] + v * TW * NN] = ld[it][5 + v];
-        if (kStageVis && c.do_vis) {
+          for (int v = 0; v < 3; ++v) sM[li[it] + v * TW * NN] = lr[it][v];
+          if (kStageVis && c.do_vis) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) sV[li[it] + v * TW * NN] = R(ld[it][8 + v]);
+            for (int v = 0; v < 4; ++v) sV[li[it] + v * TW * NN] = lr[it][3 + v];
+          }
+          if (okh[it]) {
+#pragma unroll
+            for (int v = 0; v < 3; ++v) sH[lhi[it] + v * TW * NH] = lr[it][7 + v];
+          }
+        } else {
+#pragma unroll
+          for (int v = 0; v < 3; ++v) sM[li[it] + v * TW * NN] = ld[it][5 + v];
+          if (kStageVis && c.do_vis) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sV[li[it] + v * TW * NN] = R(ld[it][8 + v]);
+          }
         }
       }
     }
@@ -634,35 +700,42 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
         R vl[5], vr[5];
 #pragma unroll
         for (int f = 0; f < 5; ++f) weno_pair(V[0][f], V[1][f], V[2][f], V[3][f], V[4][f], eps, linear, vl[f], vr[f]);
-        if (need_p) {
-          R ul[5], F[5];
-          unproject(B, G, vl, ul);
-          const R hx = R(half_metric([&](int m) { return sM[L::f(0, w, sc + m, NN)]; }));
-          const R hy = R(half_metric([&](int m) { return sM[L::f(1, w, sc + m, NN)]; }));
-          const R hz = R(half_metric([&](int m) { return sM[L::f(2, w, sc + m, NN)]; }));
-          const R hinv = metric_rsq(hx, hy, hz);
-          if constexpr (kHalfLds<R>) {  // for the F- of the node right of n+1/2
-            sH[L::f(0, w, s, NH)] = hx;
-            sH[L::f(1, w, s, NH)] = hy;
-            sH[L::f(2, w, s, NH)] = hz;
-            sH[L::f(3, w, s, NH)] = hinv;
-          }
-          sw_flux<+1>(ul, hx, hy, hz, hinv, G, F);
+        if constexpr (kHalfPre<R>) {
+          // half-point metrics from LDS: slot s holds n+1/2, slot s-1 holds n-1/2
+          if (need_p) {
+            R ul[5], F[5];
+            unproject(B, G, vl, ul);
+            const R hx = sH[L::f(0, w, s, NH)], hy = sH[L::f(1, w, s, NH)], hz = sH[L::f(2, w, s, NH)];
+            sw_flux<+1>(ul, hx, hy, hz, G, F);
 #pragma unroll
-          for (int v = 0; v < 5; ++v) sF[L::f(v, w, s, NH)] = F[v];
-        }
-        if (need_m) {
-          if constexpr (kHalfLds<R>) {
-            // the state right of n-1/2; its F- waits for the half-point metric in LDS
-            unproject(B, G, vr, Fkeep);
-          } else {
+            for (int v = 0; v < 5; ++v) sF[L::f(v, w, s, NH)] = F[v];
+          }
+          if (need_m) {
+            R ur[5];
+            unproject(B, G, vr, ur);
+            const R hx = sH[L::f(0, w, s - 1, NH)], hy = sH[L::f(1, w, s - 1, NH)], hz = sH[L::f(2, w, s - 1, NH)];
+            sw_flux<-1>(ur, hx, hy, hz, G, Fkeep);
+          }
+        } else {
+          // half-point metrics interpolated from the staged node metrics
+          if (need_p) {
+            R ul[5], F[5];
+            unproject(B, G, vl, ul);
+            const R hx = R(half_metric([&](int m) { return sM[L::f(0, w, sc + m, NN)]; }));
+            const R hy = R(half_metric([&](int m) { return sM[L::f(1, w, sc + m, NN)]; }));
+            const R hz = R(half_metric([&](int m) { return sM[L::f(2, w, sc + m, NN)]; }));
+            sw_flux<+1>(ul, hx, hy, hz, G, F);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) sF[L::f(v, w, s, NH)] = F[v];
+          }
+          if (need_m) {
             R ur[5];
             unproject(B, G, vr, ur);
             // half point n-1/2 = (n-1)+1/2, centred on staged index sc-1
             const R hx = R(half_metric([&](int m) { return sM[L::f(0, w, sc - 1 + m, NN)]; }));
             const R hy = R(half_metric([&](int m) { return sM[L::f(1, w, sc - 1 + m, NN)]; }));
             const R hz = R(half_metric([&](int m) { return sM[L::f(2, w, sc - 1 + m, NN)]; }));
-            sw_flux<-1>(ur, hx, hy, hz, metric_rsq(hx, hy, hz), G, Fkeep);
+            sw_flux<-1>(ur, hx, hy, hz, G, Fkeep);
           }
         }
       }
@@ -678,8 +751,15 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
       const int w = DIR == 0 ? eh / NH : eh % TW;
       if (eh < TW * NH && s <= ts && c1_0 + w < n1 && d0 - 1 + s <= nd - 1) {
         const int sc = s + 2;
-        // half-point metric, formed again where it is used rather than held in registers
-        auto hm = [&](int c) { return R(half_metric([&](int m) { return sM[L::f(c, w, sc + m, NN)]; })); };
+        // half-point metric: read from LDS in mixed precision; in FP64 formed again where it
+        // is used rather than held in registers
+        auto hm = [&](int c) {
+          if constexpr (kHalfPre<R>) {
+            return sH[L::f(c, w, s, NH)];
+          } else {
+            return R(half_metric([&](int m) { return sM[L::f(c, w, sc + m, NN)]; }));
+          }
+        };
         R qa[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) qa[v] = R(0.5) * (R(sFn[L::f(v, w, sc, NN)]) + R(sFn[L::f(v, w, sc + 1, NN)]));
@@ -703,11 +783,11 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
         for (int f = 0; f < 5; ++f) vr[f] = weno_left(V[0][f], V[4][f], V[3][f], V[2][f], V[1][f], eps, linear);
         // this thread alone writes slot s: F+ goes to LDS, F- is added to it
         unproject(B, G, vl, uh);
-        sw_flux<+1>(uh, hm(0), hm(1), hm(2), metric_rsq(hm(0), hm(1), hm(2)), G, F);
+        sw_flux<+1>(uh, hm(0), hm(1), hm(2), G, F);
 #pragma unroll
         for (int v = 0; v < 5; ++v) sF[L::f(v, w, s, NH)] = F[v];
         unproject(B, G, vr, uh);
-        sw_flux<-1>(uh, hm(0), hm(1), hm(2), metric_rsq(hm(0), hm(1), hm(2)), G, F);
+        sw_flux<-1>(uh, hm(0), hm(1), hm(2), G, F);
 #pragma unroll
         for (int v = 0; v < 5; ++v) sF[L::f(v, w, s, NH)] += F[v];
       }
@@ -720,15 +800,6 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
     }
     __syncthreads();
     if (need_m) {  // each interface receives exactly one F-
-      if constexpr (SCHEME == kModified && kHalfLds<R>) {
-        // Fkeep holds the state; the thread of node n-1 stored the metric of n-1/2
-        const int hs = sw_ - 1;
-        R F[5];
-        sw_flux<-1>(Fkeep, sH[L::f(0, ww, hs, NH)], sH[L::f(1, ww, hs, NH)], sH[L::f(2, ww, hs, NH)],
-                    sH[L::f(3, ww, hs, NH)], G, F);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) Fkeep[v] = F[v];
-      }
 #pragma unroll
       for (int v = 0; v < 5; ++v) sF[L::f(v, ww, sw_ - 1, NH)] += Fkeep[v];
     }

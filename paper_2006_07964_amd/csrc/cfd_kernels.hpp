@@ -46,6 +46,10 @@ template <typename R>
 hipError_t launch_visc(ViscArgs a, hipStream_t s);
 // dst[e] = float(src[e]) for e < n
 hipError_t launch_round(const double* src, float* dst, int64_t n, hipStream_t s);
+// Half-point metrics of a mixed-precision block: plane 3 d + c of hm holds, at node n along
+// direction d, component c of the direction-d metric at n+1/2 (sixth-order interpolation in
+// FP64, rounded once), for n = -1 .. nd-1 along d at every stored position across.
+hipError_t launch_half_metrics(const Geom& g, const double* met, float* hm, hipStream_t s);
 // batched viscous prepass over the tiles (64 x 16 columns, a chunk of k planes) of every
 // block; one_sided: some block has faces with the one-sided closure
 template <typename R>
@@ -68,6 +72,9 @@ struct SweepBlock {
   int tiles_c1, tiles_d, tile_len;  // filled by the launcher
   int one_sided;  // faces with the one-sided viscous closure (bit 2*axis + side): the
                   // viscous derivative at the three nodes next to them
+  // mixed precision: the 10 metric planes rounded to FP32, then the 9 half-point metric
+  // planes of launch_half_metrics (null in FP64)
+  const float* met_r;
 };
 // part shared by every block of a launch
 struct SweepCommon {
