@@ -432,7 +432,7 @@ template hipError_t launch_visc_batch<float>(const ViscArgs*, const TileList&, b
 // RK3 stage of Eq 20).
 //
 // A workgroup owns a tile of TW grid lines (cross direction c1) by TS output nodes along
-// the sweep direction.  It stages Q, the direction's node metrics and (FP64) viscous
+// the sweep direction.  It stages Q, the direction's node metrics and the viscous
 // fluxes of nodes d0-3 .. d0+TS+2 in LDS; evaluates per node the characteristic WENO pair
 // and the two split fluxes (nodes d0-1 .. d0+TS, one per thread) into interface fluxes;
 // replaces the staged Q by the nodal fluxes; and assembles Eq 19, the viscous derivative
@@ -446,12 +446,6 @@ struct LdsIdx {
     return DIR == 0 ? (v * TW + w) * len + s : (v * len + s) * TW + w;
   }
 };
-
-// Type of the staged Q / nodal-flux tile: FP64 in FP64 sweeps and in the last sweep
-// direction (the one that carries the RK combination, which then takes Q from the tile in
-// FP64 instead of reading it again), the compute type otherwise.
-template <typename R, int DIR>
-using StageT = typename std::conditional<sizeof(R) == 8 || DIR == kSweepOrder[2], double, R>::type;
 
 template <int TW, int TS>
 struct SweepLds {
@@ -475,12 +469,16 @@ template <typename R>
 using StageM = typename std::conditional<kHalfPre<R>, R, double>::type;
 
 // LDS of one workgroup for the largest tile configuration in use.
-template <typename R, typename S, int TW, int TS>
+// The staged Q / nodal-flux tile is in the compute type.  An FP64 tile gives the RK
+// combination Q_cur from LDS; a mixed-precision RK sweep reads Q_cur again (from L2,
+// moments after the staging read it) rather than convert an FP64 tile at every use (its
+// FP32 tile runs that sweep 3% faster on the 512 x 512 x 384 channel).
+template <typename R, int TW, int TS>
 struct SweepShared {
   R F[5 * TW * SweepLds<TW, TS>::NH];   // interface fluxes f(n+1/2)
-  S Fn[5 * TW * SweepLds<TW, TS>::NN];  // staged Q, then nodal fluxes
+  R Fn[5 * TW * SweepLds<TW, TS>::NN];  // staged Q, then nodal fluxes
   StageM<R> M[3 * TW * SweepLds<TW, TS>::NN];  // node metrics of the sweep direction
-  R V[(sizeof(R) == 8 || sizeof(S) == sizeof(R)) ? 4 * TW * SweepLds<TW, TS>::NN : 1];  // viscous fluxes
+  R V[4 * TW * SweepLds<TW, TS>::NN];  // viscous fluxes of the direction
   R H[kHalfPre<R> ? 3 * TW * SweepLds<TW, TS>::NH : 1];  // half-point metrics (mixed precision)
 };
 
@@ -490,9 +488,9 @@ struct SweepShared {
 // instantiation keeps the register budget of the others)
 template <int DIR, typename R, int TW, int TS, int NT, int SCHEME = kModified, bool OS = false>
 __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBlock& b, int t,
-                                           SweepShared<R, StageT<R, DIR>, TW, TS>& sh) {
+                                           SweepShared<R, TW, TS>& sh) {
   R* const sF = sh.F;
-  StageT<R, DIR>* const sFn = sh.Fn;
+  R* const sFn = sh.Fn;
   StageM<R>* const sM = sh.M;
   R* const sV = sh.V;
   R* const sH = sh.H;
@@ -500,12 +498,6 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
   constexpr int NN = SweepLds<TW, TS>::NN;
   constexpr int NW = SweepLds<TW, TS>::NW;
   using L = LdsIdx<DIR, TW>;
-  using S = StageT<R, DIR>;
-  // The direction's viscous fluxes are staged with the tile (their stencil then reads LDS),
-  // except in the mixed-precision RK sweep, whose FP64 tile leaves no LDS for them
-  // (measured on the 512 x 512 x 384 channel: staging them costs that sweep 3% and saves
-  // the other mixed sweeps 2 to 4%)
-  constexpr bool kStageVis = sizeof(R) == 8 || sizeof(S) == sizeof(R);
 
   const Geom& g = b.g;
   const int nd = DIR == 0 ? g.ni : DIR == 1 ? g.nj : g.nk;
@@ -556,7 +548,7 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
   double Jo = 0.0, qno[5], qco[5];
   auto fetch = [&]() {
     if (!out_here) return;
-    if (c.do_vis && !(kStageVis && c.do_inv)) {  // else staged with the tile
+    if (c.do_vis && !c.do_inv) {  // else staged with the tile
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const GP<const R> vp = plane_ptr(vis, v * plane);
@@ -571,7 +563,7 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
     if (c.out_kind != kOutPartial) Jo = ldg(plane_ptr(met, 9 * plane), po);
     if (c.out_kind == kOutRK) {
       // Q at the output node (an inviscid sweep with an FP64 tile took it from there already)
-      if (!(sizeof(S) == 8 && c.do_inv)) {
+      if (!(sizeof(R) == 8 && c.do_inv)) {
 #pragma unroll
         for (int v = 0; v < 5; ++v) qco[v] = ldg(plane_ptr(Q, v * plane), po);
       }
@@ -617,7 +609,7 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
             lr[it][0] = ldg(mx, p);
             lr[it][1] = ldg(my, p);
             lr[it][2] = ldg(mz, p);
-            if (kStageVis && c.do_vis) {
+            if (c.do_vis) {
 #pragma unroll
               for (int v = 0; v < 4; ++v) lr[it][3 + v] = ldg(plane_ptr(vis, v * plane), p);
             }
@@ -632,7 +624,7 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
             ld[it][5] = ldg(mx, p);
             ld[it][6] = ldg(my, p);
             ld[it][7] = ldg(mz, p);
-            if (kStageVis && c.do_vis) {
+            if (c.do_vis) {
 #pragma unroll
               for (int v = 0; v < 4; ++v) ld[it][8 + v] = double(ldg(plane_ptr(vis, v * plane), p));
             }
@@ -644,11 +636,11 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
       for (int it = 0; it < ITEMS; ++it) {
         if (!ok[it]) continue;
 #pragma unroll
-        for (int v = 0; v < 5; ++v) sFn[li[it] + v * TW * NN] = S(R(ld[it][v]));
+        for (int v = 0; v < 5; ++v) sFn[li[it] + v * TW * NN] = R(ld[it][v]);
         if constexpr (kHalfPre<R>) {
 #pragma unroll
           for (int v = 0; v < 3; ++v) sM[li[it] + v * TW * NN] = lr[it][v];
-          if (kStageVis && c.do_vis) {
+          if (c.do_vis) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) sV[li[it] + v * TW * NN] = lr[it][3 + v];
           }
@@ -659,7 +651,7 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
         } else {
 #pragma unroll
           for (int v = 0; v < 3; ++v) sM[li[it] + v * TW * NN] = ld[it][5 + v];
-          if (kStageVis && c.do_vis) {
+          if (c.do_vis) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) sV[li[it] + v * TW * NN] = R(ld[it][8 + v]);
           }
@@ -794,7 +786,7 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
     }
     // a staged Q in FP64 is exact: the output node's copy for the RK combination is read
     // here, before the barrier after which the nodal fluxes overwrite it
-    if (sizeof(S) == 8 && c.out_kind == kOutRK && out_here) {
+    if (sizeof(R) == 8 && c.out_kind == kOutRK && out_here) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) qco[v] = double(sFn[L::f(v, wo, so + 3, NN)]);
     }
@@ -816,7 +808,7 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
       for (int v = 0; v < 5; ++v) q[v] = R(sFn[L::f(v, w, s, NN)]);
       phys_flux(q, R(sM[L::f(0, w, s, NN)]), R(sM[L::f(1, w, s, NN)]), R(sM[L::f(2, w, s, NN)]), G, F);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) sFn[L::f(v, w, s, NN)] = S(F[v]);
+      for (int v = 0; v < 5; ++v) sFn[L::f(v, w, s, NN)] = F[v];
     }
     __syncthreads();
   }
@@ -852,7 +844,7 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
         for (int m = 0; m < 7; ++m) acc += R(os6_weight(row, sign, m)) * ldg(vp, po + (uint32_t)(first + m - d0 - s) * sd);
         r[v] += acc;
       }
-    } else if (kStageVis && c.do_inv) {
+    } else if (c.do_inv) {
 #pragma unroll
       for (int v = 1; v < 5; ++v) r[v] += d6<R>([&](int m) { return sV[L::f(v - 1, w, s + 3 + m, NN)]; });
     } else {
@@ -887,14 +879,14 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
 // Single block: one workgroup per tile, ids remapped XCD-contiguously.
 template <int DIR, typename R, int TW, int TS, int NT, int SCHEME, bool OS>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep(SweepArgs a) {
-  __shared__ SweepShared<R, StageT<R, DIR>, TW, TS> sh;
+  __shared__ SweepShared<R, TW, TS> sh;
   sweep_tile<DIR, R, TW, TS, NT, SCHEME, OS>(a.c, a.b, xcd_remap(blockIdx.x, gridDim.x), sh);
 }
 // the original scheme in FP64 holds six stencil points and the half-point basis at once:
 // three waves per SIMD give it the registers that four would make it spill
 template <int DIR, typename R, int TW, int TS, int NT, bool OS>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_sweep_w3(SweepArgs a) {
-  __shared__ SweepShared<R, StageT<R, DIR>, TW, TS> sh;
+  __shared__ SweepShared<R, TW, TS> sh;
   sweep_tile<DIR, R, TW, TS, NT, kOriginal, OS>(a.c, a.b, xcd_remap(blockIdx.x, gridDim.x), sh);
 }
 
@@ -906,7 +898,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_
 template <int DIR, typename R, int TW, int TS, int NT, bool PERSIST, bool OS>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(PERSIST && sizeof(R) == 8 ? 3 : 4))) void k_sweep_batch(
     const SweepBlock* __restrict__ blocks, SweepCommon c, TileList tl) {
-  __shared__ SweepShared<R, StageT<R, DIR>, TW, TS> sh;
+  __shared__ SweepShared<R, TW, TS> sh;
   const int total = tl.prefix[tl.nblk];
   if (!PERSIST) {
     const int t = xcd_remap(blockIdx.x, gridDim.x);
@@ -931,7 +923,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(PERSIST && s
 // (see k_sweep_w3), FP32 the usual four.
 template <int DIR, typename R, int TW, int TS, int NT, bool OS>
 __device__ __forceinline__ void batch_orig_tile(const SweepBlock* __restrict__ blocks, const SweepCommon& c,
-                                                const TileList& tl, SweepShared<R, StageT<R, DIR>, TW, TS>& sh) {
+                                                const TileList& tl, SweepShared<R, TW, TS>& sh) {
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   int blk = 0;
   while (t >= tl.prefix[blk + 1]) ++blk;
@@ -940,7 +932,7 @@ __device__ __forceinline__ void batch_orig_tile(const SweepBlock* __restrict__ b
 template <int DIR, typename R, int TW, int TS, int NT, bool OS>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 3 : 4))) void k_sweep_batch_orig(
     const SweepBlock* __restrict__ blocks, SweepCommon c, TileList tl) {
-  __shared__ SweepShared<R, StageT<R, DIR>, TW, TS> sh;
+  __shared__ SweepShared<R, TW, TS> sh;
   batch_orig_tile<DIR, R, TW, TS, NT, OS>(blocks, c, tl, sh);
 }
 
