@@ -1017,7 +1017,7 @@ void fill_tiles(cfd_batch* bt) {
   bt->visc_tl.prefix[0] = 0;
   for (int b = 0; b < nb; ++b) {
     int kc, t;
-    visc_tiling(bt->blocks[b]->g, 0, &kc, &t);
+    visc_tiling(bt->blocks[b]->g, kViscMinTilesBatch, &kc, &t);
     bt->visc_tl.prefix[b + 1] = bt->visc_tl.prefix[b] + t;
   }
   for (int d = 0; d < 3; ++d) {
@@ -1135,7 +1135,7 @@ void build_args(cfd_batch* bt, double* const* Qn, double* const* QA, double* con
       v.ph = ph;
       v.one_sided = one_sided_mask(B->d);
       int tiles;
-      visc_tiling(B->g, 0, &v.kc, &tiles);  // the batch list is long enough
+      visc_tiling(B->g, kViscMinTilesBatch, &v.kc, &tiles);
       for (int d = 0; d < 3; ++d) {
         SweepBlock& a = sa[(st * 3 + d) * nb + b];
         std::memset(&a, 0, sizeof a);
