@@ -468,11 +468,11 @@ constexpr bool kHalfPre = sizeof(R) == 4;
 template <typename R>
 using StageM = typename std::conditional<kHalfPre<R>, R, double>::type;
 
-// LDS of one workgroup for the largest tile configuration in use.
-// The staged Q / nodal-flux tile is in the compute type.  An FP64 tile gives the RK
-// combination Q_cur from LDS; a mixed-precision RK sweep reads Q_cur again (from L2,
-// moments after the staging read it) rather than convert an FP64 tile at every use (its
-// FP32 tile runs that sweep 3% faster on the 512 x 512 x 384 channel).
+// LDS of one workgroup for the largest tile configuration in use.  The staged Q /
+// nodal-flux tile is in the compute type: an FP64 tile gives the RK combination Q_cur from
+// LDS; a mixed-precision RK sweep reads Q_cur again (from L2, moments after the staging
+// read it) rather than convert an FP64 tile at every use (its FP32 tile runs that sweep 3%
+// faster on the 512 x 512 x 384 channel).
 template <typename R, int TW, int TS>
 struct SweepShared {
   R F[5 * TW * SweepLds<TW, TS>::NH];   // interface fluxes f(n+1/2)
@@ -562,7 +562,7 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
     }
     if (c.out_kind != kOutPartial) Jo = ldg(plane_ptr(met, 9 * plane), po);
     if (c.out_kind == kOutRK) {
-      // Q at the output node (an inviscid sweep with an FP64 tile took it from there already)
+      // Q at the output node (an inviscid FP64 sweep took it from its tile already)
       if (!(sizeof(R) == 8 && c.do_inv)) {
 #pragma unroll
         for (int v = 0; v < 5; ++v) qco[v] = ldg(plane_ptr(Q, v * plane), po);
