@@ -57,6 +57,16 @@ template <typename T>
 __device__ __forceinline__ void stg(GP<T> base, uint32_t e, T v) {
   *(GP<T>)((GP<char>)base + e * (uint32_t)sizeof(T)) = v;
 }
+// streaming forms (no reuse expected): the line is a first candidate for eviction, which
+// keeps the cache for data that neighbouring workgroups read again
+template <typename T>
+__device__ __forceinline__ T ldg_nt(GP<const T> base, uint32_t e) {
+  return __builtin_nontemporal_load((GP<const T>)((GP<const char>)base + e * (uint32_t)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ void stg_nt(GP<T> base, uint32_t e, T v) {
+  __builtin_nontemporal_store(v, (GP<T>)((GP<char>)base + e * (uint32_t)sizeof(T)));
+}
 
 // Physical constants of one block (FP64 on the host side of the kernel arguments).
 struct Phys {

@@ -279,12 +279,15 @@ __device__ __forceinline__ void visc_tile(const ViscArgs& a, int t, ViscShared<R
           for (int n = 0; n < 4; ++n) gr[n][d] = acc[n];
         }
       }
+      // the metrics and the flux planes stream through (read or written once): streaming
+      // accesses leave L2 to the Q rows and columns that the neighbouring tiles read as
+      // their halo (measured on the 512 x 512 x 384 channel: 4% faster in FP64)
       R mh[3][3];
 #pragma unroll
       for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) mh[d][c] = ldg(plane_ptr(met, (3 * d + c) * plane), p);
-      const R J = ldg(plane_ptr(met, 9 * plane), p);
+        for (int c = 0; c < 3; ++c) mh[d][c] = ldg_nt(plane_ptr(met, (3 * d + c) * plane), p);
+      const R J = ldg_nt(plane_ptr(met, 9 * plane), p);
       R dx[4][3];  // d(u, v, w, T)/d(x, y, z), Eq 21
 #pragma unroll
       for (int n = 0; n < 4; ++n)
@@ -311,7 +314,7 @@ __device__ __forceinline__ void visc_tile(const ViscArgs& a, int t, ViscShared<R
         for (int n = 0; n < 3; ++n) f[n] = mh[d][0] * tau[n][0] + mh[d][1] * tau[n][1] + mh[d][2] * tau[n][2];
         f[3] = mh[d][0] * bet[0] + mh[d][1] * bet[1] + mh[d][2] * bet[2];
 #pragma unroll
-        for (int n = 0; n < 4; ++n) stg(plane_ptr(out, (4 * d + n) * plane), p, f[n]);
+        for (int n = 0; n < 4; ++n) stg_nt(plane_ptr(out, (4 * d + n) * plane), p, f[n]);
         // a block periodic with itself along d: the node's image in the halo across the
         // d-faces (the direction-d flux is the one the d sweep differentiates)
         if (a.periodic & (1 << d)) {
@@ -321,7 +324,7 @@ __device__ __forceinline__ void visc_tile(const ViscArgs& a, int t, ViscShared<R
           if (idx < kHalo || idx >= nd - kHalo) {
             const uint32_t pi = idx < kHalo ? p + (uint32_t)nd * sd : p - (uint32_t)nd * sd;
 #pragma unroll
-            for (int n = 0; n < 4; ++n) stg(plane_ptr(out, (4 * d + n) * plane), pi, f[n]);
+            for (int n = 0; n < 4; ++n) stg_nt(plane_ptr(out, (4 * d + n) * plane), pi, f[n]);
           }
         }
       }
