@@ -267,47 +267,87 @@ __device__ __forceinline__ void unproject(const Basis<R>& B, const Gas<R>& G, co
 // 1/16 and beta_1 on {i-2,i-1,i}, 5/8 on {i-1,i,i+1}, 5/16 on {i,i+1,i+2} for the
 // left-biased value at i+1/2; the right-biased value at i-1/2 uses the mirror images with
 // the same betas (modified AFWENO, Sec. 4.5.1).
-template <typename R>
+// CORR: the same weights and values in the correction form (each value c plus one eighth of
+// a combination of the differences that also give the smoothness indicators), which takes
+// fewer FP64 instructions and a few more VGPRs
+template <typename R, bool CORR = false>
 __device__ __forceinline__ void weno_pair(R a, R b, R c, R d, R e, R eps, bool linear, R& vl, R& vr) {
-  // quadratic interpolants of Eq 14 at i+1/2 (p) and their mirror images at i-1/2 (m),
-  // pre-multiplied by their ideal weights (1/16, 5/8, 5/16) and (5/16, 5/8, 1/16)
-  const R p0 = R(3.0 / 128.0) * a - R(5.0 / 64.0) * b + R(15.0 / 128.0) * c;
-  const R p1 = R(-5.0 / 64.0) * b + R(15.0 / 32.0) * c + R(15.0 / 64.0) * d;
-  const R p2 = R(15.0 / 128.0) * c + R(15.0 / 64.0) * d - R(5.0 / 128.0) * e;
-  const R m0 = R(-5.0 / 128.0) * a + R(15.0 / 64.0) * b + R(15.0 / 128.0) * c;
-  const R m1 = R(15.0 / 64.0) * b + R(15.0 / 32.0) * c - R(5.0 / 64.0) * d;
-  const R m2 = R(15.0 / 128.0) * c - R(5.0 / 64.0) * d + R(3.0 / 128.0) * e;
-  if (linear) {
-    vl = p0 + p1 + p2;
-    vr = m0 + m1 + m2;
-    return;
-  }
-  // smoothness indicators of Eq 17 written as sums of squares of the second and first
-  // differences (13/12 (.)^2 + 1/4 (.)^2, algebraically identical); the differences cancel
-  // before squaring, so beta carries a relative rounding error instead of one of |v|^2.
-  const R d0 = a - R(2) * b + c, e0 = a - R(4) * b + R(3) * c;
-  const R d1 = b - R(2) * c + d, e1 = b - d;
-  const R d2 = c - R(2) * d + e, e2 = R(3) * c - R(4) * d + e;
-  const R k13 = R(13.0 / 12.0), k14 = R(0.25);
-  const R t0 = eps + (k13 * d0 * d0 + k14 * e0 * e0);
-  const R t1 = eps + (k13 * d1 * d1 + k14 * e1 * e1);
-  const R t2 = eps + (k13 * d2 * d2 + k14 * e2 * e2);
-  // Eq 15 over a common denominator: w_j ~ gamma_j / s_j with s_j = t_j^2 equals
-  // gamma_j * prod_{k != j} s_k up to a common factor, which the normalisation removes.
-  const R s0 = t0 * t0, s1 = t1 * t1, s2 = t2 * t2;
-  const R q0 = s1 * s2, q1 = s0 * s2, q2 = s0 * s1;
-  const R nl = q0 * p0 + q1 * p1 + q2 * p2;
-  const R nr = q0 * m0 + q1 * m1 + q2 * m2;
-  const R dl = R(0.0625) * q0 + R(0.625) * q1 + R(0.3125) * q2;
-  const R dr = R(0.3125) * q0 + R(0.625) * q1 + R(0.0625) * q2;
-  if constexpr (sizeof(R) == 8) {
-    // one reciprocal for both sides (the product stays far inside the double range)
-    const R inv = rcp(dl * dr);
-    vl = nl * dr * inv;
-    vr = nr * dl * inv;
+  if constexpr (CORR) {
+    // second differences d_j and combinations e_j of first differences of the sub-stencils;
+    // the smoothness indicators of Eq 17 are 13/12 d_j^2 + 1/4 e_j^2
+    const R d0 = a - R(2) * b + c, e0 = a - R(4) * b + R(3) * c;
+    const R d1 = b - R(2) * c + d, e1 = b - d;
+    const R d2 = c - R(2) * d + e, e2 = R(3) * c - R(4) * d + e;
+    // the quadratic interpolants of Eq 14 as c + (.)/8: at i+1/2 d0 + 2 e0, d1 - 2 e1,
+    // d2 - 2 e2; at i-1/2 the mirror images d0 - 2 e0, d1 + 2 e1, d2 + 2 e2
+    const R A0 = d0 + R(2) * e0, A1 = d1 - R(2) * e1, A2 = d2 - R(2) * e2;
+    const R B0 = d0 - R(2) * e0, B1 = d1 + R(2) * e1, B2 = d2 + R(2) * e2;
+    if (linear) {  // ideal weights (1, 10, 5)/16 at i+1/2 and (5, 10, 1)/16 at i-1/2
+      vl = c + (A0 + R(10) * A1 + R(5) * A2) * R(1.0 / 128.0);
+      vr = c + (R(5) * B0 + R(10) * B1 + B2) * R(1.0 / 128.0);
+      return;
+    }
+    // t_j = 4 (eps + beta_j): the common factor 4 cancels in Eq 15
+    const R eps4 = R(4) * eps;
+    const R t0 = eps4 + (R(13.0 / 3.0) * d0 * d0 + e0 * e0);
+    const R t1 = eps4 + (R(13.0 / 3.0) * d1 * d1 + e1 * e1);
+    const R t2 = eps4 + (R(13.0 / 3.0) * d2 * d2 + e2 * e2);
+    // Eq 15 over a common denominator, as below
+    const R s0 = t0 * t0, s1 = t1 * t1, s2 = t2 * t2;
+    const R q0 = s1 * s2, q1 = s0 * s2, q2 = s0 * s1;
+    const R nl = q0 * A0 + R(10) * (q1 * A1) + R(5) * (q2 * A2);
+    const R nr = R(5) * (q0 * B0) + R(10) * (q1 * B1) + q2 * B2;
+    const R dl = q0 + R(10) * q1 + R(5) * q2;
+    const R dr = R(5) * q0 + R(10) * q1 + q2;
+    if constexpr (sizeof(R) == 8) {
+      const R inv = R(0.125) * rcp(dl * dr);
+      vl = c + nl * dr * inv;
+      vr = c + nr * dl * inv;
+    } else {
+      vl = c + R(0.125) * nl * rcp(dl);
+      vr = c + R(0.125) * nr * rcp(dr);
+    }
   } else {
-    vl = nl * rcp(dl);
-    vr = nr * rcp(dr);
+    // quadratic interpolants of Eq 14 at i+1/2 (p) and their mirror images at i-1/2 (m),
+    // pre-multiplied by their ideal weights (1/16, 5/8, 5/16) and (5/16, 5/8, 1/16)
+    const R p0 = R(3.0 / 128.0) * a - R(5.0 / 64.0) * b + R(15.0 / 128.0) * c;
+    const R p1 = R(-5.0 / 64.0) * b + R(15.0 / 32.0) * c + R(15.0 / 64.0) * d;
+    const R p2 = R(15.0 / 128.0) * c + R(15.0 / 64.0) * d - R(5.0 / 128.0) * e;
+    const R m0 = R(-5.0 / 128.0) * a + R(15.0 / 64.0) * b + R(15.0 / 128.0) * c;
+    const R m1 = R(15.0 / 64.0) * b + R(15.0 / 32.0) * c - R(5.0 / 64.0) * d;
+    const R m2 = R(15.0 / 128.0) * c - R(5.0 / 64.0) * d + R(3.0 / 128.0) * e;
+    if (linear) {
+      vl = p0 + p1 + p2;
+      vr = m0 + m1 + m2;
+      return;
+    }
+    // smoothness indicators of Eq 17 written as sums of squares of the second and first
+    // differences (13/12 (.)^2 + 1/4 (.)^2, algebraically identical); the differences cancel
+    // before squaring, so beta carries a relative rounding error instead of one of |v|^2.
+    const R d0 = a - R(2) * b + c, e0 = a - R(4) * b + R(3) * c;
+    const R d1 = b - R(2) * c + d, e1 = b - d;
+    const R d2 = c - R(2) * d + e, e2 = R(3) * c - R(4) * d + e;
+    const R k13 = R(13.0 / 12.0), k14 = R(0.25);
+    const R t0 = eps + (k13 * d0 * d0 + k14 * e0 * e0);
+    const R t1 = eps + (k13 * d1 * d1 + k14 * e1 * e1);
+    const R t2 = eps + (k13 * d2 * d2 + k14 * e2 * e2);
+    // Eq 15 over a common denominator: w_j ~ gamma_j / s_j with s_j = t_j^2 equals
+    // gamma_j * prod_{k != j} s_k up to a common factor, which the normalisation removes.
+    const R s0 = t0 * t0, s1 = t1 * t1, s2 = t2 * t2;
+    const R q0 = s1 * s2, q1 = s0 * s2, q2 = s0 * s1;
+    const R nl = q0 * p0 + q1 * p1 + q2 * p2;
+    const R nr = q0 * m0 + q1 * m1 + q2 * m2;
+    const R dl = R(0.0625) * q0 + R(0.625) * q1 + R(0.3125) * q2;
+    const R dr = R(0.3125) * q0 + R(0.625) * q1 + R(0.0625) * q2;
+    if constexpr (sizeof(R) == 8) {
+      // one reciprocal for both sides (the product stays far inside the double range)
+      const R inv = rcp(dl * dr);
+      vl = nl * dr * inv;
+      vr = nr * dl * inv;
+    } else {
+      vl = nl * rcp(dl);
+      vr = nr * rcp(dr);
+    }
   }
 }
 

@@ -693,8 +693,12 @@ __device__ __forceinline__ void sweep_tile(const SweepCommon& c, const SweepBloc
           project(B, G, qq, V[tt]);
         }
         R vl[5], vr[5];
+        // FP64: the correction form (2.4% and 1.5% faster zeta and eta sweeps), except in the
+        // RK sweep, whose registers it would overflow (2 VGPRs spilled, 4% slower)
+        constexpr bool kCorr = sizeof(R) == 8 && DIR != kSweepOrder[2];
 #pragma unroll
-        for (int f = 0; f < 5; ++f) weno_pair(V[0][f], V[1][f], V[2][f], V[3][f], V[4][f], eps, linear, vl[f], vr[f]);
+        for (int f = 0; f < 5; ++f)
+          weno_pair<R, kCorr>(V[0][f], V[1][f], V[2][f], V[3][f], V[4][f], eps, linear, vl[f], vr[f]);
         if constexpr (kHalfPre<R>) {
           // half-point metrics from LDS: slot s holds n+1/2, slot s-1 holds n-1/2
           if (need_p) {
